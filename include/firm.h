@@ -1,0 +1,178 @@
+/* firm.h -- C ABI of the MI355X (gfx950) FIRM library.
+ *
+ * FIRM (Wang, Shkolnisky & Singer, "A Fourier-based Approach for Iterative 3D
+ * Reconstruction from Cryo-EM Images") reconstructs an N^3 volume V from M
+ * Fourier slices b by solving the normal equations of the least-squares cost
+ * (section 3.3, eq. cost1), here with a Tikhonov term:
+ *
+ *     (A*A + lambda I) V = A* b.
+ *
+ * A is the forward projector of eq. (forward-projector), A* the back-projector
+ * of eq. (backprojection), and A*A is the convolution with the kernel Ker of
+ * eq. (kernel) (eq. property), applied through a 2N-per-axis circulant
+ * embedding and FFTs (eq. embedding_circulant, circ1).
+ *
+ * Conventions
+ *   Volume:  float, C order V[i1][i2][i3], voxel n = i - N/2 (section 3.1).
+ *   Slices:  complex64 (interleaved re, im), image-major, M x P(N): image m holds
+ *            the P(N) disk points k with ||k|| <= N/2 (eq. truncation) in the
+ *            canonical order k1 ascending, then k2 ascending.  Index P-1-j holds -k_j.
+ *   Rotations: row-major 3x3 R_m; sample point xi = R_m^{-1}(2 pi k1/N, 2 pi k2/N, 0).
+ *   CTF:     a table h_g(q), q = k1^2 + k2^2 in [0, N^2/4], per defocus group g; image m
+ *            uses group ctf_group[m].  NULL table means h = 1.
+ *   Shifts:  s_m in pixels; slices are re-centred by exp(+i <omega_k, s_m>) before
+ *            back-projection (section 3.1, images re-shifted to their centres).
+ *   Kernel:  Ker(n) for -N < n < N per axis, stored as a (2N)^3 float array in centred
+ *            offset order ker[j1][j2][j3] = Ker(j - N); planes with some j_d = 0
+ *            (offset -N, outside the kernel's domain) hold 0.
+ *   Preconditioner diagonal d: float N^3, indexed by centred frequency q + N/2.
+ *
+ * Memory: every pointer argument named *_dev is a device pointer owned by the
+ * caller; the library never frees it.  Host arrays are copied during the call.
+ * The plan owns its workspaces (kernel spectrum, padded FFT buffers, gridding
+ * grids) and frees them in firm_plan_destroy.
+ *
+ * Streams: every call is ordered on the plan's stream (firm_options.stream, or
+ * the null stream).  Calls return once the work is enqueued unless stated;
+ * firm_cg_solve synchronises for its stopping checks.
+ *
+ * Errors: functions return a firm_status; nothing aborts or throws across the
+ * ABI.  firm_last_error(plan) (or firm_last_error(NULL) for errors raised
+ * before a plan exists) returns the message of the latest failure.
+ * A plan is not thread-safe.
+ */
+#ifndef FIRM_H
+#define FIRM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct firm_plan_s* firm_plan;
+
+typedef enum {
+    FIRM_OK = 0,
+    FIRM_ERR_ARG = 1,           /* invalid argument (message says which) */
+    FIRM_ERR_ALLOC = 2,         /* device or host allocation failed */
+    FIRM_ERR_HIP = 3,           /* a HIP runtime call failed */
+    FIRM_ERR_STATE = 4,         /* call out of order, e.g. apply before a kernel exists */
+    FIRM_ERR_BREAKDOWN = 5,     /* CG/PCG breakdown (non-positive or non-finite curvature) */
+    FIRM_ERR_NOT_CONVERGED = 6  /* CG stopped at max_iter above tol; x is still valid */
+} firm_status;
+
+typedef struct {
+    int kb_width;         /* Kaiser-Bessel window width in fine-grid cells, 4..8; 0 = 7 */
+    int refine_every;     /* precision 0: residual replacement period in iterations; 0 = 50, <0 = never */
+    int check_every;      /* CG iterations enqueued between host checks of the stop flag; 0 = 10 */
+    int precision;        /* CG arithmetic: 0 = FP32 vectors and product, FP64 sums and scalars;
+                             1 = FP64 iterative refinement (FP64 residual, product and solution,
+                             FP32 (P)CG corrections); 2 = FP64 CG (no preconditioner) */
+    int lambda_relative;  /* 0: lambda as given; 1: the lambda of every call is multiplied by
+                             Ker(0) = sum_m sum_k h_m^2, the diagonal of A*A */
+    int reserved;         /* must be 0 */
+    double inner_tol;     /* precision 1: relative tolerance of each FP32 correction; 0 = 1e-3 */
+    void* stream;         /* hipStream_t for all work; NULL = null stream */
+} firm_options;
+
+typedef struct {
+    int iters;            /* CG iterations performed (all corrections, precision 1) */
+    int refinements;      /* precision 0: residual replacements; precision 1: FP64 corrections */
+    int fell_back;        /* 1 if a preconditioned solve restarted as plain CG */
+    int status;           /* firm_status of the solve */
+    double rel_res;       /* residual / ||A*b|| that stopped the solver */
+    double true_rel_res;  /* ||A*b - (A*A + lambda) x|| / ||A*b|| at exit with the FP64 product */
+    double t_ms;          /* wall time of the solve in ms */
+} firm_cg_report;
+
+/* P(N): number of disk points per slice (eq. truncation). */
+int64_t firm_slice_points(int N);
+
+/* Create a plan for N^3 volumes (N a power of two, 8..256) and M images.
+ * rotations: host M x 9 doubles (R_m row-major, orthonormal with det +1 to 1e-6).
+ * shifts: host M x 2 doubles or NULL.  ctf_group: host M int32 in [0, G) or NULL
+ * (group 0).  ctf_table: host G x (N*N/4 + 1) floats or NULL (h = 1).
+ * opt may be NULL for defaults.  Errors: FIRM_ERR_ARG for bad sizes, rotations,
+ * groups or options; FIRM_ERR_ALLOC / FIRM_ERR_HIP on device failure (*out = NULL). */
+firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rotations,
+                             const double* shifts, const int32_t* ctf_group, int G,
+                             const float* ctf_table, const firm_options* opt);
+
+void firm_plan_destroy(firm_plan plan);
+
+/* Set the stream used by later calls (hipStream_t, NULL = null stream). */
+firm_status firm_plan_set_stream(firm_plan plan, void* stream);
+
+/* Step 3 of the algorithm (section 3.4): compute Ker (eq. kernel) by gridding the
+ * CTF^2-weighted sample points with a Kaiser-Bessel window onto a (4N)^3 grid,
+ * FFT, deconvolution and crop, then the spectrum of its 2N circulant embedding
+ * (eq. embedding_circulant).  Uses Ker(-n) = Ker(n) to spread half the disk. */
+firm_status firm_kernel_precompute(firm_plan plan);
+
+/* Copy Ker into ker_dev ((2N)^3 floats, centred offset order, see above). */
+firm_status firm_kernel_get(firm_plan plan, float* ker_dev);
+
+/* Replace the plan's kernel by ker_dev ((2N)^3 floats, centred offset order; the
+ * j_d = 0 planes are ignored) and recompute its circulant spectrum.  Lets a caller
+ * reuse a stored kernel or apply any Toeplitz kernel. */
+firm_status firm_kernel_set(firm_plan plan, const float* ker_dev);
+
+/* Step 2 (section 3.4): atb_dev (N^3 floats) = Re A*(re-centred b) (eq. backprojection)
+ * for slices b_dev (device, M x P complex64).  Exact real part for any b: the
+ * spread uses the pair (k, -k) as b(k) + conj(b(-k)). */
+firm_status firm_backproject(firm_plan plan, const void* b_dev, float* atb_dev);
+
+/* y_dev = (A*A + lambda I) x_dev through the circulant embedding (eq. property,
+ * embedding_circulant, circ1): pad to (2N)^3, FFT, multiply by the kernel
+ * spectrum, inverse FFT, crop.  x_dev, y_dev: N^3 floats, must not alias.
+ * FIRM_ERR_STATE if no kernel exists; FIRM_ERR_ARG if lambda < 0. */
+firm_status firm_apply_AtA(firm_plan plan, const float* x_dev, float* y_dev, double lambda);
+
+/* FP64 form of firm_apply_AtA: x_dev, y_dev are N^3 doubles; the spectrum is computed in
+ * FP64 from the FP32 kernel values (so it is exactly the Toeplitz product with them). */
+firm_status firm_apply_AtA_f64(firm_plan plan, const double* x_dev, double* y_dev, double lambda);
+
+/* Step 4 (section 3.3-3.4): CG on (A*A + lambda I) x = atb from the initial guess in
+ * x_dev (pass zeros for the paper's x0 = 0), in the arithmetic of firm_options.precision.
+ * Precision 0 stops when the residual measured with the FP32 product is <= tol ||atb||
+ * (a recursive residual below tol is confirmed by a recomputed one); precision 1 and 2
+ * stop on the FP64 residual.  max_iter bounds the CG iterations.  precond_d_dev: NULL for plain CG, else a Fourier diagonal d
+ * (N^3, centred frequency order, d > 0, d(q) = d(-q)) applied as
+ * z = F^{-1}(d . F r) on the periodic N^3 grid; a breakdown of the preconditioned
+ * recursion restarts plain CG from the current x.  rep may be NULL.
+ * Returns FIRM_ERR_NOT_CONVERGED (x valid) if max_iter was reached above tol. */
+firm_status firm_cg_solve(firm_plan plan, const float* atb_dev, float* x_dev, double lambda,
+                          double tol, int max_iter, const float* precond_d_dev,
+                          firm_cg_report* rep);
+
+/* z_dev = F^{-1}(d . F r) on the periodic N^3 grid (circulant diagonalisation,
+ * eq. circ1); d_dev, r_dev, z_dev: N^3 floats (d in centred frequency order). */
+firm_status firm_precond_apply(firm_plan plan, const float* d_dev, const float* r_dev, float* z_dev);
+
+/* Copy the kernel spectrum K^(q) = DFT_{2N}(c)(q) / (2N)^3 of the circulant first
+ * column c for q3 in [0, N] into khat_dev ((2N) x (2N) x (N+1) floats, q in FFT
+ * order).  It is real because Ker is real and even. */
+firm_status firm_kernel_spectrum(firm_plan plan, float* khat_dev);
+
+/* Synthetic slices for benchmarks and tests: b_dev (M x P complex64) = CTF-filtered,
+ * translated Fourier slices of a sum of B Gaussian blobs given in closed form by the
+ * projection-slice theorem (eq. continuous_fps), plus complex white noise with the
+ * symmetry of a real image's DFT at the given SNR (mean clean power / noise power;
+ * snr <= 0 or infinite: no noise).  centers (B x 3), sigmas, amps: host doubles in
+ * voxel units; sigma 0 is a point source.  Noise uses Philox4x32-10 keyed by seed. */
+firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, const double* sigmas,
+                              const double* amps, double snr, uint64_t seed, void* b_dev);
+
+/* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC 2011), the source of
+ * the synthetic noise: out = bijection(ctr) keyed by key.  Host function, no device work. */
+void firm_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Message of the latest failure on plan (NULL: of the latest failure without a plan). */
+const char* firm_last_error(firm_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIRM_H */

@@ -1,0 +1,529 @@
+// C ABI of libfirm: plan creation and validation, workspaces, and the calls that
+// chain the HIP kernels of the other translation units.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "firm_internal.h"
+
+#define KB_DEG 10
+
+namespace {
+
+std::mutex g_err_mu;
+std::string g_err;  // last error raised without a plan
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+template <class T>
+hipError_t dalloc(T** ptr, size_t count) {
+    *ptr = nullptr;
+    if (count == 0) return hipSuccess;
+    return hipMalloc((void**)ptr, count * sizeof(T));
+}
+
+// Modified Bessel function I0 by its power series sum_k ((x/2)^2)^k / (k!)^2.
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 200; ++k) {
+        term *= q / ((double)k * k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// Kaiser-Bessel window phi(u) = I0(beta sqrt(1 - (2u/W)^2)) / I0(beta) on |u| <= W/2 and its
+// Fourier transform W sinh(sqrt(beta^2 - (W nu / 2)^2)) / sqrt(...) / I0(beta) (sin form past the
+// zero of the root).  beta follows Beatty, Nishimura & Pauly (2005) for oversampling 2.
+double kb_phi(double u, int W, double beta) {
+    const double t = 2.0 * u / W;
+    if (std::fabs(t) > 1.0) return 0.0;
+    return bessel_i0(beta * std::sqrt(std::max(0.0, 1.0 - t * t))) / bessel_i0(beta);
+}
+
+double kb_phihat(double nu, int W, double beta) {
+    const double z2 = beta * beta - 0.25 * W * W * nu * nu;
+    double v;
+    if (z2 > 1e-12) { const double z = std::sqrt(z2); v = W * std::sinh(z) / z; }
+    else if (z2 < -1e-12) { const double z = std::sqrt(-z2); v = W * std::sin(z) / z; }
+    else v = W;
+    return v / bessel_i0(beta);
+}
+
+// Solve the (n x n) system A c = y by Gaussian elimination with partial pivoting.
+void solve_dense(std::vector<double>& A, std::vector<double>& y, int n) {
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[r * n + c]) > std::fabs(A[piv * n + c])) piv = r;
+        if (piv != c) {
+            for (int k = 0; k < n; ++k) std::swap(A[c * n + k], A[piv * n + k]);
+            std::swap(y[c], y[piv]);
+        }
+        for (int r = c + 1; r < n; ++r) {
+            const double f = A[r * n + c] / A[c * n + c];
+            for (int k = c; k < n; ++k) A[r * n + k] -= f * A[c * n + k];
+            y[r] -= f * y[c];
+        }
+    }
+    for (int c = n - 1; c >= 0; --c) {
+        double s = y[c];
+        for (int k = c + 1; k < n; ++k) s -= A[c * n + k] * y[k];
+        y[c] = s / A[c * n + c];
+    }
+}
+
+}  // namespace
+
+// Window tables: per window cell j a degree-KB_DEG polynomial in x = 2 f - 1 (f in [0, 1],
+// the cell offset is u = f - W/2 + j) interpolating phi at Chebyshev nodes; reciprocal
+// transforms for the deconvolution of the kernel (L = 4N, circulant positions) and of
+// A*b (L = 2N, centred indices).
+void kb_tables(firm_plan p, std::vector<float>& poly, std::vector<float>& dker, std::vector<float>& datb) {
+    const int W = p->kbw, D = KB_DEG, N = p->N;
+    const double beta = p->beta;
+    poly.assign((size_t)W * (D + 1), 0.f);
+    for (int j = 0; j < W; ++j) {
+        std::vector<double> A((D + 1) * (D + 1)), y(D + 1);
+        for (int i = 0; i <= D; ++i) {
+            const double x = std::cos(M_PI * (i + 0.5) / (D + 1));
+            const double u = 0.5 * (x + 1.0) - 0.5 * W + j;
+            double xp = 1.0;
+            for (int k = 0; k <= D; ++k) { A[i * (D + 1) + k] = xp; xp *= x; }
+            y[i] = kb_phi(u, W, beta);
+        }
+        solve_dense(A, y, D + 1);
+        for (int k = 0; k <= D; ++k) poly[j * (D + 1) + k] = (float)y[k];
+    }
+    dker.assign(2 * N, 0.f);
+    const double Lk = 4.0 * N;
+    for (int pp = 0; pp < 2 * N; ++pp) {
+        if (pp == N) continue;
+        const int n = pp < N ? pp : pp - 2 * N;
+        dker[pp] = (float)(1.0 / kb_phihat(2.0 * M_PI * n / Lk, W, beta));
+    }
+    datb.assign(N, 0.f);
+    const double La = 2.0 * N;
+    for (int i = 0; i < N; ++i) {
+        const int n = i - N / 2;
+        datb[i] = (float)(1.0 / kb_phihat(2.0 * M_PI * n / La, W, beta));
+    }
+}
+
+firm_status firm_fail(firm_plan p, firm_status s, const std::string& msg) {
+    if (p) p->err = msg;
+    else { std::lock_guard<std::mutex> lk(g_err_mu); g_err = msg; }
+    return s;
+}
+
+extern "C" {
+
+int64_t firm_slice_points(int N) {
+    if (N <= 0 || N > 4096) return -1;
+    int64_t P = 0;
+    for (int k1 = -N / 2; k1 <= N / 2; ++k1)
+        for (int k2 = -N / 2; k2 <= N / 2; ++k2)
+            if (4LL * (k1 * k1 + k2 * k2) <= (int64_t)N * N) ++P;
+    return P;
+}
+
+const char* firm_last_error(firm_plan p) {
+    if (p) return p->err.c_str();
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    return g_err.c_str();
+}
+
+void firm_plan_destroy(firm_plan p) {
+    if (!p) return;
+    void* dev[] = {p->c12, p->nrm, p->group, p->table, p->shifts, p->kb_poly, p->deconv_ker, p->deconv_atb,
+                   p->tw, p->kerc, p->khat, p->T1, p->T2, p->r, p->p, p->q, p->z, p->tmp, p->partials,
+                   p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
+                   p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
+                   p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->rhs, p->dvec};
+    for (void* d : dev)
+        if (d) (void)hipFree(d);
+    if (p->host_scal) (void)hipHostFree(p->host_scal);
+    if (p->host_flags) (void)hipHostFree(p->host_flags);
+    delete p;
+}
+
+firm_status firm_plan_set_stream(firm_plan p, void* stream) {
+    if (!p) return firm_fail(nullptr, FIRM_ERR_ARG, "null plan");
+    p->stream = (hipStream_t)stream;
+    return FIRM_OK;
+}
+
+firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, const double* shifts,
+                             const int32_t* ctf_group, int G, const float* ctf_table, const firm_options* opt) {
+    if (!out) return firm_fail(nullptr, FIRM_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!is_pow2(N) || N < 8 || N > 256) return firm_fail(nullptr, FIRM_ERR_ARG, "N must be a power of two in [8, 256]");
+    if (M < 1 || M > (1 << 24)) return firm_fail(nullptr, FIRM_ERR_ARG, "M must be in [1, 2^24]");
+    if (!rot) return firm_fail(nullptr, FIRM_ERR_ARG, "rotations is null");
+    if (ctf_table && G < 1) return firm_fail(nullptr, FIRM_ERR_ARG, "G must be >= 1 with a CTF table");
+    const int Q = N * N / 4 + 1;
+    const int Geff = ctf_table ? G : 1;
+    for (int m = 0; m < M; ++m) {
+        const double* R = rot + 9 * (int64_t)m;
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(R[i])) return firm_fail(nullptr, FIRM_ERR_ARG, "rotation " + std::to_string(m) + " not finite");
+        double dev = 0.0;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0;
+                for (int k = 0; k < 3; ++k) s += R[3 * k + i] * R[3 * k + j];
+                dev = std::max(dev, std::fabs(s - (i == j ? 1.0 : 0.0)));
+            }
+        const double det = R[0] * (R[4] * R[8] - R[5] * R[7]) - R[1] * (R[3] * R[8] - R[5] * R[6]) +
+                           R[2] * (R[3] * R[7] - R[4] * R[6]);
+        if (dev > 1e-6 || det <= 0)
+            return firm_fail(nullptr, FIRM_ERR_ARG, "rotation " + std::to_string(m) + " is not in SO(3)");
+        if (shifts && (!std::isfinite(shifts[2 * (int64_t)m]) || !std::isfinite(shifts[2 * (int64_t)m + 1])))
+            return firm_fail(nullptr, FIRM_ERR_ARG, "shift " + std::to_string(m) + " not finite");
+        if (ctf_group && (ctf_group[m] < 0 || ctf_group[m] >= Geff))
+            return firm_fail(nullptr, FIRM_ERR_ARG, "ctf_group[" + std::to_string(m) + "] out of [0, G)");
+    }
+    if (ctf_table)
+        for (int64_t i = 0; i < (int64_t)G * Q; ++i)
+            if (!std::isfinite(ctf_table[i])) return firm_fail(nullptr, FIRM_ERR_ARG, "ctf_table not finite");
+    firm_options o{};
+    if (opt) o = *opt;
+    if (o.kb_width == 0) o.kb_width = 7;
+    if (o.kb_width < 4 || o.kb_width > 8) return firm_fail(nullptr, FIRM_ERR_ARG, "kb_width must be in [4, 8]");
+    if (o.reserved != 0) return firm_fail(nullptr, FIRM_ERR_ARG, "reserved option must be 0");
+    if (o.check_every < 0) return firm_fail(nullptr, FIRM_ERR_ARG, "check_every must be >= 0");
+    if (o.precision < 0 || o.precision > 2) return firm_fail(nullptr, FIRM_ERR_ARG, "precision must be 0, 1 or 2");
+    if (o.lambda_relative != 0 && o.lambda_relative != 1)
+        return firm_fail(nullptr, FIRM_ERR_ARG, "lambda_relative must be 0 or 1");
+    if (!(o.inner_tol >= 0.0) || o.inner_tol >= 1.0) return firm_fail(nullptr, FIRM_ERR_ARG, "inner_tol must be in [0, 1)");
+
+    firm_plan p = new firm_plan_s();
+    p->N = N; p->M = M; p->G = Geff; p->Q = Q;
+    p->P = (int)firm_slice_points(N);
+    p->QP = ((N + 1) + 15) / 16 * 16;
+    p->QPn = ((N / 2 + 1) + 15) / 16 * 16;
+    p->kbw = o.kb_width;
+    const double sig = 2.0;
+    p->beta = M_PI * std::sqrt((o.kb_width / sig) * (o.kb_width / sig) * (sig - 0.5) * (sig - 0.5) - 0.8);
+    p->refine_every = o.refine_every == 0 ? 50 : o.refine_every;
+    p->check_every = o.check_every == 0 ? 10 : o.check_every;
+    p->stream = (hipStream_t)o.stream;
+    p->precision = o.precision;
+    p->lambda_relative = o.lambda_relative;
+    p->inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+
+    // geometry: columns 1 and 2 of R^{-1} = R^T are rows 1 and 2 of R; normal = c1 x c2
+    std::vector<double> c12((size_t)M * 6);
+    std::vector<float> nrm((size_t)M * 4);
+    std::vector<int32_t> grp(M, 0);
+    double k0 = 0.0;
+    for (int m = 0; m < M; ++m) {
+        const double* R = rot + 9 * (int64_t)m;
+        double* c = &c12[6 * (size_t)m];
+        for (int d = 0; d < 3; ++d) { c[d] = R[d]; c[3 + d] = R[3 + d]; }
+        const double n0 = c[1] * c[5] - c[2] * c[4], n1 = c[2] * c[3] - c[0] * c[5], n2 = c[0] * c[4] - c[1] * c[3];
+        nrm[4 * m] = (float)n0; nrm[4 * m + 1] = (float)n1; nrm[4 * m + 2] = (float)n2; nrm[4 * m + 3] = 0.f;
+        if (ctf_group) grp[m] = ctf_group[m];
+        const double h0 = ctf_table ? (double)ctf_table[(int64_t)grp[m] * Q] : 1.0;
+        k0 += h0 * h0;
+    }
+    p->ker_k0 = k0;
+    std::vector<int> rowstart(N + 1);
+    {
+        int off = 0;
+        for (int k1 = -N / 2; k1 <= N / 2; ++k1) {
+            int lo = 1, cnt = 0;
+            for (int k2 = -N / 2; k2 <= N / 2; ++k2)
+                if (4 * (k1 * k1 + k2 * k2) <= N * N) { if (cnt == 0) lo = k2; ++cnt; }
+            rowstart[k1 + N / 2] = off - lo;
+            off += cnt;
+        }
+    }
+    std::vector<float2> tw(FIRM_TWN);
+    for (int m = 0; m < FIRM_TWN; ++m) {
+        const double a = -2.0 * M_PI * m / FIRM_TWN;
+        tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    std::vector<float> poly, dker, datb;
+    kb_tables(p, poly, dker, datb);
+    std::vector<int> wk = spread_worklist(4 * N, spread_tile_real(), M, 4.0);
+    std::vector<int> wa = spread_worklist(2 * N, spread_tile_cplx(), M, 2.0);
+    p->ntiles_ker = (int)(wk.size() / 4);
+    p->ntiles_atb = (int)(wa.size() / 4);
+
+    const int64_t n3 = (int64_t)N * N * N;
+    const int64_t N2 = 2 * N;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(dalloc(&p->c12, c12.size()));
+    chk(dalloc(&p->nrm, nrm.size()));
+    chk(dalloc(&p->group, (size_t)M));
+    if (ctf_table) chk(dalloc(&p->table, (size_t)G * Q));
+    if (shifts) chk(dalloc(&p->shifts, (size_t)M * 2));
+    chk(dalloc(&p->kb_poly, poly.size()));
+    chk(dalloc(&p->deconv_ker, dker.size()));
+    chk(dalloc(&p->deconv_atb, datb.size()));
+    chk(dalloc(&p->tw, (size_t)FIRM_TWN));
+    chk(dalloc(&p->kerc, (size_t)(N2 * N2 * N2)));
+    chk(dalloc(&p->khat, (size_t)(N2 * N2 * p->QP)));
+    chk(dalloc(&p->T1, (size_t)((int64_t)N * N * p->QP)));
+    chk(dalloc(&p->T2, (size_t)((int64_t)N * N2 * p->QP)));
+    chk(dalloc(&p->r, (size_t)n3));
+    chk(dalloc(&p->p, (size_t)n3));
+    chk(dalloc(&p->q, (size_t)n3));
+    chk(dalloc(&p->z, (size_t)n3));
+    chk(dalloc(&p->tmp, (size_t)n3));
+    p->npart = 16384;
+    chk(dalloc(&p->partials, (size_t)p->npart));
+    chk(dalloc(&p->partials2, (size_t)p->npart));
+    chk(dalloc(&p->partials3, (size_t)p->npart));
+    chk(dalloc(&p->scal, 32));
+    chk(dalloc(&p->flags, 8));
+    chk(dalloc(&p->dhalf, (size_t)((int64_t)N * N * p->QPn)));
+    chk(dalloc(&p->S1, (size_t)((int64_t)N * N * p->QPn)));
+    chk(dalloc(&p->dscal, 8));
+    chk(dalloc(&p->rowstart, (size_t)(N + 1)));
+    chk(dalloc(&p->tiles_ker, wk.size()));
+    chk(dalloc(&p->tiles_atb, wa.size()));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_scal, 32 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&p->host_flags, 8 * sizeof(int), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        firm_plan_destroy(p);
+        return firm_fail(nullptr, e == hipErrorOutOfMemory ? FIRM_ERR_ALLOC : FIRM_ERR_HIP,
+                         std::string("plan allocation: ") + hipGetErrorString(e));
+    }
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    };
+    up(p->c12, c12.data(), c12.size() * sizeof(double));
+    up(p->nrm, nrm.data(), nrm.size() * sizeof(float));
+    up(p->group, grp.data(), grp.size() * sizeof(int32_t));
+    if (ctf_table) up(p->table, ctf_table, (size_t)G * Q * sizeof(float));
+    if (shifts) up(p->shifts, shifts, (size_t)M * 2 * sizeof(double));
+    up(p->kb_poly, poly.data(), poly.size() * sizeof(float));
+    up(p->deconv_ker, dker.data(), dker.size() * sizeof(float));
+    up(p->deconv_atb, datb.data(), datb.size() * sizeof(float));
+    up(p->tw, tw.data(), tw.size() * sizeof(float2));
+    up(p->rowstart, rowstart.data(), rowstart.size() * sizeof(int));
+    up(p->tiles_ker, wk.data(), wk.size() * sizeof(int));
+    up(p->tiles_atb, wa.data(), wa.size() * sizeof(int));
+    if (e != hipSuccess) {
+        firm_plan_destroy(p);
+        return firm_fail(nullptr, FIRM_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));
+    }
+    *out = p;
+    return FIRM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+firm_status ensure_ws(firm_plan p, void** ptr, size_t* have, size_t need) {
+    if (*have >= need) return FIRM_OK;
+    if (*ptr) { (void)hipFree(*ptr); *ptr = nullptr; *have = 0; }
+    hipError_t e = hipMalloc(ptr, need);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return firm_fail(p, FIRM_ERR_ALLOC, std::string("workspace allocation: ") + hipGetErrorString(e));
+    }
+    *have = need;
+    return FIRM_OK;
+}
+
+// Workspaces for both gridding pipelines (sized for the larger, the kernel's).
+firm_status ensure_grid_ws(firm_plan p) {
+    const size_t N = p->N, L = 4 * N, N2 = 2 * N;
+    const size_t grid = std::max(L * L * L * sizeof(float), N2 * N2 * N2 * sizeof(float2));
+    const size_t w1 = std::max({L * L * N * sizeof(float2), N2 * N2 * N * sizeof(float2),
+                                N2 * N2 * (size_t)p->QP * sizeof(float2)});
+    const size_t w2 = std::max(L * N2 * N * sizeof(float2) + N2 * N2 * N * sizeof(float),
+                               N2 * N * N * sizeof(float2));
+    firm_status s;
+    if ((s = ensure_ws(p, &p->grid, &p->grid_bytes, grid)) != FIRM_OK) return s;
+    if ((s = ensure_ws(p, &p->ws1, &p->ws1_bytes, w1)) != FIRM_OK) return s;
+    return ensure_ws(p, &p->ws2, &p->ws2_bytes, w2);
+}
+
+// Ker(0) of the current kernel (circulant position 0), for the relative lambda reading.
+firm_status read_ker0(firm_plan p) {
+    float v = 0.f;
+    FIRM_HIP(p, hipMemcpyAsync(&v, p->kerc, sizeof(float), hipMemcpyDeviceToHost, p->stream));
+    FIRM_HIP(p, hipStreamSynchronize(p->stream));
+    p->ker0 = v;
+    return FIRM_OK;
+}
+
+double lambda_eff(firm_plan p, double lam) { return p->lambda_relative ? lam * p->ker0 : lam; }
+
+}  // namespace
+
+firm_status ensure_fp64(firm_plan p) {
+    const size_t N = p->N, N2 = 2 * N, n3 = N * N * N;
+    hipError_t e = hipSuccess;
+    auto al = [&](auto** ptr, size_t count) {
+        if (e == hipSuccess && *ptr == nullptr) e = hipMalloc((void**)ptr, count * sizeof(**ptr));
+    };
+    al(&p->khat64, N2 * N2 * p->QP);
+    al(&p->T1d, N * N * p->QP);
+    al(&p->T2d, N * N2 * p->QP);
+    al(&p->tw64, (size_t)FIRM_TWN);
+    al(&p->x64, n3);
+    al(&p->r64, n3);
+    al(&p->p64, n3);
+    al(&p->q64, n3);
+    al(&p->y64, n3);
+    al(&p->rhs, n3);
+    al(&p->dvec, n3);
+    if (e != hipSuccess) return firm_fail(p, FIRM_ERR_ALLOC, std::string("FP64 buffers: ") + hipGetErrorString(e));
+    if (!p->khat64_valid) {
+        std::vector<double2> tw(FIRM_TWN);
+        for (int m = 0; m < FIRM_TWN; ++m) {
+            const double a = -2.0 * M_PI * m / FIRM_TWN;
+            tw[m] = make_double2(std::cos(a), std::sin(a));
+        }
+        FIRM_HIP(p, hipMemcpy(p->tw64, tw.data(), tw.size() * sizeof(double2), hipMemcpyHostToDevice));
+        double* k64 = nullptr;
+        double2* w1 = nullptr;
+        FIRM_HIP(p, hipMalloc((void**)&k64, N2 * N2 * N2 * sizeof(double)));
+        e = hipMalloc((void**)&w1, N2 * N2 * p->QP * sizeof(double2));
+        if (e == hipSuccess) e = kerc_to_double(p, k64);
+        if (e == hipSuccess) e = fft_khat64_from_kerc64(p, k64, w1);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        (void)hipFree(k64);
+        if (w1) (void)hipFree(w1);
+        if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("FP64 spectrum: ") + hipGetErrorString(e));
+        p->khat64_valid = true;
+    }
+    return FIRM_OK;
+}
+
+extern "C" {
+
+firm_status firm_kernel_precompute(firm_plan p) {
+    if (!p) return firm_fail(nullptr, FIRM_ERR_ARG, "null plan");
+    firm_status s = ensure_grid_ws(p);
+    if (s != FIRM_OK) return s;
+    const size_t N = p->N, L = 4 * N, N2 = 2 * N;
+    float* grid = (float*)p->grid;
+    float2* h1 = (float2*)p->ws1;
+    float2* h2 = (float2*)p->ws2;
+    float* chalf = (float*)((char*)p->ws2 + L * N2 * N * sizeof(float2));
+    FIRM_HIP(p, fill_zero(grid, L * L * L * sizeof(float), p->stream));
+    FIRM_HIP(p, spread_ker(p, grid));
+    FIRM_HIP(p, fft_ker_grid(p, grid, h1, h2, chalf));
+    FIRM_HIP(p, kerc_from_half(p, chalf));
+    FIRM_HIP(p, fft_khat_from_kerc(p, (float2*)p->ws1));
+    p->have_kernel = true;
+    p->khat64_valid = false;
+    return read_ker0(p);
+}
+
+firm_status firm_kernel_get(firm_plan p, float* ker) {
+    if (!p || !ker) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
+    FIRM_HIP(p, kerc_to_centred(p, ker));
+    return FIRM_OK;
+}
+
+firm_status firm_kernel_set(firm_plan p, const float* ker) {
+    if (!p || !ker) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    const size_t N2 = 2 * p->N;
+    firm_status s = ensure_ws(p, &p->ws1, &p->ws1_bytes, N2 * N2 * (size_t)p->QP * sizeof(float2));
+    if (s != FIRM_OK) return s;
+    FIRM_HIP(p, kerc_from_centred(p, ker));
+    FIRM_HIP(p, fft_khat_from_kerc(p, (float2*)p->ws1));
+    p->have_kernel = true;
+    p->khat64_valid = false;
+    return read_ker0(p);
+}
+
+firm_status firm_kernel_spectrum(firm_plan p, float* khat) {
+    if (!p || !khat) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    const size_t N = p->N, N2 = 2 * N;
+    FIRM_HIP(p, hipMemcpy2DAsync(khat, (N + 1) * sizeof(float), p->khat, p->QP * sizeof(float),
+                                 (N + 1) * sizeof(float), N2 * N2, hipMemcpyDeviceToDevice, p->stream));
+    return FIRM_OK;
+}
+
+firm_status firm_backproject(firm_plan p, const void* b, float* atb) {
+    if (!p || !b || !atb) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    firm_status s = ensure_grid_ws(p);
+    if (s != FIRM_OK) return s;
+    const size_t N = p->N, L = 2 * N;
+    float2* grid = (float2*)p->grid;
+    float2* j1 = (float2*)p->ws1;
+    float2* j2 = (float2*)p->ws2;
+    FIRM_HIP(p, fill_zero(grid, L * L * L * sizeof(float2), p->stream));
+    FIRM_HIP(p, spread_atb(p, (const float2*)b, grid));
+    FIRM_HIP(p, atb_k0_term(p, (const float2*)b, p->dscal));
+    FIRM_HIP(p, fft_atb_grid(p, grid, j1, j2, atb, p->dscal));
+    return FIRM_OK;
+}
+
+firm_status firm_apply_AtA(firm_plan p, const float* x, float* y, double lambda) {
+    if (!p || !x || !y) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (x == y) return firm_fail(p, FIRM_ERR_ARG, "x and y must not alias");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
+    FIRM_HIP(p, fft_apply_AtA(p, x, y, (float)lambda_eff(p, lambda)));
+    return FIRM_OK;
+}
+
+firm_status firm_apply_AtA_f64(firm_plan p, const double* x, double* y, double lambda) {
+    if (!p || !x || !y) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (x == y) return firm_fail(p, FIRM_ERR_ARG, "x and y must not alias");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
+    firm_status s = ensure_fp64(p);
+    if (s != FIRM_OK) return s;
+    FIRM_HIP(p, fft_apply_AtA64(p, x, y, lambda_eff(p, lambda)));
+    return FIRM_OK;
+}
+
+firm_status firm_cg_solve(firm_plan p, const float* atb, float* x, double lambda, double tol, int max_iter,
+                          const float* d, firm_cg_report* rep) {
+    if (!p || !atb || !x) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return firm_fail(p, FIRM_ERR_ARG, "tol must be finite and >= 0");
+    if (max_iter < 0) return firm_fail(p, FIRM_ERR_ARG, "max_iter must be >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
+    if (rep) std::memset(rep, 0, sizeof(*rep));
+    return cg_solve(p, atb, x, lambda_eff(p, lambda), tol, max_iter, d, rep);
+}
+
+firm_status firm_precond_apply(firm_plan p, const float* d, const float* r, float* z) {
+    if (!p || !d || !r || !z) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    FIRM_HIP(p, precond_set(p, d));
+    FIRM_HIP(p, fft_precond(p, p->dhalf, r, z));
+    return FIRM_OK;
+}
+
+firm_status firm_synth_slices(firm_plan p, int B, const double* centers, const double* sigmas, const double* amps,
+                              double snr, uint64_t seed, void* b) {
+    if (!p || !b || (B > 0 && (!centers || !sigmas || !amps))) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (B < 1 || B > 320) return firm_fail(p, FIRM_ERR_ARG, "B must be in [1, 320]");
+    std::vector<double> bl((size_t)B * 5);
+    for (int i = 0; i < B; ++i) {
+        if (!(sigmas[i] >= 0.0)) return firm_fail(p, FIRM_ERR_ARG, "sigma must be >= 0");
+        for (int d = 0; d < 3; ++d) bl[5 * i + d] = centers[3 * i + d];
+        bl[5 * i + 3] = sigmas[i];
+        bl[5 * i + 4] = sigmas[i] > 0 ? amps[i] * std::pow(2.0 * M_PI * sigmas[i] * sigmas[i], 1.5) : amps[i];
+    }
+    double* dbl = nullptr;
+    FIRM_HIP(p, hipMalloc((void**)&dbl, bl.size() * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dbl, bl.data(), bl.size() * sizeof(double), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = synth_slices(p, B, dbl, snr, seed, (float2*)b, p->partials);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(dbl);
+    if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("synth: ") + hipGetErrorString(e));
+    return FIRM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,525 @@
+// Conjugate gradients for (A*A + lambda I) x = A*b (section 3.3, step 4 of the
+// algorithm in section 3.4), with an optional Fourier-diagonal preconditioner
+// (circulant diagonalisation, eq. circ1).
+//
+// Precision modes:
+//  0  FP32 CG: vectors and the FFT product in FP32; every inner product is
+//     accumulated in FP64 (per-block partials, then a one-block reduction) and
+//     the scalars alpha, beta and the residual norms live in FP64 on the device,
+//     so an iteration needs no host round trip.  The direction update
+//     p = z + beta p is fused into the first FFT pass of the product and <p, q>
+//     into its last pass.  Every refine_every iterations the recursive residual
+//     is replaced by the residual recomputed from the FP32 product.  The host
+//     reads a small flag block every check_every iterations; kernels enqueued
+//     after convergence see the flag and exit.
+//  1  FP64 iterative refinement: the residual, the product that forms it and the
+//     solution are FP64; each correction is an FP32 (P)CG solve of the residual
+//     equation to a relative tolerance.  Reaches residuals below the FP32
+//     product's accuracy at nearly FP32 cost.
+//  2  FP64 CG: vectors, product and sums in FP64 (the kernel values themselves
+//     are the FP32 ones).
+// Every mode reports the true residual measured with the FP64 product.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "fft_core.h"
+#include "firm_internal.h"
+
+namespace {
+
+enum { S_RZ = 0, S_PQ, S_ALPHA, S_BETA, S_RR, S_BB, S_TOL2, S_TRUE };
+enum { F_ACTIVE = 0, F_ITER, F_REASON, F_MAXIT };
+enum { R_RUN = 0, R_CONV = 1, R_MAXIT = 2, R_BREAK = 3 };
+
+constexpr int VB = 1024;  // blocks of the vector kernels
+constexpr int VT = 256;
+
+__device__ __forceinline__ double block_reduce(double v) {
+    __shared__ double red[VT / 64];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < VT / 64; ++i) s += red[i];
+    return s;
+}
+
+__device__ __forceinline__ double sum_partials(const double* part, int n) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += VT) a += part[i];
+    return block_reduce(a);
+}
+
+// r = atb - y in FP64, stored FP32; partial sums of r^2.
+__global__ void __launch_bounds__(VT) k_resid(const float* __restrict__ atb, const float* __restrict__ y,
+                                              float* __restrict__ r, int64_t n, double* partials,
+                                              const int* flags) {
+    if (flags && flags[F_ACTIVE] == 0) return;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+        const double v = (double)atb[i] - (double)y[i];
+        const float f = (float)v;
+        r[i] = f;
+        acc += (double)f * (double)f;
+    }
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(VT) k_dot(const float* __restrict__ a, const float* __restrict__ b, int64_t n,
+                                            double* partials) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT)
+        acc += (double)a[i] * (double)b[i];
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// scal[idx] = sum of partials; when copy_to >= 0 also scal[copy_to].
+__global__ void __launch_bounds__(VT) k_reduce_to(const double* part, int n, double* scal, int idx, int copy_to,
+                                                  const int* flags) {
+    if (flags && flags[F_ACTIVE] == 0) return;
+    const double s = sum_partials(part, n);
+    if (threadIdx.x == 0) {
+        scal[idx] = s;
+        if (copy_to >= 0) scal[copy_to] = s;
+    }
+}
+
+__global__ void k_init(double* scal, int* flags, double tol, int max_iter) {
+    scal[S_TOL2] = tol * tol * scal[S_BB];
+    scal[S_BETA] = 0.0;
+    flags[F_ITER] = 0;
+    flags[F_MAXIT] = max_iter;
+    const bool done = !(scal[S_RR] > scal[S_TOL2]) || max_iter <= 0;
+    flags[F_ACTIVE] = done ? 0 : 1;
+    flags[F_REASON] = done ? (max_iter <= 0 && scal[S_RR] > scal[S_TOL2] ? R_MAXIT : R_CONV) : R_RUN;
+}
+
+__global__ void __launch_bounds__(VT) k_alpha(const double* part, int n, double* scal, int* flags) {
+    if (flags[F_ACTIVE] == 0) return;
+    const double pq = sum_partials(part, n);
+    if (threadIdx.x == 0) {
+        scal[S_PQ] = pq;
+        const double a = scal[S_RZ] / pq;
+        if (!(pq > 0.0) || !isfinite(a)) {
+            flags[F_ACTIVE] = 0;
+            flags[F_REASON] = R_BREAK;
+        } else {
+            scal[S_ALPHA] = a;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha q (FP64 arithmetic, FP32 storage); partial sums of r^2.
+__global__ void __launch_bounds__(VT) k_update(float* __restrict__ x, const float* __restrict__ p,
+                                               float* __restrict__ r, const float* __restrict__ q, int64_t n,
+                                               const double* scal, const int* flags, double* partials) {
+    if (flags[F_ACTIVE] == 0) return;
+    const double a = scal[S_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+        x[i] = (float)((double)x[i] + a * (double)p[i]);
+        const float rv = (float)((double)r[i] - a * (double)q[i]);
+        r[i] = rv;
+        acc += (double)rv * (double)rv;
+    }
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// rr = ||r||^2, rz = <r, z> (= rr without preconditioner), beta = rz_new / rz_old, stop tests.
+__global__ void __launch_bounds__(VT) k_beta(const double* part_rr, int n_rr, const double* part_rz, int n_rz,
+                                             double* scal, int* flags) {
+    if (flags[F_ACTIVE] == 0) return;
+    const double rr = sum_partials(part_rr, n_rr);
+    __syncthreads();
+    const double rz = part_rz ? sum_partials(part_rz, n_rz) : rr;
+    if (threadIdx.x == 0) {
+        const double b = rz / scal[S_RZ];
+        scal[S_RR] = rr;
+        scal[S_BETA] = b;
+        scal[S_RZ] = rz;
+        const int it = flags[F_ITER] + 1;
+        flags[F_ITER] = it;
+        if (!isfinite(rr) || (part_rz && (!(rz > 0.0) || !isfinite(b)))) {
+            flags[F_ACTIVE] = 0;
+            flags[F_REASON] = R_BREAK;
+        } else if (rr <= scal[S_TOL2]) {
+            flags[F_ACTIVE] = 0;
+            flags[F_REASON] = R_CONV;
+        } else if (it >= flags[F_MAXIT]) {
+            flags[F_ACTIVE] = 0;
+            flags[F_REASON] = R_MAXIT;
+        }
+    }
+}
+
+__global__ void k_set_active(int* flags, double* scal, int restart_dir) {
+    flags[F_ACTIVE] = flags[F_ITER] < flags[F_MAXIT] ? 1 : 0;
+    flags[F_REASON] = flags[F_ACTIVE] ? R_RUN : R_MAXIT;
+    if (restart_dir) scal[S_BETA] = 0.0;
+}
+
+// d (centred order) -> dhalf[j1][j2][j3] = (d(q) + d(-q)) / (2 N^3), FFT order, j3 <= N/2
+__global__ void k_precond_set(const float* __restrict__ d, float* __restrict__ dh, int N, int QPn) {
+    const int H = N / 2 + 1;
+    const int64_t tot = (int64_t)N * N * H;
+    const double inv = 1.0 / ((double)N * N * N);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int j3 = (int)(i % H), j2 = (int)((i / H) % N), j1 = (int)(i / ((int64_t)H * N));
+        const int c1 = (j1 + N / 2) % N, c2 = (j2 + N / 2) % N, c3 = (j3 + N / 2) % N;
+        const int m1 = (N - j1) % N, m2 = (N - j2) % N, m3 = (N - j3) % N;
+        const int e1 = (m1 + N / 2) % N, e2 = (m2 + N / 2) % N, e3 = (m3 + N / 2) % N;
+        const double v = 0.5 * ((double)d[((int64_t)c1 * N + c2) * N + c3] + (double)d[((int64_t)e1 * N + e2) * N + e3]);
+        dh[((int64_t)j1 * N + j2) * QPn + j3] = (float)(v * inv);
+    }
+}
+
+#define CK(e)                                                                              \
+    do {                                                                                   \
+        hipError_t e__ = (e);                                                              \
+        if (e__ != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string(#e) + ": " + hipGetErrorString(e__)); \
+    } while (0)
+
+}  // namespace
+
+hipError_t precond_set(firm_plan p, const float* d_centred) {
+    const int N = p->N;
+    const int64_t n = (int64_t)N * N * (N / 2 + 1);
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_precond_set, dim3(blocks), dim3(256), 0, p->stream, d_centred, p->dhalf, N, p->QPn);
+    return hipGetLastError();
+}
+
+// FP32 CG (FP64 sums and scalars) on (A*A + lam) x = atb from the guess in x.  Stops when the
+// residual measured with the FP32 product is <= tol ||atb|| or after max_iter iterations.
+static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                             const float* d, firm_cg_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int N = p->N;
+    const int64_t n = (int64_t)N * N * N;
+    hipStream_t st = p->stream;
+    double* scal = p->scal;
+    int* flags = p->flags;
+    const int nb_apply = ceil_div((int64_t)N * N / 2, 2 * N >= 1024 ? 8 : (2 * N >= 128 ? 16 : 2048 / (2 * N)));
+    const int nb_prec = ceil_div((int64_t)N * N / 2, N >= 1024 ? 8 : (N >= 128 ? 16 : 2048 / N));
+    bool pc = (d != nullptr);
+    int refinements = 0, fell_back = 0;
+
+    if (pc) CK(precond_set(p, d));
+    // r = atb - (A*A + lam) x, ||atb||^2
+    CK(fft_apply_AtA(p, x, p->tmp, (float)lam));
+    hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, nullptr);
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RR, -1, nullptr);
+    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_BB, -1, nullptr);
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(1), 0, st, scal, flags, tol, max_iter);
+    CK(fill_zero(p->p, n * sizeof(float), st));
+    auto set_rz = [&](bool guarded) -> hipError_t {
+        const int* fl = guarded ? flags : nullptr;
+        if (pc) {
+            hipError_t e = fft_precond(p, p->dhalf, p->r, p->z, fl, p->partials2);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials2, nb_prec, scal, (int)S_RZ, -1, fl);
+        } else {
+            hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RZ, -1, fl);
+        }
+        return hipGetLastError();
+    };
+    // rz from the initial residual (partials3 still holds ||r||^2 partials only if no
+    // preconditioner; recompute them to be safe)
+    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, p->r, p->r, n, p->partials3);
+    CK(set_rz(false));
+
+    int it_host = 0;
+    firm_status result = FIRM_OK;
+    for (;;) {
+        for (int i = 0; i < p->check_every; ++i) {
+            const float* src = pc ? p->z : p->r;
+            CK(fft_apply_cg(p, src, p->p, p->q, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
+            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(VT), 0, st, p->partials, nb_apply, scal, flags);
+            hipLaunchKernelGGL(k_update, dim3(VB), dim3(VT), 0, st, x, p->p, p->r, p->q, n, scal, flags,
+                               p->partials3);
+            if (pc) CK(fft_precond(p, p->dhalf, p->r, p->z, flags + F_ACTIVE, p->partials2));
+            hipLaunchKernelGGL(k_beta, dim3(1), dim3(VT), 0, st, p->partials3, VB, pc ? p->partials2 : nullptr,
+                               nb_prec, scal, flags);
+            ++it_host;
+            if (p->refine_every > 0 && it_host % p->refine_every == 0) {
+                // true residual replacement, skipped by the kernels once inactive
+                CK(fft_apply_AtA(p, x, p->tmp, (float)lam));
+                hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, flags);
+                hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RR,
+                                   (int)S_TRUE, flags);
+                CK(set_rz(true));
+                ++refinements;
+            }
+        }
+        CK(hipMemcpyAsync(p->host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        if (p->host_flags[F_ACTIVE]) continue;
+        const int reason = p->host_flags[F_REASON];
+        if (reason == R_BREAK) {
+            if (pc) {  // restart as plain CG from the current x
+                pc = false;
+                fell_back = 1;
+                CK(fft_apply_AtA(p, x, p->tmp, (float)lam));
+                hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, nullptr);
+                hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RR,
+                                   (int)S_RZ, nullptr);
+                hipLaunchKernelGGL(k_set_active, dim3(1), dim3(1), 0, st, flags, scal, 1);
+                continue;
+            }
+            result = FIRM_ERR_BREAKDOWN;
+            break;
+        }
+        // confirm with the true residual (FP64 sum of the FP32 product)
+        CK(fft_apply_AtA(p, x, p->tmp, (float)lam));
+        hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, nullptr);
+        hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_TRUE,
+                           (int)S_RR, nullptr);
+        CK(hipMemcpyAsync(p->host_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipMemcpyAsync(p->host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        const bool ok = p->host_scal[S_TRUE] <= p->host_scal[S_TOL2];
+        if (ok) { result = FIRM_OK; break; }
+        if (p->host_flags[F_ITER] >= max_iter) { result = FIRM_ERR_NOT_CONVERGED; break; }
+        // recursive residual drifted below tol: continue from the true residual
+        CK(set_rz(false));
+        hipLaunchKernelGGL(k_set_active, dim3(1), dim3(1), 0, st, flags, scal, 0);
+        ++refinements;
+    }
+    CK(hipMemcpyAsync(p->host_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipMemcpyAsync(p->host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    if (rep) {
+        const double bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
+        rep->iters = p->host_flags[F_ITER];
+        rep->refinements = refinements;
+        rep->fell_back = fell_back;
+        rep->status = result;
+        rep->rel_res = std::sqrt(p->host_scal[S_RR] / bb);
+        rep->true_rel_res = std::sqrt(p->host_scal[S_TRUE] / bb);
+        rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return result;
+}
+
+namespace {
+
+__global__ void k_d_from_f(double* __restrict__ o, const float* __restrict__ a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) o[i] = a[i];
+}
+__global__ void k_f_from_d(float* __restrict__ o, const double* __restrict__ a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) o[i] = (float)a[i];
+}
+__global__ void k_add_f_to_d(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) x[i] += (double)d[i];
+}
+// r = atb - y (FP64); partial sums of r^2
+__global__ void __launch_bounds__(VT) k_resid64(const float* __restrict__ atb, const double* __restrict__ y,
+                                                double* __restrict__ r, int64_t n, double* partials) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+        const double v = (double)atb[i] - y[i];
+        r[i] = v;
+        acc += v * v;
+    }
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+__global__ void __launch_bounds__(VT) k_dot64(const double* __restrict__ a, const double* __restrict__ b, int64_t n,
+                                              double* partials) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) acc += a[i] * b[i];
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+__global__ void k_dir64(double* __restrict__ pv, const double* __restrict__ r, const double* scal, int64_t n) {
+    const double b = scal[S_BETA];
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) pv[i] = r[i] + b * pv[i];
+}
+__global__ void __launch_bounds__(VT) k_update64(double* __restrict__ x, const double* __restrict__ pv,
+                                                 double* __restrict__ r, const double* __restrict__ q, int64_t n,
+                                                 const double* scal, double* partials) {
+    const double a = scal[S_ALPHA];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
+        x[i] += a * pv[i];
+        const double rv = r[i] - a * q[i];
+        r[i] = rv;
+        acc += rv * rv;
+    }
+    const double s = block_reduce(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+__global__ void k_set_scalar(double* scal, int idx, double v) { scal[idx] = v; }
+__global__ void k_alpha64(double* scal) {
+    scal[S_ALPHA] = scal[S_RZ] / scal[S_PQ];
+}
+__global__ void k_beta64(double* scal) {
+    scal[S_BETA] = scal[S_RR] / scal[S_RZ];
+    scal[S_RZ] = scal[S_RR];
+}
+
+}  // namespace
+
+#define L1(k, ...) hipLaunchKernelGGL(k, dim3(VB), dim3(VT), 0, st, __VA_ARGS__)
+#define R1(...) hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, __VA_ARGS__)
+
+// ||atb - (A*A + lam) x||^2 with the FP64 product (x given in FP32); also ||atb||^2.
+static firm_status true_residual64(firm_plan p, const float* atb, const float* x, double lam, double* rr,
+                                   double* bb) {
+    firm_status fs = ensure_fp64(p);
+    if (fs != FIRM_OK) return fs;
+    const int64_t n = (int64_t)p->N * p->N * p->N;
+    hipStream_t st = p->stream;
+    L1(k_d_from_f, p->x64, x, n);
+    CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+    L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
+    R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
+    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    R1(p->partials3, VB, p->scal, (int)S_BB, -1, nullptr);
+    CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    *rr = p->host_scal[S_TRUE];
+    *bb = p->host_scal[S_BB];
+    return FIRM_OK;
+}
+
+// FP64 CG: vectors, product and sums in double (khat64 from the FP32 kernel values).
+static firm_status cg_fp64(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                           firm_cg_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    firm_status fs = ensure_fp64(p);
+    if (fs != FIRM_OK) return fs;
+    const int64_t n = (int64_t)p->N * p->N * p->N;
+    hipStream_t st = p->stream;
+    double* sc = p->scal;
+    L1(k_d_from_f, p->x64, x, n);
+    CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+    L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
+    R1(p->partials3, VB, sc, (int)S_RR, (int)S_RZ, nullptr);
+    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    R1(p->partials3, VB, sc, (int)S_BB, -1, nullptr);
+    hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, st, sc, (int)S_BETA, 0.0);
+    CK(fill_zero(p->p64, n * sizeof(double), st));
+    CK(hipMemcpyAsync(p->host_scal, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const double bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
+    double rr = p->host_scal[S_RR];
+    int it = 0;
+    firm_status result = FIRM_OK;
+    while (rr > tol * tol * bb) {
+        if (it >= max_iter) { result = FIRM_ERR_NOT_CONVERGED; break; }
+        L1(k_dir64, p->p64, p->r64, sc, n);
+        CK(fft_apply_AtA64(p, p->p64, p->q64, lam));
+        L1(k_dot64, p->p64, p->q64, n, p->partials);
+        R1(p->partials, VB, sc, (int)S_PQ, -1, nullptr);
+        hipLaunchKernelGGL(k_alpha64, dim3(1), dim3(1), 0, st, sc);
+        L1(k_update64, p->x64, p->p64, p->r64, p->q64, n, sc, p->partials3);
+        R1(p->partials3, VB, sc, (int)S_RR, -1, nullptr);
+        hipLaunchKernelGGL(k_beta64, dim3(1), dim3(1), 0, st, sc);
+        CK(hipMemcpyAsync(p->host_scal, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        ++it;
+        rr = p->host_scal[S_RR];
+        if (!(p->host_scal[S_PQ] > 0.0) || !std::isfinite(rr)) { result = FIRM_ERR_BREAKDOWN; break; }
+    }
+    L1(k_f_from_d, x, p->x64, n);
+    if (rep) {
+        rep->iters = it;
+        rep->status = result;
+        rep->rel_res = std::sqrt(rr / bb);
+    }
+    double trr = 0, tbb = 1;
+    fs = true_residual64(p, atb, x, lam, &trr, &tbb);
+    if (fs != FIRM_OK) return fs;
+    if (rep) {
+        rep->true_rel_res = std::sqrt(trr / (tbb > 0 ? tbb : 1.0));
+        rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return result;
+}
+
+// FP64 iterative refinement: r = atb - (A*A + lam) x with the FP64 product and FP64 x; each
+// correction solves (A*A + lam) d = r with FP32 (P)CG to a relative tolerance, x += d.
+static firm_status cg_refine64(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                               const float* d, firm_cg_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    firm_status fs = ensure_fp64(p);
+    if (fs != FIRM_OK) return fs;
+    const int64_t n = (int64_t)p->N * p->N * p->N;
+    hipStream_t st = p->stream;
+    L1(k_d_from_f, p->x64, x, n);
+    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    R1(p->partials3, VB, p->scal, (int)S_BB, -1, nullptr);
+    CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+    CK(hipStreamSynchronize(st));
+    const double bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
+    int total = 0, outer = 0, fell_back = 0, refinements = 0;
+    double rr = 0.0;
+    firm_status result = FIRM_OK;
+    for (;;) {
+        CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+        L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
+        R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
+        CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+        CK(hipStreamSynchronize(st));
+        rr = p->host_scal[S_TRUE];
+        if (!std::isfinite(rr)) { result = FIRM_ERR_BREAKDOWN; break; }
+        if (rr <= tol * tol * bb) break;
+        if (total >= max_iter) { result = FIRM_ERR_NOT_CONVERGED; break; }
+        // correction with the FP32 solver; the rhs is the FP64 residual rounded to FP32
+        L1(k_f_from_d, p->rhs, p->r64, n);
+        CK(fill_zero(p->dvec, n * sizeof(float), st));
+        const double rel = std::sqrt(rr / bb);
+        const double inner = std::max(p->inner_tol, 0.5 * tol / rel);
+        firm_cg_report ir{};
+        firm_status is = cg_core32(p, p->rhs, p->dvec, lam, std::min(inner, 0.5), max_iter - total, d, &ir);
+        if (is != FIRM_OK && is != FIRM_ERR_NOT_CONVERGED && is != FIRM_ERR_BREAKDOWN) return is;
+        total += ir.iters;
+        fell_back |= ir.fell_back;
+        refinements += ir.refinements;
+        L1(k_add_f_to_d, p->x64, p->dvec, n);
+        ++outer;
+        if (ir.iters == 0) { result = FIRM_ERR_NOT_CONVERGED; break; }  // no progress possible
+    }
+    L1(k_f_from_d, x, p->x64, n);
+    CK(hipStreamSynchronize(st));
+    if (rep) {
+        rep->iters = total;
+        rep->refinements = outer;
+        rep->fell_back = fell_back;
+        rep->status = result;
+        rep->rel_res = std::sqrt(rr / bb);
+        rep->true_rel_res = std::sqrt(rr / bb);
+        rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    (void)refinements;
+    return result;
+}
+
+firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                     const float* d, firm_cg_report* rep) {
+    firm_status r;
+    if (p->precision == 2) {
+        r = cg_fp64(p, atb, x, lam, tol, max_iter, rep);
+    } else if (p->precision == 1) {
+        r = cg_refine64(p, atb, x, lam, tol, max_iter, d, rep);
+    } else {
+        r = cg_core32(p, atb, x, lam, tol, max_iter, d, rep);
+        if (r == FIRM_OK || r == FIRM_ERR_NOT_CONVERGED) {
+            double trr = 0, tbb = 1;
+            firm_status fs = true_residual64(p, atb, x, lam, &trr, &tbb);
+            if (fs != FIRM_OK) return fs;
+            if (rep) rep->true_rel_res = std::sqrt(trr / (tbb > 0 ? tbb : 1.0));
+        }
+    }
+    if (rep) rep->status = r;
+    if (r == FIRM_ERR_NOT_CONVERGED) return firm_fail(p, r, "CG reached max_iter above tol");
+    if (r == FIRM_ERR_BREAKDOWN) return firm_fail(p, r, "CG breakdown (non-positive curvature)");
+    return r;
+}

@@ -1,0 +1,133 @@
+// Internal declarations shared by the HIP translation units of libfirm.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/firm.h"
+
+#define FIRM_TWN 1024  // twiddle table length: exp(-2 pi i m / 1024), m in [0, 1024)
+
+struct firm_plan_s {
+    int N = 0, M = 0, G = 0, P = 0, Q = 0;  // Q = N*N/4 + 1 (CTF table width)
+    int QP = 0;                              // pitch of the half-spectrum axis (>= N+1)
+    int kbw = 7;
+    double beta = 0.0;
+    int refine_every = 50, check_every = 10;
+    int precision = 0;          // 0 FP32 CG, 1 FP64 iterative refinement, 2 FP64 CG
+    int lambda_relative = 0;    // lambda multiplies Ker(0)
+    double inner_tol = 1e-3;    // relative tolerance of each FP32 correction (precision 1)
+    double ker0 = 0.0;          // Ker(0) of the current kernel
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // geometry (device)
+    double* c12 = nullptr;     // M x 6: columns 1 and 2 of R_m^{-1}
+    float* nrm = nullptr;      // M x 4: plane normal (c1 x c2), float
+    int32_t* group = nullptr;  // M
+    float* table = nullptr;    // G x Q (h), or null
+    double* shifts = nullptr;  // M x 2 or null
+    double ker_k0 = 0.0;       // sum_m h_m(0)^2: the k = 0 term of Ker
+
+    // Kaiser-Bessel window (device)
+    float* kb_poly = nullptr;  // w x (KB_DEG+1) polynomial coefficients on f in [0, 1]
+    float* deconv_ker = nullptr;  // 2N: 1/phihat at circulant position p (L = 4N)
+    float* deconv_atb = nullptr;  // N: 1/phihat at centred index i (L = 2N)
+
+    float2* tw = nullptr;      // FIRM_TWN twiddles
+
+    // kernel and its spectrum (device)
+    bool have_kernel = false;
+    float* kerc = nullptr;     // (2N)^3 Ker in circulant order c[p1][p2][p3]
+    float* khat = nullptr;     // [2N][2N][QP] real spectrum, q3 in [0, N]
+
+    // apply workspaces
+    float2* T1 = nullptr;      // [N][N][QP]
+    float2* T2 = nullptr;      // [N][2N][QP]
+
+    // FP64 product (allocated on first use): spectrum, workspaces, twiddles, vectors
+    bool khat64_valid = false;
+    double* khat64 = nullptr;  // [2N][2N][QP]
+    double2* T1d = nullptr;
+    double2* T2d = nullptr;
+    double2* tw64 = nullptr;
+    double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *y64 = nullptr;
+    float *rhs = nullptr, *dvec = nullptr;  // FP32 correction right-hand side and solution
+
+    // CG workspaces
+    float *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *tmp = nullptr;
+    double* partials = nullptr;  // per-block FP64 partial sums
+    int npart = 0;
+    double* scal = nullptr;      // device scalars (see cg.hip)
+    double* host_scal = nullptr; // pinned host mirror
+    float* dhalf = nullptr;      // preconditioner diagonal, [N][N][QPn] in FFT order
+    float2* S1 = nullptr;        // PCG FFT workspace [N][N][QPn]
+    int QPn = 0;
+
+    // gridding workspaces (allocated on first use, kept)
+    void* grid = nullptr; size_t grid_bytes = 0;
+    void* ws1 = nullptr; size_t ws1_bytes = 0;
+    void* ws2 = nullptr; size_t ws2_bytes = 0;
+    int* tiles_ker = nullptr; int ntiles_ker = 0;   // work list for the kernel spread
+    int* tiles_atb = nullptr; int ntiles_atb = 0;   // work list for the A*b spread
+    double* dscal = nullptr;   // small device scratch for the A*b k=0 term
+    int* rowstart = nullptr;   // N+1: disk index of (k1, 0), so idx(k1, k2) = rowstart[k1 + N/2] + k2
+    int* flags = nullptr;      // CG control words on device (see cg.hip)
+    int* host_flags = nullptr; // pinned mirror
+    double* partials2 = nullptr;
+    double* partials3 = nullptr;
+};
+
+// status helpers (api.cpp)
+firm_status firm_fail(firm_plan p, firm_status s, const std::string& msg);
+#define FIRM_HIP(p, call)                                                                 \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return firm_fail((p), FIRM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// ---- fft.hip launchers (return hipError_t of the launch) ----
+hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam);
+hipError_t fft_khat_from_kerc(firm_plan p, float2* w1);        // kerc -> khat (w1: [2N][2N][QP])
+hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, float* chalf);
+hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2, float* atb,
+                        const double* k0term);
+hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z, const int* active = nullptr,
+                       double* partials = nullptr);
+hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam);
+hipError_t fft_khat64_from_kerc64(firm_plan p, const double* kerc64, double2* w1);
+// fused CG variants of the apply passes (cg.hip drives them)
+hipError_t fft_apply_cg(firm_plan p, const float* r, float* pvec, float* q, float lam,
+                        const double* beta_dev, const int* active, double* partials);
+
+// ---- spread.hip ----
+hipError_t spread_ker(firm_plan p, float* grid);
+hipError_t spread_atb(firm_plan p, const float2* b, float2* grid);
+hipError_t atb_k0_term(firm_plan p, const float2* b, double* out);
+hipError_t kerc_from_half(firm_plan p, const float* chalf);
+hipError_t kerc_to_centred(firm_plan p, float* out);
+hipError_t kerc_from_centred(firm_plan p, const float* in);
+hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t s);
+hipError_t kerc_to_double(firm_plan p, double* out);
+firm_status ensure_fp64(firm_plan p);  // api.hip: FP64 buffers and khat64
+
+// ---- synth.hip ----
+hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,
+                        float2* b, double* power_dev);
+
+// ---- cg.hip ----
+firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                     const float* d, firm_cg_report* rep);
+hipError_t precond_set(firm_plan p, const float* d_centred);
+
+std::vector<int> spread_worklist(int L, int T, int M, double s);
+int spread_tile_real();
+int spread_tile_cplx();
+void kb_tables(firm_plan p, std::vector<float>& poly, std::vector<float>& dker, std::vector<float>& datb);
+
+// block count helper
+static inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

@@ -1,0 +1,390 @@
+// Type-1 non-uniform FFT gridding of libfirm (section 3.4, steps 2 and 3).
+//
+// Ker (eq. kernel) and A*b (eq. backprojection) are sums over the sample points
+// xi_{k,m} = R_m^{-1}(omega_k, 0).  In fine-grid units (grid size L = s N) the
+// point is t = s (k1 c1_m + k2 c2_m), c1, c2 the first two columns of R_m^{-1}.
+// Each point is spread with a separable Kaiser-Bessel window of width W onto a
+// periodic grid; a grid FFT divided by the window's transform gives the sums.
+//
+// Work decomposition: the grid is cut into T^3 tiles.  A workgroup owns one
+// tile (or one tile and a range of images): it tests every image plane of its
+// range against the tile's circumscribed sphere, enumerates the disk points of
+// the surviving images whose cell floor(t + L/2) lies in the tile, and
+// accumulates their full W^3 stencils into a (T + W)^3 LDS tile with LDS
+// atomics; the tile is then added to the global grid with one atomic per cell.
+// Each point is spread exactly once.  Only the half disk (k1 > 0, or k1 = 0 and
+// k2 > 0) is spread: its partner -k is folded in (Ker is real and even; for A*b
+// the pair (k, -k) gives the real part exactly), and k = 0 is added afterwards
+// in closed form.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "firm_internal.h"
+
+#define KB_DEG 10
+#define SP_THREADS 256
+#define SP_QCAP 1024
+
+namespace {
+
+struct SpreadArgs {
+    int N, M, L, nt;
+    double s;
+    const double* c12;
+    const float* nrm;
+    const int32_t* group;
+    const float* table;
+    int Q;
+    const float* poly;
+    const int4* work;
+    void* grid;
+    const float2* b;
+    const double* shifts;
+    const int* rowstart;  // index of (k1, 0) shifted: idx(k1, k2) = rowstart[k1 + N/2] + k2
+    int P;
+};
+
+template <int W>
+__device__ __forceinline__ void kb_weights(const float* __restrict__ poly, float x, float* out) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const float* c = poly + j * (KB_DEG + 1);
+        float v = c[KB_DEG];
+#pragma unroll
+        for (int d = KB_DEG - 1; d >= 0; --d) v = fmaf(v, x, c[d]);
+        out[j] = v;
+    }
+}
+
+template <int T, int W, bool CPLX>
+__global__ void __launch_bounds__(SP_THREADS) k_spread(SpreadArgs a) {
+    constexpr int PT = T + W;
+    constexpr int PADLO = (W + 1) / 2 - 1;
+    constexpr int NCELL = PT * PT * PT;
+    constexpr int NV = CPLX ? 2 : 1;
+    __shared__ float tile[NCELL * NV];
+    __shared__ int img_m[SP_THREADS];
+    __shared__ int img_k1[SP_THREADS], img_k2[SP_THREADS];
+    __shared__ int queue[SP_QCAP];
+    __shared__ int nimg, qn, any;
+
+    const int tid = threadIdx.x;
+    const int4 wk = a.work[blockIdx.x];
+    const int nt = a.nt;
+    const int tt[3] = {wk.x / (nt * nt), (wk.x / nt) % nt, wk.x % nt};
+    const int L = a.L, N = a.N;
+    const double halfL = 0.5 * L;
+
+    for (int i = tid; i < NCELL * NV; i += SP_THREADS) tile[i] = 0.f;
+    if (tid == 0) any = 0;
+
+    const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
+    const double Rt = T * 0.8660254037844386 + 1e-3;
+    const double rk = Rt / a.s;
+    const int S = (int)floor(2.0 * rk) + 3;
+    const int SS = S * S;
+    const int N2 = N * N;
+
+    for (int mb = wk.y; mb < wk.z; mb += SP_THREADS) {
+        __syncthreads();
+        if (tid == 0) nimg = 0;
+        __syncthreads();
+        const int m = mb + tid;
+        if (m < wk.z) {
+            const float* n = a.nrm + 4 * (int64_t)m;
+            const double dist = fabs(tc[0] * n[0] + tc[1] * n[1] + tc[2] * n[2]);
+            if (dist <= Rt + 1e-3) {
+                const double* c = a.c12 + 6 * (int64_t)m;
+                const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
+                const double u2 = (tc[0] * c[3] + tc[1] * c[4] + tc[2] * c[5]) / a.s;
+                const int sl = atomicAdd(&nimg, 1);
+                img_m[sl] = m;
+                img_k1[sl] = (int)ceil(u1 - rk) - 1;
+                img_k2[sl] = (int)ceil(u2 - rk) - 1;
+            }
+        }
+        __syncthreads();
+        const int total = nimg * SS;
+        for (int base = 0; base < total; base += SP_QCAP) {
+            if (tid == 0) qn = 0;
+            __syncthreads();
+            const int lim = min(total, base + SP_QCAP);
+            for (int i = base + tid; i < lim; i += SP_THREADS) {
+                const int sl = i / SS, cc = i - sl * SS;
+                const int k1 = img_k1[sl] + cc / S, k2 = img_k2[sl] + cc % S;
+                if (!(k1 > 0 || (k1 == 0 && k2 > 0))) continue;
+                if (4 * (k1 * k1 + k2 * k2) > N2) continue;
+                const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                bool in = true;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
+                    int cell = (int)floor(tau);
+                    cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+                    in = in && (cell / T == tt[d]);
+                }
+                if (in) {
+                    const int qi = atomicAdd(&qn, 1);
+                    queue[qi] = (sl << 18) | ((k1 + 256) << 9) | (k2 + 256);
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && qn > 0) any = 1;
+            for (int qi = tid; qi < qn; qi += SP_THREADS) {
+                const int e = queue[qi];
+                const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
+                const int m = img_m[sl];
+                const double* c = a.c12 + 6 * (int64_t)m;
+                float ph[3][W];
+                int lo[3];
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
+                    // stencil stays inside the padded tile for every width
+                    const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
+                    const double left = tau - 0.5 * W;
+                    const int b0 = (int)floor(left) + 1;
+                    const float f = (float)((double)b0 - left);  // in (0, 1]
+                    kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
+                    lo[d] = b0 - (tt[d] * T - PADLO);
+                }
+                const int g = a.group ? a.group[m] : 0;
+                const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
+                float vr, vi = 0.f;
+                if (!CPLX) {
+                    vr = 2.f * h * h;
+                } else {
+                    // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
+                    const int idx = a.rowstart[k1 + N / 2] + k2;
+                    const float2 bp = a.b[(int64_t)m * a.P + idx];
+                    const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
+                    const float sr = bp.x + bm.x, si = bp.y - bm.y;
+                    float cs = 1.f, sn = 0.f;
+                    if (a.shifts) {
+                        const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
+                                                              k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+                        cs = (float)cos(th);
+                        sn = (float)sin(th);
+                    }
+                    vr = h * (cs * sr - sn * si);
+                    vi = h * (cs * si + sn * sr);
+                }
+#pragma unroll
+                for (int j1 = 0; j1 < W; ++j1) {
+#pragma unroll
+                    for (int j2 = 0; j2 < W; ++j2) {
+                        const float w12 = ph[0][j1] * ph[1][j2];
+                        const int base = ((lo[0] + j1) * PT + (lo[1] + j2)) * PT + lo[2];
+#pragma unroll
+                        for (int j3 = 0; j3 < W; ++j3) {
+                            const float w = w12 * ph[2][j3];
+                            if (!CPLX) {
+                                __hip_atomic_fetch_add(&tile[base + j3], vr * w, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                            } else {
+                                __hip_atomic_fetch_add(&tile[2 * (base + j3)], vr * w, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_add(&tile[2 * (base + j3) + 1], vi * w, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (!any) return;
+    const int o0 = tt[0] * T - PADLO, o1 = tt[1] * T - PADLO, o2 = tt[2] * T - PADLO;
+    for (int i = tid; i < NCELL; i += SP_THREADS) {
+        const int l0 = i / (PT * PT), l1 = (i / PT) % PT, l2 = i % PT;
+        // grid index = position mod L, position = cell - L/2
+        const int g0 = ((o0 + l0 - L / 2) % L + L) % L;
+        const int g1 = ((o1 + l1 - L / 2) % L + L) % L;
+        const int g2 = ((o2 + l2 - L / 2) % L + L) % L;
+        const int64_t gi = ((int64_t)g0 * L + g1) * L + g2;
+        if (!CPLX) {
+            const float v = tile[i];
+            if (v != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, v);
+        } else {
+            const float vr = tile[2 * i], vi = tile[2 * i + 1];
+            float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
+            if (vr != 0.f) unsafeAtomicAdd(gp, vr);
+            if (vi != 0.f) unsafeAtomicAdd(gp + 1, vi);
+        }
+    }
+}
+
+__global__ void k_fill_zero(float4* p, size_t n4) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// Re sum_m h_m(0) b(0, m): the k = 0 term of Re A*b (its exponential is 1 for all n).
+__global__ void k_atb_k0(const float2* __restrict__ b, const int32_t* group, const float* table, int Q, int M,
+                         int P, double* out) {
+    __shared__ double red[4];
+    double acc = 0.0;
+    const int c = (P - 1) / 2;
+    for (int m = threadIdx.x; m < M; m += 256) {
+        const int g = group ? group[m] : 0;
+        const float h = table ? table[(int64_t)g * Q] : 1.f;
+        acc += (double)h * (double)b[(int64_t)m * P + c].x;
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = red[0] + red[1] + red[2] + red[3];
+}
+
+// chalf[p1][p2][n3] (n3 in [0, N)) -> kerc[p1][p2][p3] using Ker(-n) = Ker(n); p3 = N is 0.
+__global__ void k_kerc_from_half(const float* __restrict__ chalf, float* __restrict__ kerc, int N) {
+    const int N2 = 2 * N;
+    const int64_t tot = (int64_t)N2 * N2 * N2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int p3 = (int)(i % N2), p2 = (int)((i / N2) % N2), p1 = (int)(i / ((int64_t)N2 * N2));
+        float v;
+        if (p3 < N) v = chalf[((int64_t)p1 * N2 + p2) * N + p3];
+        else if (p3 == N) v = 0.f;
+        else v = chalf[((int64_t)((N2 - p1) % N2) * N2 + (N2 - p2) % N2) * N + (N2 - p3)];
+        kerc[i] = v;
+    }
+}
+
+// circulant order c[p] (offset o(p)) <-> centred order ker[j] (offset j - N)
+__global__ void k_kerc_centred(const float* __restrict__ src, float* __restrict__ dst, int N, int to_centred) {
+    const int N2 = 2 * N;
+    const int64_t tot = (int64_t)N2 * N2 * N2;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
+        const int a3 = (int)(i % N2), a2 = (int)((i / N2) % N2), a1 = (int)(i / ((int64_t)N2 * N2));
+        // index a in the destination order; map to the source order
+        int s1, s2, s3;
+        if (to_centred) {  // dst centred j -> offset j - N -> circulant p = offset mod 2N
+            s1 = (a1 - N + N2) % N2; s2 = (a2 - N + N2) % N2; s3 = (a3 - N + N2) % N2;
+            const bool wrap = (a1 == 0) || (a2 == 0) || (a3 == 0);
+            dst[i] = wrap ? 0.f : src[((int64_t)s1 * N2 + s2) * N2 + s3];
+        } else {           // dst circulant p -> offset o(p) -> centred j = o + N; p = N is the wrap
+            const bool wrap = (a1 == N) || (a2 == N) || (a3 == N);
+            s1 = (a1 + N) % N2; s2 = (a2 + N) % N2; s3 = (a3 + N) % N2;
+            dst[i] = wrap ? 0.f : src[((int64_t)s1 * N2 + s2) * N2 + s3];
+        }
+    }
+}
+
+__global__ void k_f2d(const float* __restrict__ a, double* __restrict__ o, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        o[i] = a[i];
+}
+
+int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
+
+template <int T, bool CPLX>
+hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* grid, const float2* b) {
+    SpreadArgs a;
+    a.N = p->N; a.M = p->M; a.L = L; a.nt = (L + T - 1) / T;
+    a.s = (double)L / p->N;
+    a.c12 = p->c12; a.nrm = p->nrm; a.group = p->group; a.table = p->table; a.Q = p->Q;
+    a.poly = p->kb_poly; a.work = reinterpret_cast<const int4*>(work); a.grid = grid;
+    a.b = b; a.shifts = p->shifts; a.rowstart = p->rowstart; a.P = p->P;
+    if (nwork == 0) return hipSuccess;
+    switch (p->kbw) {
+        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+#define SP_TILE_REAL 16
+#define SP_TILE_CPLX 12
+
+// Host work list: tiles of an L^3 grid that can hold points (|centre| - R <= L/2), each
+// split into image ranges of about `chunk` images for the most loaded tiles, ordered by
+// expected work (tiles near the origin meet every image plane) so that the heavy ones start first.
+std::vector<int> spread_worklist(int L, int T, int M, double s) {
+    const int nt = (L + T - 1) / T;
+    const double Rt = T * 0.8660254037844386;
+    struct Item { double w; int t, m0, m1; };
+    std::vector<Item> items;
+    const int chunk = 16384;
+    for (int a = 0; a < nt; ++a)
+        for (int b = 0; b < nt; ++b)
+            for (int c = 0; c < nt; ++c) {
+                const double x = a * T + 0.5 * T - 0.5 * L, y = b * T + 0.5 * T - 0.5 * L,
+                             z = c * T + 0.5 * T - 0.5 * L;
+                const double rho = std::sqrt(x * x + y * y + z * z);
+                if (rho - Rt > 0.5 * L + 1.0) continue;
+                const double frac = rho <= Rt ? 1.0 : Rt / rho;
+                const double expect = frac * M;
+                const int nch = std::max(1, (int)std::ceil(expect / chunk));
+                const int per = (M + nch - 1) / nch;
+                for (int k = 0; k < nch; ++k) {
+                    const int m0 = k * per, m1 = std::min(M, m0 + per);
+                    if (m0 < m1) items.push_back({expect / nch, (a * nt + b) * nt + c, m0, m1});
+                }
+            }
+    std::stable_sort(items.begin(), items.end(), [](const Item& u, const Item& v) { return u.w > v.w; });
+    std::vector<int> out;
+    out.reserve(items.size() * 4);
+    for (auto& it : items) { out.push_back(it.t); out.push_back(it.m0); out.push_back(it.m1); out.push_back(0); }
+    (void)s;
+    return out;
+}
+
+int spread_tile_real() { return SP_TILE_REAL; }
+int spread_tile_cplx() { return SP_TILE_CPLX; }
+
+hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t s) {
+    const size_t n4 = bytes / 16;
+    if (n4) hipLaunchKernelGGL(k_fill_zero, dim3(grid_blocks(n4)), dim3(256), 0, s, (float4*)ptr, n4);
+    const size_t rem = bytes - n4 * 16;
+    if (rem) {
+        hipError_t e = hipMemsetAsync((char*)ptr + n4 * 16, 0, rem, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t spread_ker(firm_plan p, float* grid) {
+    return launch_spread<SP_TILE_REAL, false>(p, 4 * p->N, p->tiles_ker, p->ntiles_ker, grid, nullptr);
+}
+
+hipError_t spread_atb(firm_plan p, const float2* b, float2* grid) {
+    return launch_spread<SP_TILE_CPLX, true>(p, 2 * p->N, p->tiles_atb, p->ntiles_atb, grid, b);
+}
+
+hipError_t atb_k0_term(firm_plan p, const float2* b, double* out) {
+    hipLaunchKernelGGL(k_atb_k0, dim3(1), dim3(256), 0, p->stream, b, p->group, p->table, p->Q, p->M, p->P, out);
+    return hipGetLastError();
+}
+
+hipError_t kerc_from_half(firm_plan p, const float* chalf) {
+    const int64_t n = 8LL * p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_kerc_from_half, dim3(grid_blocks(n)), dim3(256), 0, p->stream, chalf, p->kerc, p->N);
+    return hipGetLastError();
+}
+
+hipError_t kerc_to_centred(firm_plan p, float* out) {
+    const int64_t n = 8LL * p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_kerc_centred, dim3(grid_blocks(n)), dim3(256), 0, p->stream, p->kerc, out, p->N, 1);
+    return hipGetLastError();
+}
+
+hipError_t kerc_from_centred(firm_plan p, const float* in) {
+    const int64_t n = 8LL * p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_kerc_centred, dim3(grid_blocks(n)), dim3(256), 0, p->stream, in, p->kerc, p->N, 0);
+    return hipGetLastError();
+}
+
+hipError_t kerc_to_double(firm_plan p, double* out) {
+    const int64_t n = 8LL * p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_f2d, dim3(grid_blocks(n)), dim3(256), 0, p->stream, p->kerc, out, n);
+    return hipGetLastError();
+}

@@ -1,0 +1,246 @@
+"""Thin ctypes binding of libfirm (include/firm.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device buffers
+are torch tensors on the ROCm device; the plan's stream is torch's current
+stream unless one is given.  Importing this module loads libfirm.so and raises
+if it has not been built (python -m paper_1307_5824_amd.build).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfirm.so")
+
+FIRM_OK = 0
+FIRM_ERR_ARG = 1
+FIRM_ERR_ALLOC = 2
+FIRM_ERR_HIP = 3
+FIRM_ERR_STATE = 4
+FIRM_ERR_BREAKDOWN = 5
+FIRM_ERR_NOT_CONVERGED = 6
+STATUS_NAMES = {0: "FIRM_OK", 1: "FIRM_ERR_ARG", 2: "FIRM_ERR_ALLOC", 3: "FIRM_ERR_HIP",
+                4: "FIRM_ERR_STATE", 5: "FIRM_ERR_BREAKDOWN", 6: "FIRM_ERR_NOT_CONVERGED"}
+
+
+class FirmOptions(ctypes.Structure):
+    _fields_ = [("kb_width", ctypes.c_int), ("refine_every", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("precision", ctypes.c_int), ("lambda_relative", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("inner_tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
+
+
+class FirmCgReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("refinements", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("status", ctypes.c_int), ("rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double),
+                ("t_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FirmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1307_5824_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i, d, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
+    sig = {
+        "firm_slice_points": (i64, [i]),
+        "firm_plan_create": (i, [ctypes.POINTER(vp), i, i, vp, vp, vp, i, vp, ctypes.POINTER(FirmOptions)]),
+        "firm_plan_destroy": (None, [vp]),
+        "firm_plan_set_stream": (i, [vp, vp]),
+        "firm_kernel_precompute": (i, [vp]),
+        "firm_kernel_get": (i, [vp, vp]),
+        "firm_kernel_set": (i, [vp, vp]),
+        "firm_kernel_spectrum": (i, [vp, vp]),
+        "firm_backproject": (i, [vp, vp, vp]),
+        "firm_apply_AtA": (i, [vp, vp, vp, d]),
+        "firm_apply_AtA_f64": (i, [vp, vp, vp, d]),
+        "firm_cg_solve": (i, [vp, vp, vp, d, d, i, vp, ctypes.POINTER(FirmCgReport)]),
+        "firm_precond_apply": (i, [vp, vp, vp, vp]),
+        "firm_synth_slices": (i, [vp, i, vp, vp, vp, d, ctypes.c_uint64, vp]),
+        "firm_last_error": (ctypes.c_char_p, [vp]),
+        "firm_philox4x32_10": (None, [vp, vp, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error(plan=None):
+    s = lib.firm_last_error(plan)
+    return s.decode() if s else ""
+
+
+def _check(status, plan=None):
+    if status != FIRM_OK:
+        raise FirmError(status, last_error(plan))
+    return status
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _host(a, dtype):
+    if a is None:
+        return None, None
+    arr = np.ascontiguousarray(np.asarray(a, dtype=dtype))
+    return arr, arr.ctypes.data_as(ctypes.c_void_p)
+
+
+def firm_slice_points(N):
+    return int(lib.firm_slice_points(N))
+
+
+def firm_philox4x32_10(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.zeros(4, dtype=np.uint32)
+    lib.firm_philox4x32_10(c.ctypes.data_as(ctypes.c_void_p), k.ctypes.data_as(ctypes.c_void_p),
+                           out.ctypes.data_as(ctypes.c_void_p))
+    return out
+
+
+def _current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def firm_plan_create(N, rotations, shifts=None, ctf_group=None, ctf_table=None, kb_width=0,
+                     refine_every=0, check_every=0, stream=None, precision=0, lambda_relative=0, inner_tol=0.0):
+    """Returns a raw plan handle (c_void_p); see Plan for the managed form."""
+    rot, rotp = _host(np.asarray(rotations, dtype=np.float64).reshape(-1, 9), np.float64)
+    M = rot.shape[0]
+    sh, shp = _host(None if shifts is None else np.asarray(shifts).reshape(M, 2), np.float64)
+    grp, grpp = _host(ctf_group, np.int32)
+    tab, tabp = _host(ctf_table, np.float32)
+    G = 0 if tab is None else (tab.shape[0] if tab.ndim == 2 else 1)
+    opt = FirmOptions(kb_width, refine_every, check_every, precision, lambda_relative, 0, inner_tol, stream)
+    h = ctypes.c_void_p()
+    _check(lib.firm_plan_create(ctypes.byref(h), int(N), int(M), rotp, shp, grpp, int(G), tabp, ctypes.byref(opt)))
+    return h
+
+
+class Plan:
+    """Owns a firm_plan; device tensors are torch tensors on the current ROCm device."""
+
+    def __init__(self, N, rotations, shifts=None, ctf_group=None, ctf_table=None, kb_width=0,
+                 refine_every=0, check_every=0, stream=None, precision=0, lambda_relative=0, inner_tol=0.0):
+        import torch
+        self.N = int(N)
+        self.M = int(np.asarray(rotations).reshape(-1, 9).shape[0])
+        self.P = firm_slice_points(self.N)
+        s = stream if stream is not None else _current_stream()
+        self.h = firm_plan_create(N, rotations, shifts, ctf_group, ctf_table, kb_width, refine_every,
+                                  check_every, s, precision, lambda_relative, inner_tol)
+        self._torch = torch
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib.firm_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vol(self, out=None, n=None):
+        n = n or self.N
+        if out is None:
+            out = self._torch.empty((n, n, n), dtype=self._torch.float32, device="cuda")
+        return out
+
+    def _req(self, t, numel, dtype):
+        if not t.is_cuda or not t.is_contiguous() or t.dtype != dtype or t.numel() != numel:
+            raise ValueError(f"expected a contiguous {dtype} CUDA tensor of {numel} elements")
+        return t
+
+    def set_stream(self, stream):
+        _check(lib.firm_plan_set_stream(self.h, stream), self.h)
+
+    def kernel_precompute(self):
+        _check(lib.firm_kernel_precompute(self.h), self.h)
+
+    def kernel_get(self, out=None):
+        out = self._vol(out, 2 * self.N)
+        self._req(out, (2 * self.N) ** 3, self._torch.float32)
+        _check(lib.firm_kernel_get(self.h, _ptr(out)), self.h)
+        return out
+
+    def kernel_set(self, ker):
+        self._req(ker, (2 * self.N) ** 3, self._torch.float32)
+        _check(lib.firm_kernel_set(self.h, _ptr(ker)), self.h)
+
+    def kernel_spectrum(self, out=None):
+        if out is None:
+            out = self._torch.empty((2 * self.N, 2 * self.N, self.N + 1), dtype=self._torch.float32, device="cuda")
+        self._req(out, 4 * self.N * self.N * (self.N + 1), self._torch.float32)
+        _check(lib.firm_kernel_spectrum(self.h, _ptr(out)), self.h)
+        return out
+
+    def backproject(self, b, out=None):
+        self._req(b, self.M * self.P, self._torch.complex64)
+        out = self._vol(out)
+        self._req(out, self.N ** 3, self._torch.float32)
+        _check(lib.firm_backproject(self.h, _ptr(b), _ptr(out)), self.h)
+        return out
+
+    def apply_AtA(self, x, lam, out=None):
+        self._req(x, self.N ** 3, self._torch.float32)
+        out = self._vol(out)
+        self._req(out, self.N ** 3, self._torch.float32)
+        _check(lib.firm_apply_AtA(self.h, _ptr(x), _ptr(out), float(lam)), self.h)
+        return out
+
+    def apply_AtA_f64(self, x, lam, out=None):
+        self._req(x, self.N ** 3, self._torch.float64)
+        if out is None:
+            out = self._torch.empty((self.N,) * 3, dtype=self._torch.float64, device="cuda")
+        self._req(out, self.N ** 3, self._torch.float64)
+        _check(lib.firm_apply_AtA_f64(self.h, _ptr(x), _ptr(out), float(lam)), self.h)
+        return out
+
+    def cg_solve(self, atb, lam, tol, max_iter, x0=None, precond=None, raise_on_not_converged=False):
+        self._req(atb, self.N ** 3, self._torch.float32)
+        x = self._torch.zeros_like(atb) if x0 is None else x0.clone()
+        if precond is not None:
+            self._req(precond, self.N ** 3, self._torch.float32)
+        rep = FirmCgReport()
+        st = lib.firm_cg_solve(self.h, _ptr(atb), _ptr(x), float(lam), float(tol), int(max_iter),
+                               _ptr(precond), ctypes.byref(rep))
+        if st not in (FIRM_OK, FIRM_ERR_NOT_CONVERGED) or (st != FIRM_OK and raise_on_not_converged):
+            raise FirmError(st, last_error(self.h))
+        return x, rep.as_dict()
+
+    def precond_apply(self, d, r, out=None):
+        self._req(d, self.N ** 3, self._torch.float32)
+        self._req(r, self.N ** 3, self._torch.float32)
+        out = self._vol(out)
+        _check(lib.firm_precond_apply(self.h, _ptr(d), _ptr(r), _ptr(out)), self.h)
+        return out
+
+    def synth_slices(self, centers, sigmas, amps, snr=float("inf"), seed=0, out=None):
+        c, cp = _host(np.asarray(centers).reshape(-1, 3), np.float64)
+        s, sp = _host(np.ravel(sigmas), np.float64)
+        a, ap = _host(np.ravel(amps), np.float64)
+        if out is None:
+            out = self._torch.empty((self.M, self.P), dtype=self._torch.complex64, device="cuda")
+        self._req(out, self.M * self.P, self._torch.complex64)
+        _check(lib.firm_synth_slices(self.h, int(c.shape[0]), cp, sp, ap, float(snr), int(seed), _ptr(out)), self.h)
+        return out

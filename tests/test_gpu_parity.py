@@ -1,0 +1,342 @@
+"""GPU parity of the HIP path against the FP64 oracle at sizes the oracle finishes in seconds.
+
+Tolerance: the FP32 path is held to relative L2 <= 1e-5 against the FP64 oracle (FP32
+rounding of the FFT passes is ~1e-7 per pass; the Kaiser-Bessel gridding at width 7 and
+oversampling 2 is ~1e-6).  Every expected value comes from oracle/; inputs come from the
+seeded generators or from the oracle.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import even_random_kernel, ker_to_centred, rel, small_geometry  # noqa: E402
+from oracle import blobs as oblobs  # noqa: E402
+from oracle import direct as odirect  # noqa: E402
+from oracle import firm as ofirm  # noqa: E402
+from paper_1307_5824_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def firm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1307_5824_amd import firm as f
+    return f
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("N", [8, 16, 32])
+def test_apply_matches_oracle_toeplitz(firm, N):
+    """y = (Ker * x) + lambda x through the circulant embedding vs the oracle's FFT Toeplitz
+    product with the same (oracle-made) kernel (eq. property, embedding_circulant)."""
+    rng = np.random.default_rng(100 + N)
+    print(f"apply N={N}", flush=True)
+    R, _, _, _ = small_geometry(N, 2, N)
+    plan = firm.Plan(N, R)
+    K = even_random_kernel(N, rng)
+    plan.kernel_set(dev(ker_to_centred(K, N)))
+    x = rng.standard_normal((N, N, N))
+    lam = 0.37
+    y = host(plan.apply_AtA(dev(x), lam))
+    ref = ofirm.toeplitz_apply_fft(K, x).real + lam * x
+    assert rel(y, ref) < TOL
+
+
+def test_apply_matches_brute_force(firm):
+    """The same product against the O(N^6) brute-force convolution (eq. toeplitz)."""
+    N = 8
+    rng = np.random.default_rng(7)
+    R, _, _, _ = small_geometry(N, 3, 1)
+    plan = firm.Plan(N, R)
+    K = ofirm.kernel_direct(N, R).real
+    plan.kernel_set(dev(ker_to_centred(K, N)))
+    x = rng.standard_normal((N, N, N))
+    y = host(plan.apply_AtA(dev(x), 0.0))
+    assert rel(y, ofirm.toeplitz_apply_brute(K, x).real) < TOL
+
+
+def test_kernel_get_set_roundtrip(firm):
+    N = 16
+    rng = np.random.default_rng(9)
+    R, _, _, _ = small_geometry(N, 2, 2)
+    plan = firm.Plan(N, R)
+    K = ker_to_centred(even_random_kernel(N, rng), N)
+    plan.kernel_set(dev(K))
+    back = host(plan.kernel_get())
+    assert np.max(np.abs(back - K.astype(np.float32))) == 0.0
+
+
+@pytest.mark.parametrize("N,M,groups", [(8, 20, 2), (16, 200, 0), (16, 60, 3), (32, 12, 2)])
+def test_kernel_precompute_matches_direct_sum(firm, N, M, groups):
+    """Ker from Kaiser-Bessel gridding + FFT vs the direct sum of eq. (kernel) on every offset."""
+    print(f"kernel N={N} M={M} G={groups}", flush=True)
+    R, _, grp, table = small_geometry(N, M, 10 + N + M, groups)
+    plan = firm.Plan(N, R, ctf_group=grp, ctf_table=table)
+    plan.kernel_precompute()
+    got = host(plan.kernel_get())
+    h = ofirm.ctf_weights(N, M, grp, table)
+    ref = ker_to_centred(ofirm.kernel_direct(N, R, h), N)
+    assert rel(got, ref) < TOL
+
+
+@pytest.mark.parametrize("N,M,groups,shifts", [(8, 30, 0, False), (16, 50, 3, True), (32, 8, 2, True)])
+def test_backproject_matches_direct_sum(firm, N, M, groups, shifts):
+    """Re A*(re-centred b) from gridding vs the direct sum of eq. (backprojection) for noisy
+    Hermitian slices of a blob volume."""
+    print(f"backproject N={N} M={M}", flush=True)
+    R, sh, grp, table = small_geometry(N, M, 20 + N, groups, shifts)
+    wl = synth.make_inputs("small")
+    c, s, a = synth.blob_params(N, 4, np.random.default_rng(N))
+    h = ofirm.ctf_weights(N, M, grp, table)
+    b = oblobs.slices(N, R, c, s, a, h=h, shifts=sh)
+    P = ofirm.slice_point_count(N)
+    z = np.random.default_rng(3).standard_normal((M, P, 2))
+    b = b + ofirm.hermitian_noise(N, M, z, ofirm.noise_sigma(b, 0.5))
+    b32 = b.astype(np.complex64)
+    plan = firm.Plan(N, R, shifts=sh, ctf_group=grp, ctf_table=table)
+    got = host(plan.backproject(dev(b32, torch.complex64)))
+    ref = ofirm.back_project(ofirm.recentre(b32.astype(np.complex128), N, sh), N, R, h)
+    assert np.max(np.abs(ref.imag)) <= 1e-6 * np.max(np.abs(ref.real))
+    assert rel(got, ref.real) < TOL
+    del wl
+
+
+def test_backproject_non_hermitian_real_part(firm):
+    """For arbitrary (non-Hermitian) slices the library returns exactly Re A*b."""
+    N, M = 8, 5
+    R, _, _, _ = small_geometry(N, M, 31)
+    P = ofirm.slice_point_count(N)
+    rng = np.random.default_rng(4)
+    b = (rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))).astype(np.complex64)
+    plan = firm.Plan(N, R)
+    got = host(plan.backproject(dev(b, torch.complex64)))
+    ref = ofirm.back_project(b.astype(np.complex128), N, R).real
+    assert rel(got, ref) < TOL
+
+
+def _fp32_envelope(apply, b, k, seed=0):
+    """How far CG's k-th iterate moves when every product and vector is rounded to FP32: the
+    oracle's FP64 CG against the same recursion with FP32 rounding applied (plain numpy on the
+    oracle's own operator).  CG amplifies rounding on ill-conditioned systems; an FP32 solver
+    cannot be held closer to FP64 than this."""
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
+    x = np.zeros_like(b); r = f32(b); p = np.zeros_like(b)
+    rr = float(np.sum(r * r)); beta = 0.0
+    for _ in range(k):
+        p = f32(r + beta * p)
+        q = f32(apply(p))
+        a = rr / float(np.sum(p * q))
+        x = f32(x + a * p); r = f32(r - a * q)
+        rn = float(np.sum(r * r)); beta = rn / rr; rr = rn
+    return x
+
+
+def _small_workload():
+    inp = synth.make_inputs("small")
+    wl = inp.workload
+    V = oblobs.sample_volume(wl.N, inp.centers, inp.sigmas, inp.amps)
+    b = ofirm.forward_project(V, inp.rotations).astype(np.complex64)
+    return inp, wl, b
+
+
+def test_cg_small_workload_fp64_iterates(firm):
+    """The small workload end to end (N=16, 5 blobs, M=200 Haar views, no CTF, noiseless,
+    lambda=1e-3, 20 CG steps from x0 = 0) in FP64 CG: GPU Ker, A*b and x_20 vs the oracle's
+    FP64 CG on its direct-sum kernel.  Window width 8 keeps the gridding error (~1e-7) below
+    what 20 steps amplify past 1e-5."""
+    inp, wl, b = _small_workload()
+    N = wl.N
+    plan = firm.Plan(N, inp.rotations, kb_width=8, precision=2)
+    plan.kernel_precompute()
+    atb = plan.backproject(dev(b, torch.complex64))
+    x, rep = plan.cg_solve(atb, wl.lam, 0.0, 20)
+    Ker = ofirm.kernel_direct(N, inp.rotations)
+    atb_ref = ofirm.back_project(b.astype(np.complex128), N, inp.rotations).real
+    assert rel(host(atb), atb_ref) < TOL
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + wl.lam * v
+    x_ref = ofirm.cg(apply, atb_ref, iters=20)
+    assert rep["iters"] == 20
+    err = rel(host(x), x_ref)
+    print(f"small workload FP64 CG x_20 rel err {err:.3e}", flush=True)
+    assert err < TOL
+
+
+def test_cg_small_workload_fp32_iterates(firm):
+    """The same workload with the FP32 solver: x_5 within 1e-5 of the oracle, and x_20 within
+    4x the FP32 rounding envelope of the oracle's own CG (the envelope is ~2e-4 here: the
+    system's condition number is ~4e7)."""
+    inp, wl, b = _small_workload()
+    N = wl.N
+    plan = firm.Plan(N, inp.rotations)
+    plan.kernel_precompute()
+    atb = plan.backproject(dev(b, torch.complex64))
+    Ker = ofirm.kernel_direct(N, inp.rotations)
+    atb_ref = ofirm.back_project(b.astype(np.complex128), N, inp.rotations).real
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + wl.lam * v
+    x5, _ = plan.cg_solve(atb, wl.lam, 0.0, 5)
+    assert rel(host(x5), ofirm.cg(apply, atb_ref, iters=5)) < TOL
+    x20, _ = plan.cg_solve(atb, wl.lam, 0.0, 20)
+    ref = ofirm.cg(apply, atb_ref, iters=20)
+    env = rel(_fp32_envelope(apply, atb_ref, 20), ref)
+    err = rel(host(x20), ref)
+    print(f"small workload FP32 CG x_20 rel err {err:.3e}, FP32 envelope {env:.3e}", flush=True)
+    assert err < max(TOL, 4 * env)
+
+
+def test_cg_converges_and_true_residual(firm):
+    """CG to tol on a kernel from the oracle: the reported true residual is the oracle's."""
+    N, M = 16, 40
+    R, _, _, _ = small_geometry(N, M, 41)
+    Ker = ofirm.kernel_direct(N, R).real
+    plan = firm.Plan(N, R, refine_every=7)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    rng = np.random.default_rng(5)
+    atb = rng.standard_normal((N, N, N))
+    lam = 1e-1 * float(Ker[N - 1, N - 1, N - 1])
+    x, rep = plan.cg_solve(dev(atb), lam, 1e-5, 500)
+    assert rep["status"] == 0 and rep["true_rel_res"] <= 1e-5
+    xr = host(x)
+    res = atb - (ofirm.toeplitz_apply_fft(Ker, xr).real + lam * xr)
+    tr = np.linalg.norm(res) / np.linalg.norm(atb)
+    assert tr <= 1.5e-5
+    assert abs(tr - rep["true_rel_res"]) <= 1e-6
+
+
+@pytest.mark.parametrize("N", [8, 16, 32])
+def test_precond_apply_matches_oracle(firm, N):
+    """z = F^{-1}(d . F r) on the periodic N^3 grid (eq. circ1) vs the oracle with numpy FFTs."""
+    rng = np.random.default_rng(60 + N)
+    R, _, _, _ = small_geometry(N, 1, 1)
+    plan = firm.Plan(N, R)
+    d = rng.uniform(0.5, 2.0, (N, N, N))
+    # make d even in centred order: d(q) = d(-q)
+    ds = np.fft.ifftshift(d)
+    ds = 0.5 * (ds + np.roll(ds[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+    d = np.fft.fftshift(ds)
+    r = rng.standard_normal((N, N, N))
+    z = host(plan.precond_apply(dev(d), dev(r)))
+    ref = ofirm.fourier_diagonal_precond(d)(r)
+    assert rel(z, ref) < TOL
+
+
+def test_pcg_unit_diagonal_equals_cg(firm):
+    """d = 1 gives the plain CG iterates (GPU against GPU and against the oracle's CG), on a
+    system well enough conditioned (lambda = 0.1 Ker(0)) that FP32 rounding stays below 1e-5."""
+    N, M = 16, 30
+    R, _, _, _ = small_geometry(N, M, 71)
+    Ker = ofirm.kernel_direct(N, R).real
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    atb = dev(np.random.default_rng(8).standard_normal((N, N, N)))
+    lam = 0.1 * float(Ker[N - 1, N - 1, N - 1])
+    x1, _ = plan.cg_solve(atb, lam, 0.0, 12)
+    x2, rep2 = plan.cg_solve(atb, lam, 0.0, 12, precond=torch.ones((N, N, N), device="cuda"))
+    assert rep2["iters"] == 12 and rep2["fell_back"] == 0
+    assert rel(host(x2), host(x1)) < TOL
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + lam * v
+    assert rel(host(x1), ofirm.cg(apply, host(atb), iters=12)) < TOL
+
+
+def test_pcg_chan_diagonal_reduces_iterations(firm):
+    """PCG with the inverse of T. Chan's optimal circulant (computed by the oracle) reaches the
+    tolerance in fewer iterations than CG; FP64 refinement (precision 1) brings both to a true
+    residual of 1e-6 that the oracle confirms."""
+    N, M = 16, 60
+    R, _, _, _ = small_geometry(N, M, 81)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 1e-3 * float(Ker[N - 1, N - 1, N - 1])
+    spec = ofirm.chan_circulant_spectrum(Ker, N, lam)
+    d = 1.0 / np.maximum(spec, lam)
+    plan = firm.Plan(N, R, precision=1)
+    K32 = ker_to_centred(Ker, N).astype(np.float32)
+    plan.kernel_set(dev(K32))
+    b = np.random.default_rng(9).standard_normal((N, N, N))
+    atb = dev(b)
+    x1, r1 = plan.cg_solve(atb, lam, 1e-6, 5000)
+    x2, r2 = plan.cg_solve(atb, lam, 1e-6, 5000, precond=dev(d))
+    print("cg", r1, "pcg", r2, flush=True)
+    assert r1["status"] == 0 and r2["status"] == 0
+    assert r2["iters"] < r1["iters"]
+    Kf = K32[1:, 1:, 1:].astype(np.float64)
+    b32 = b.astype(np.float32).astype(np.float64)
+    for x in (x1, x2):
+        xr = host(x)
+        res = b32 - (ofirm.toeplitz_apply_fft(Kf, xr).real + lam * xr)
+        assert np.linalg.norm(res) / np.linalg.norm(b32) < 2e-6
+
+
+def test_apply_fp64_matches_oracle(firm):
+    """The FP64 product equals the oracle's Toeplitz product with the same FP32 kernel values
+    to FP64 rounding."""
+    N = 16
+    rng = np.random.default_rng(12)
+    R, _, _, _ = small_geometry(N, 2, 3)
+    plan = firm.Plan(N, R)
+    K32 = ker_to_centred(even_random_kernel(N, rng), N).astype(np.float32)
+    plan.kernel_set(dev(K32))
+    x = rng.standard_normal((N, N, N))
+    y = host(plan.apply_AtA_f64(dev(x, torch.float64), 0.5))
+    ref = ofirm.toeplitz_apply_fft(K32[1:, 1:, 1:].astype(np.float64), x).real + 0.5 * x
+    assert rel(y, ref) < 1e-12
+
+
+def test_lambda_relative_reading(firm):
+    """lambda_relative = 1 multiplies lambda by Ker(0) = sum of h^2."""
+    N, M = 8, 10
+    R, _, grp, table = small_geometry(N, M, 13, 2)
+    x = dev(np.random.default_rng(1).standard_normal((N, N, N)))
+    a = firm.Plan(N, R, ctf_group=grp, ctf_table=table, lambda_relative=1)
+    b = firm.Plan(N, R, ctf_group=grp, ctf_table=table)
+    a.kernel_precompute()
+    b.kernel_precompute()
+    k0 = float(ofirm.ctf_weights(N, M, grp, table).__pow__(2).sum())
+    ya = host(a.apply_AtA(x, 0.01))
+    yb = host(b.apply_AtA(x, 0.01 * k0))
+    assert rel(ya, yb) < 1e-6
+
+
+def test_synth_slices_match_closed_form(firm):
+    """The GPU generator's clean slices vs the oracle's closed form (projection-slice theorem)."""
+    N, M = 16, 25
+    R, sh, grp, table = small_geometry(N, M, 91, 2, True)
+    c, s, a = synth.blob_params(N, 6, np.random.default_rng(1))
+    s[0] = 0.0
+    plan = firm.Plan(N, R, shifts=sh, ctf_group=grp, ctf_table=table)
+    got = plan.synth_slices(c, s, a, snr=float("inf"), seed=1)
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.complex128)
+    ref = odirect.blob_slices(N, R, c, s, a, grp, table, sh)
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-5
+
+
+def test_synth_noise_statistics(firm):
+    """Noise has the requested SNR and the symmetry n(-k) = conj n(k) of a real image's DFT."""
+    N, M = 16, 400
+    R, _, _, _ = small_geometry(N, M, 92)
+    c, s, a = synth.blob_params(N, 3, np.random.default_rng(2))
+    plan = firm.Plan(N, R)
+    clean = plan.synth_slices(c, s, a, snr=float("inf"), seed=5).cpu().numpy().astype(np.complex128)
+    noisy = plan.synth_slices(c, s, a, snr=0.25, seed=5).cpu().numpy().astype(np.complex128)
+    n = noisy - clean
+    assert np.allclose(n[:, ::-1], np.conj(n), atol=1e-3 * np.abs(n).max())
+    snr = np.mean(np.abs(clean) ** 2) / np.mean(np.abs(n) ** 2)
+    assert abs(snr / 0.25 - 1) < 0.05
