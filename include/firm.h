@@ -129,6 +129,13 @@ firm_status firm_backproject(firm_plan plan, const void* b_dev, float* atb_dev);
  * FIRM_ERR_STATE if no kernel exists; FIRM_ERR_ARG if lambda < 0. */
 firm_status firm_apply_AtA(firm_plan plan, const float* x_dev, float* y_dev, double lambda);
 
+/* Instrumented firm_apply_AtA: runs it reps times with HIP events between its five FFT
+ * passes on the plan stream (rows along i3 with padding; columns along i2; the fused
+ * multiply pass along i1; inverse along i2; inverse along i3 with crop and lambda x) and
+ * writes their average durations in ms to pass_ms[5] (host).  Synchronises. */
+firm_status firm_apply_AtA_timed(firm_plan plan, const float* x_dev, float* y_dev, double lambda, int reps,
+                                 float* pass_ms);
+
 /* FP64 form of firm_apply_AtA: x_dev, y_dev are N^3 doubles; the spectrum is computed in
  * FP64 from the FP32 kernel values (so it is exactly the Toeplitz product with them). */
 firm_status firm_apply_AtA_f64(firm_plan plan, const double* x_dev, double* y_dev, double lambda);

@@ -270,7 +270,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->deconv_atb, datb.size()));
     chk(dalloc(&p->tw, (size_t)FIRM_TWN));
     chk(dalloc(&p->kerc, (size_t)(N2 * N2 * N2)));
-    chk(dalloc(&p->khat, (size_t)(N2 * N2 * p->QP)));
+    chk(dalloc(&p->khat, blocked_spectrum_elems(2 * N, 2 * N, N + 1, false)));
     chk(dalloc(&p->T1, (size_t)((int64_t)N * N * p->QP)));
     chk(dalloc(&p->T2, (size_t)((int64_t)N * N2 * p->QP)));
     chk(dalloc(&p->r, (size_t)n3));
@@ -284,7 +284,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->partials3, (size_t)p->npart));
     chk(dalloc(&p->scal, 32));
     chk(dalloc(&p->flags, 8));
-    chk(dalloc(&p->dhalf, (size_t)((int64_t)N * N * p->QPn)));
+    chk(dalloc(&p->dhalf, blocked_spectrum_elems(N, N, N / 2 + 1, false)));
     chk(dalloc(&p->S1, (size_t)((int64_t)N * N * p->QPn)));
     chk(dalloc(&p->dscal, 8));
     chk(dalloc(&p->rowstart, (size_t)(N + 1)));
@@ -369,7 +369,7 @@ firm_status ensure_fp64(firm_plan p) {
     auto al = [&](auto** ptr, size_t count) {
         if (e == hipSuccess && *ptr == nullptr) e = hipMalloc((void**)ptr, count * sizeof(**ptr));
     };
-    al(&p->khat64, N2 * N2 * p->QP);
+    al(&p->khat64, blocked_spectrum_elems(2 * N, 2 * N, N + 1, true));
     al(&p->T1d, N * N * p->QP);
     al(&p->T2d, N * N2 * p->QP);
     al(&p->tw64, (size_t)FIRM_TWN);
@@ -446,9 +446,7 @@ firm_status firm_kernel_set(firm_plan p, const float* ker) {
 firm_status firm_kernel_spectrum(firm_plan p, float* khat) {
     if (!p || !khat) return firm_fail(p, FIRM_ERR_ARG, "null argument");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
-    const size_t N = p->N, N2 = 2 * N;
-    FIRM_HIP(p, hipMemcpy2DAsync(khat, (N + 1) * sizeof(float), p->khat, p->QP * sizeof(float),
-                                 (N + 1) * sizeof(float), N2 * N2, hipMemcpyDeviceToDevice, p->stream));
+    FIRM_HIP(p, fft_khat_unblock(p, khat));
     return FIRM_OK;
 }
 
@@ -473,6 +471,32 @@ firm_status firm_apply_AtA(firm_plan p, const float* x, float* y, double lambda)
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
     FIRM_HIP(p, fft_apply_AtA(p, x, y, (float)lambda_eff(p, lambda)));
+    return FIRM_OK;
+}
+
+firm_status firm_apply_AtA_timed(firm_plan p, const float* x, float* y, double lambda, int reps,
+                                 float* pass_ms) {
+    if (!p || !x || !y || !pass_ms) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (x == y) return firm_fail(p, FIRM_ERR_ARG, "x and y must not alias");
+    if (reps < 1) return firm_fail(p, FIRM_ERR_ARG, "reps must be >= 1");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
+    hipEvent_t ev[6];
+    for (int i = 0; i < 6; ++i) FIRM_HIP(p, hipEventCreate(&ev[i]));
+    double acc[5] = {0, 0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+        e = fft_apply_AtA_events(p, x, y, (float)lambda_eff(p, lambda), ev);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+        for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            acc[i] += ms;
+        }
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("timed apply: ") + hipGetErrorString(e));
+    for (int i = 0; i < 5; ++i) pass_ms[i] = (float)(acc[i] / reps);
     return FIRM_OK;
 }
 

@@ -163,9 +163,11 @@ __global__ void k_set_active(int* flags, double* scal, int restart_dir) {
     if (restart_dir) scal[S_BETA] = 0.0;
 }
 
-// d (centred order) -> dhalf[j1][j2][j3] = (d(q) + d(-q)) / (2 N^3), FFT order, j3 <= N/2
-__global__ void k_precond_set(const float* __restrict__ d, float* __restrict__ dh, int N, int QPn) {
+// d (centred order) -> dhalf = (d(q) + d(-q)) / (2 N^3) in FFT order for q3 in [0, N/2], in the
+// blocked layout [q2][q3 group][q1][C] read by the preconditioner's middle pass.
+__global__ void k_precond_set(const float* __restrict__ d, float* __restrict__ dh, int N, int C) {
     const int H = N / 2 + 1;
+    const int ng = (H + C - 1) / C;
     const int64_t tot = (int64_t)N * N * H;
     const double inv = 1.0 / ((double)N * N * N);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < tot; i += (int64_t)gridDim.x * blockDim.x) {
@@ -174,7 +176,7 @@ __global__ void k_precond_set(const float* __restrict__ d, float* __restrict__ d
         const int m1 = (N - j1) % N, m2 = (N - j2) % N, m3 = (N - j3) % N;
         const int e1 = (m1 + N / 2) % N, e2 = (m2 + N / 2) % N, e3 = (m3 + N / 2) % N;
         const double v = 0.5 * ((double)d[((int64_t)c1 * N + c2) * N + c3] + (double)d[((int64_t)e1 * N + e2) * N + e3]);
-        dh[((int64_t)j1 * N + j2) * QPn + j3] = (float)(v * inv);
+        dh[(((int64_t)j2 * ng + j3 / C) * N + j1) * C + j3 % C] = (float)(v * inv);
     }
 }
 
@@ -190,7 +192,8 @@ hipError_t precond_set(firm_plan p, const float* d_centred) {
     const int N = p->N;
     const int64_t n = (int64_t)N * N * (N / 2 + 1);
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_precond_set, dim3(blocks), dim3(256), 0, p->stream, d_centred, p->dhalf, N, p->QPn);
+    hipLaunchKernelGGL(k_precond_set, dim3(blocks), dim3(256), 0, p->stream, d_centred, p->dhalf, N,
+                       fft_cols_per_block(N, false));
     return hipGetLastError();
 }
 

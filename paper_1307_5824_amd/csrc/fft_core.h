@@ -1,9 +1,5 @@
-// Batched 1D FFTs of power-of-two length L (8..1024) on pencils staged in LDS.
-//
-// A workgroup holds C pencils in LDS as buf[e * (C + 1) + c] (element e of
-// pencil c; the +1 pitch keeps strided rows off one bank).  It runs C * L / 8
-// threads; thread t owns pencil c = t % C and butterfly row j = t / C, and
-// keeps up to 8 complex values in registers per stage.
+// Batched 1D FFTs of power-of-two length L (8..1024); a workgroup transforms C
+// pencils with C * L / 8 threads, 8 complex values per thread.
 //
 // The transform is a self-sorting (Stockham) decomposition of the DFT
 // X_k = sum_n x_n exp(sg * 2 pi i k n / L) into radix-8 stages with one final
@@ -85,62 +81,107 @@ struct DftSmall<8, V> {
     }
 };
 
-template <int L, int C, int R, int NS, class V>
-__device__ __forceinline__ void fft_stage(V* buf, const V* __restrict__ tw, typename CxT<V>::S sg, int c, int j) {
-    constexpr int NB = 8 / R;
-    constexpr int CP = C + 1;
-    V v[8];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int u = j + b * (L / 8);
-#pragma unroll
-        for (int s = 0; s < R; ++s) v[b * R + s] = buf[(u + s * (L / R)) * CP + c];
+// ---------------------------------------------------------------------------
+// Register-resident transform.  Thread (c, j), j in [0, L/8), holds in v[t] the
+// element e = j + t L/8 of pencil c.  Every Stockham stage reads exactly these
+// elements: butterfly b (of 8/R per thread) of radix R takes u = j + b L/8 and its
+// inputs u + s L/R, i.e. slot t = b + s (8/R).  Intermediate outputs go to LDS at
+// their self-sorting positions and are read back in the same slot pattern; the
+// last stage leaves X[j + t L/8] in v[t] (natural order), so global loads and
+// stores need no LDS staging.
+//
+// Layouts of the exchange buffer: JF (lanes run along j, for contiguous rows)
+// keeps pencils apart, element e of pencil c at c (L + L/8) + e + e/8; otherwise
+// (lanes run along c, for strided columns) element-major at e (C + 1) + c.
+template <int L, int C, bool JF>
+struct Pen {
+    static constexpr int T = L / 8;                        // threads per pencil
+    static constexpr int NT = C * T;                       // threads per workgroup
+    static constexpr int LDS = JF ? C * (L + L / 8) : L * (C + 1);
+    static __device__ __forceinline__ int c() { return JF ? (int)threadIdx.x / T : (int)threadIdx.x % C; }
+    static __device__ __forceinline__ int j() { return JF ? (int)threadIdx.x % T : (int)threadIdx.x / C; }
+    static __device__ __forceinline__ int idx(int e, int cc) {
+        return JF ? cc * (L + L / 8) + e + (e >> 3) : e * (C + 1) + cc;
     }
-    __syncthreads();
+};
+
+template <int L, int C, bool JF, int R, int NS, class V>
+__device__ __forceinline__ void reg_stage(V (&v)[8], V* lds, const V* __restrict__ tw, typename CxT<V>::S sg,
+                                          int c, int j) {
+    using P = Pen<L, C, JF>;
+    constexpr int NB = 8 / R;
+    constexpr bool FIRST = (NS == 1);
+    constexpr bool LAST = (NS * R == L);
+    if (!FIRST) {  // gather this stage's inputs (written by the previous stage)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = lds[P::idx(j + t * (L / 8), c)];
+    }
+    V y[8];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         const int u = j + b * (L / 8);
         const int k = u & (NS - 1);
+        V w[R];
+#pragma unroll
+        for (int s = 0; s < R; ++s) w[s] = v[b + s * NB];
         if (NS > 1) {
 #pragma unroll
             for (int s = 1; s < R; ++s) {
-                V w = tw[(s * k) * (FIRM_TWN / (NS * R))];
-                w.y *= -sg;  // table holds exp(-2 pi i m / T); sg = -1 keeps it, sg = +1 conjugates
-                v[b * R + s] = c_mul(v[b * R + s], w);
+                V t = tw[(s * k) * (FIRM_TWN / (NS * R))];
+                t.y *= -sg;  // table holds exp(-2 pi i m / T); sg = +1 conjugates
+                w[s] = c_mul(w[s], t);
             }
         }
-        DftSmall<R, V>::run(&v[b * R], sg);
-        const int base = (u - k) * R + k;
+        DftSmall<R, V>::run(w, sg);
 #pragma unroll
-        for (int s = 0; s < R; ++s) buf[(base + s * NS) * CP + c] = v[b * R + s];
+        for (int s = 0; s < R; ++s) y[b + s * NB] = w[s];
     }
-    __syncthreads();
+    if (LAST) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = y[t];
+    } else {
+        __syncthreads();  // every thread has read the buffer's previous contents
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int u = j + b * (L / 8);
+            const int k = u & (NS - 1);
+#pragma unroll
+            for (int s = 0; s < R; ++s) lds[P::idx((u - k) * R + k + s * NS, c)] = y[b + s * NB];
+        }
+        __syncthreads();
+    }
 }
 
-template <int L, int C, int NS, class V>
-__device__ __forceinline__ void fft_stages(V* buf, const V* __restrict__ tw, typename CxT<V>::S sg, int c, int j) {
+constexpr int first_radix(int L) {
+    int r = L;
+    while (r > 8) r /= 8;
+    return r;
+}
+
+template <int L, int C, bool JF, int NS, class V>
+__device__ __forceinline__ void reg_stages(V (&v)[8], V* lds, const V* __restrict__ tw, typename CxT<V>::S sg,
+                                           int c, int j) {
     if constexpr (NS < L) {
-        constexpr int REM = L / NS;
-        constexpr int R = REM >= 8 ? 8 : REM;
-        fft_stage<L, C, R, NS, V>(buf, tw, sg, c, j);
-        fft_stages<L, C, NS * R, V>(buf, tw, sg, c, j);
+        // the radix-2 or radix-4 stage (lengths not a power of 8) goes first
+        constexpr int R = NS == 1 ? first_radix(L) : 8;
+        reg_stage<L, C, JF, R, NS, V>(v, lds, tw, sg, c, j);
+        reg_stages<L, C, JF, NS * R, V>(v, lds, tw, sg, c, j);
     }
 }
 
-// In-place transform of the C pencils in buf; must be entered after a barrier
-// that publishes buf, and leaves after one.
-template <int L, int C, class V>
-__device__ __forceinline__ void fft_lds(V* buf, const V* __restrict__ tw, typename CxT<V>::S sg) {
-    const int t = threadIdx.x;
-    fft_stages<L, C, 1, V>(buf, tw, sg, t % C, t / C);
+// In-register transform of the thread's 8 slots (see above).  The exchange buffer may
+// hold anything on entry; it is free again after the call returns (no pending reads).
+template <int L, int C, bool JF, class V>
+__device__ __forceinline__ void fft_reg(V (&v)[8], V* lds, const V* __restrict__ tw, typename CxT<V>::S sg) {
+    using P = Pen<L, C, JF>;
+    reg_stages<L, C, JF, 1, V>(v, lds, tw, sg, P::c(), P::j());
 }
 
 // pencils per workgroup for each length (threads = C * L / 8)
 template <int L, class V = float2>
 struct FftCfg {
     static constexpr bool DBL = sizeof(V) == 16;
-    static constexpr int C = DBL ? (L >= 256 ? 8 : (L >= 128 ? 16 : 2048 / L))
+    static constexpr int C = DBL ? (L >= 1024 ? 4 : (L >= 256 ? 8 : (L >= 128 ? 16 : 2048 / L)))
                                  : (L >= 1024 ? 8 : (L >= 128 ? 16 : 2048 / L));
     static constexpr int THREADS = C * L / 8;
-    static constexpr int CP = C + 1;
 };

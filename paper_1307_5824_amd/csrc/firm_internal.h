@@ -42,7 +42,7 @@ struct firm_plan_s {
     // kernel and its spectrum (device)
     bool have_kernel = false;
     float* kerc = nullptr;     // (2N)^3 Ker in circulant order c[p1][p2][p3]
-    float* khat = nullptr;     // [2N][2N][QP] real spectrum, q3 in [0, N]
+    float* khat = nullptr;     // real spectrum, q3 in [0, N], blocked as [q2][q3 group][q1][C]
 
     // apply workspaces
     float2* T1 = nullptr;      // [N][N][QP]
@@ -50,7 +50,7 @@ struct firm_plan_s {
 
     // FP64 product (allocated on first use): spectrum, workspaces, twiddles, vectors
     bool khat64_valid = false;
-    double* khat64 = nullptr;  // [2N][2N][QP]
+    double* khat64 = nullptr;  // blocked like khat (double-precision pencil width)
     double2* T1d = nullptr;
     double2* T2d = nullptr;
     double2* tw64 = nullptr;
@@ -63,7 +63,7 @@ struct firm_plan_s {
     int npart = 0;
     double* scal = nullptr;      // device scalars (see cg.hip)
     double* host_scal = nullptr; // pinned host mirror
-    float* dhalf = nullptr;      // preconditioner diagonal, [N][N][QPn] in FFT order
+    float* dhalf = nullptr;      // preconditioner diagonal / N^3, FFT order, blocked [q2][q3 group][q1][C]
     float2* S1 = nullptr;        // PCG FFT workspace [N][N][QPn]
     int QPn = 0;
 
@@ -92,6 +92,10 @@ firm_status firm_fail(firm_plan p, firm_status s, const std::string& msg);
 
 // ---- fft.hip launchers (return hipError_t of the launch) ----
 hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam);
+int fft_cols_per_block(int L, bool dbl);  // pencils per workgroup of the L-point pass
+size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl);
+hipError_t fft_khat_unblock(firm_plan p, float* out);
+hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev);
 hipError_t fft_khat_from_kerc(firm_plan p, float2* w1);        // kerc -> khat (w1: [2N][2N][QP])
 hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, float* chalf);
 hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2, float* atb,

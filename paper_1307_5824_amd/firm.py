@@ -62,6 +62,7 @@ def _load():
         "firm_backproject": (i, [vp, vp, vp]),
         "firm_apply_AtA": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_f64": (i, [vp, vp, vp, d]),
+        "firm_apply_AtA_timed": (i, [vp, vp, vp, d, i, vp]),
         "firm_cg_solve": (i, [vp, vp, vp, d, d, i, vp, ctypes.POINTER(FirmCgReport)]),
         "firm_precond_apply": (i, [vp, vp, vp, vp]),
         "firm_synth_slices": (i, [vp, i, vp, vp, vp, d, ctypes.c_uint64, vp]),
@@ -207,6 +208,14 @@ class Plan:
         self._req(out, self.N ** 3, self._torch.float32)
         _check(lib.firm_apply_AtA(self.h, _ptr(x), _ptr(out), float(lam)), self.h)
         return out
+
+    def apply_AtA_timed(self, x, lam, reps, out=None):
+        """Average ms of the five FFT passes of the product over reps runs."""
+        self._req(x, self.N ** 3, self._torch.float32)
+        out = self._vol(out)
+        ms = (ctypes.c_float * 5)()
+        _check(lib.firm_apply_AtA_timed(self.h, _ptr(x), _ptr(out), float(lam), int(reps), ms), self.h)
+        return [float(v) for v in ms]
 
     def apply_AtA_f64(self, x, lam, out=None):
         self._req(x, self.N ** 3, self._torch.float64)
