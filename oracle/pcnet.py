@@ -1,0 +1,217 @@
+"""FP64 oracle of the learned Fourier-diagonal preconditioner (test infrastructure only).
+
+The preconditioner is P r = F^{-1}(d . F r) on the periodic N^3 grid (a circulant operator,
+diagonal in the Fourier basis: section 2.3, eq. circ1), with d > 0 and d(q) = d(-q) so that P
+is real, symmetric and positive definite.  d comes from a small network:
+
+  features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32)
+  network   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))            (3^3 convolutions,
+            circular padding, channels 1 -> C -> C -> C -> 1)
+  symmetric s(u) = (o(u) + o(-u)) / 2 on the centred G^3 frequency grid
+  diagonal  d(q) = exp(U s (q)) / Ker(0),  U = periodic trilinear interpolation from the
+            G^3 grid to the N^3 frequency grid (q -> coarse coordinate q G / N)
+
+Training minimises the probe loss E_z ||P (A*A + lambda) z - z||^2 / E ||z||^2.  With
+u = (A*A + lambda) z and Parseval, for a fixed set of probes it is a per-frequency quadratic
+in d:  L(d) = sum_q (d^2 A(q) - 2 d B(q) + C(q)) / sum_q C(q), with A = sum |u^|^2,
+B = sum Re(conj(u^) z^), C = sum |z^|^2 over the probes (u^, z^ the unnormalised DFTs;
+the 1/N^3 of Parseval cancels in the ratio).
+
+Every gradient here is hand-written and pinned by central finite differences.
+"""
+import numpy as np
+
+G = 32
+
+
+# ----------------------------------------------------------------- conv layers --
+
+def conv3d(x, w, b):
+    """y[co] = b[co] + sum_ci sum_{a in {-1,0,1}^3} w[co, ci, a + 1] x[ci, i + a] (periodic).
+    x (Cin, D, D, D), w (Cout, Cin, 3, 3, 3), b (Cout,)."""
+    cout = w.shape[0]
+    D = x.shape[1:]
+    y = np.empty((cout,) + D)
+    for co in range(cout):
+        y[co] = b[co]
+    for a in range(3):
+        for bb in range(3):
+            for c in range(3):
+                xs = np.roll(x, shift=(-(a - 1), -(bb - 1), -(c - 1)), axis=(1, 2, 3))   # xs[i] = x[i + off]
+                y += np.tensordot(w[:, :, a, bb, c], xs, axes=([1], [0]))
+    return y
+
+
+def conv3d_backward(x, w, dy):
+    """Gradients of conv3d: dx[ci, i] = sum_co sum_off w[co, ci, off] dy[co, i - off],
+    dw[co, ci, off] = sum_i dy[co, i] x[ci, i + off], db[co] = sum_i dy[co, i]."""
+    dx = np.zeros_like(x)
+    dw = np.zeros_like(w)
+    for a in range(3):
+        for bb in range(3):
+            for c in range(3):
+                off = (a - 1, bb - 1, c - 1)
+                xs = np.roll(x, shift=(-off[0], -off[1], -off[2]), axis=(1, 2, 3))
+                dw[:, :, a, bb, c] = np.tensordot(dy, xs, axes=([1, 2, 3], [1, 2, 3]))
+                t = np.tensordot(w[:, :, a, bb, c], dy, axes=([0], [0]))          # (Cin, D, D, D)
+                dx += np.roll(t, shift=off, axis=(1, 2, 3))                        # t[i - off]
+    db = dy.sum(axis=(1, 2, 3))
+    return dx, dw, db
+
+
+def init_params(C=32, seed=0, zero_last=True):
+    """He-scaled random weights; the last layer starts at zero so the untrained network is the
+    analytic diagonal d = 1 / (pooled |K^| + lambda)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(C, 1), (C, C), (C, C), (1, C)]
+    params = []
+    for i, (co, ci) in enumerate(shapes):
+        std = np.sqrt(2.0 / (ci * 27))
+        w = rng.standard_normal((co, ci, 3, 3, 3)) * std
+        if zero_last and i == 3:
+            w[:] = 0.0
+        params.append((w, np.zeros(co)))
+    return params
+
+
+def net_forward(f, params):
+    """o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))); returns o and the cache for backward."""
+    x0 = f[None]
+    h = x0
+    cache = []
+    for i, (w, b) in enumerate(params):
+        z = conv3d(h, w, b)
+        cache.append((h, z))
+        h = np.maximum(z, 0.0) if i < len(params) - 1 else z
+    return -f + h[0], cache
+
+
+def net_backward(do, params, cache):
+    """Gradients of sum(do * o) with respect to the parameters (and the input features)."""
+    grads = [None] * len(params)
+    g = do[None]
+    for i in range(len(params) - 1, -1, -1):
+        h, z = cache[i]
+        if i < len(params) - 1:
+            g = g * (z > 0)
+        dx, dw, db = conv3d_backward(h, params[i][0], g)
+        grads[i] = (dw, db)
+        g = dx
+    return grads, g[0] - do
+
+
+# ----------------------------------------------------------------- features --
+
+def pool_features(khat_full, ker0, lam_rel):
+    """f = log(mean over (2N/G)^3 blocks of |K^| / Ker(0) + lam_rel), on the centred G^3 grid.
+    khat_full: the (2N)^3 spectrum in FFT order."""
+    M2 = khat_full.shape[0]
+    k = np.fft.fftshift(np.abs(khat_full))
+    s = M2 // G
+    pooled = k.reshape(G, s, G, s, G, s).mean(axis=(1, 3, 5))
+    return np.log(pooled / ker0 + lam_rel)
+
+
+def symmetrise(o):
+    """s(u) = (o(u) + o(-u)) / 2 on the centred G^3 grid (index u + G/2)."""
+    flipped = np.roll(o[::-1, ::-1, ::-1], 1, axis=(0, 1, 2))
+    return 0.5 * (o + flipped)
+
+
+def _interp_axis(N):
+    """Per-axis periodic linear interpolation from G coarse points to N fine points (both centred):
+    fine frequency q = i - N/2 sits at coarse coordinate q G / N."""
+    q = np.arange(N) - N // 2
+    u = q * (G / N)
+    lo = np.floor(u).astype(int)
+    t = u - lo
+    i0 = (lo + G // 2) % G
+    i1 = (lo + 1 + G // 2) % G
+    return i0, i1, t
+
+
+def upsample(s, N):
+    """U s: periodic trilinear interpolation of the G^3 grid onto the N^3 frequency grid."""
+    out = s
+    for ax in range(3):
+        i0, i1, t = _interp_axis(N)
+        a = np.take(out, i0, axis=ax)
+        b = np.take(out, i1, axis=ax)
+        shape = [1, 1, 1]
+        shape[ax] = N
+        out = a * (1 - t).reshape(shape) + b * t.reshape(shape)
+    return out
+
+
+def upsample_adjoint(g, N):
+    """U^T g: the adjoint of upsample (scatter-add of the interpolation weights)."""
+    out = g
+    for ax in (2, 1, 0):
+        i0, i1, t = _interp_axis(N)
+        shape = list(out.shape)
+        shape[ax] = G
+        acc = np.zeros(shape)
+        ws = [1, 1, 1]
+        ws[ax] = N
+        a = out * (1 - t).reshape(ws)
+        b = out * t.reshape(ws)
+        for i in range(N):
+            sl = [slice(None)] * 3
+            sl[ax] = i
+            dst0 = [slice(None)] * 3
+            dst0[ax] = i0[i]
+            dst1 = [slice(None)] * 3
+            dst1[ax] = i1[i]
+            acc[tuple(dst0)] += a[tuple(sl)]
+            acc[tuple(dst1)] += b[tuple(sl)]
+        out = acc
+    return out
+
+
+def diagonal(o, N, ker0):
+    """d on the centred N^3 grid from the raw network output o."""
+    return np.exp(upsample(symmetrise(o), N)) / ker0
+
+
+# ----------------------------------------------------------------- probe loss --
+
+def probe_statistics(apply, N, probes):
+    """A, B, C on the centred N^3 grid for the given real probes z (P, N, N, N) and
+    u = apply(z): A = sum |u^|^2, B = sum Re(conj(u^) z^), C = sum |z^|^2 (unnormalised DFT)."""
+    A = np.zeros((N, N, N))
+    B = np.zeros((N, N, N))
+    C = np.zeros((N, N, N))
+    for z in probes:
+        u = apply(z)
+        zh = np.fft.fftshift(np.fft.fftn(z))
+        uh = np.fft.fftshift(np.fft.fftn(u))
+        A += np.abs(uh) ** 2
+        B += np.real(np.conj(uh) * zh)
+        C += np.abs(zh) ** 2
+    return A, B, C
+
+
+def probe_loss(d, A, B, C):
+    """L(d) = sum (d^2 A - 2 d B + C) / sum C = E ||P u - z||^2 / E ||z||^2 (Parseval)."""
+    return float(np.sum(d * d * A - 2 * d * B + C) / np.sum(C))
+
+
+def probe_loss_grad_d(d, A, B, C):
+    return (2 * d * A - 2 * B) / np.sum(C)
+
+
+def loss_and_grads(f, params, N, ker0, A, B, C):
+    """Loss of the network on one sample and the gradients of every parameter."""
+    o, cache = net_forward(f, params)
+    d = diagonal(o, N, ker0)
+    L = probe_loss(d, A, B, C)
+    gd = probe_loss_grad_d(d, A, B, C)
+    gs = upsample_adjoint(gd * d, N)            # through exp and U
+    go = symmetrise(gs)                          # symmetrise is self-adjoint
+    grads, _ = net_backward(go, params, cache)
+    return L, grads, d
+
+
+def precond_apply(d, r):
+    """z = F^{-1}(d . F r), d on the centred grid."""
+    return np.fft.ifftn(np.fft.ifftshift(d) * np.fft.fftn(r)).real

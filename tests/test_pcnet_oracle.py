@@ -1,0 +1,144 @@
+"""Pins of the preconditioner-network oracle: convolution by its definition written as loops,
+identity filters, adjoints, Parseval, and central finite differences for every gradient."""
+import numpy as np
+
+from oracle import firm as ofirm
+from oracle import pcnet
+
+
+def _rng(s):
+    return np.random.default_rng(s)
+
+
+def test_conv3d_matches_loop_definition():
+    """Cross-correlation with periodic padding, written as explicit loops on a 4^3 grid."""
+    rng = _rng(1)
+    D, ci, co = 4, 2, 3
+    x = rng.standard_normal((ci, D, D, D))
+    w = rng.standard_normal((co, ci, 3, 3, 3))
+    b = rng.standard_normal(co)
+    y = pcnet.conv3d(x, w, b)
+    for o in range(co):
+        for i in range(D):
+            for j in range(D):
+                for k in range(D):
+                    s = b[o]
+                    for c in range(ci):
+                        for a in range(3):
+                            for bb in range(3):
+                                for cc in range(3):
+                                    s += w[o, c, a, bb, cc] * x[c, (i + a - 1) % D, (j + bb - 1) % D, (k + cc - 1) % D]
+                    assert abs(s - y[o, i, j, k]) < 1e-12
+
+
+def test_conv3d_identity_filter():
+    rng = _rng(2)
+    x = rng.standard_normal((3, 5, 5, 5))
+    w = np.zeros((3, 3, 3, 3, 3))
+    for c in range(3):
+        w[c, c, 1, 1, 1] = 1.0
+    assert np.allclose(pcnet.conv3d(x, w, np.zeros(3)), x)
+
+
+def test_conv3d_backward_finite_differences():
+    rng = _rng(3)
+    D, ci, co = 4, 2, 3
+    x = rng.standard_normal((ci, D, D, D))
+    w = rng.standard_normal((co, ci, 3, 3, 3))
+    b = rng.standard_normal(co)
+    dy = rng.standard_normal((co, D, D, D))
+    dx, dw, db = pcnet.conv3d_backward(x, w, dy)
+    f = lambda x_, w_, b_: float(np.sum(dy * pcnet.conv3d(x_, w_, b_)))  # noqa: E731
+    h = 1e-6
+    for idx in [(0, 1, 2, 3), (1, 0, 0, 0)]:
+        e = np.zeros_like(x); e[idx] = h
+        assert abs((f(x + e, w, b) - f(x - e, w, b)) / (2 * h) - dx[idx]) < 1e-6 * (1 + abs(dx[idx]))
+    for idx in [(2, 1, 0, 2, 1), (0, 0, 1, 1, 1)]:
+        e = np.zeros_like(w); e[idx] = h
+        assert abs((f(x, w + e, b) - f(x, w - e, b)) / (2 * h) - dw[idx]) < 1e-6 * (1 + abs(dw[idx]))
+    e = np.zeros_like(b); e[1] = h
+    assert abs((f(x, w, b + e) - f(x, w, b - e)) / (2 * h) - db[1]) < 1e-6 * (1 + abs(db[1]))
+
+
+def test_upsample_properties():
+    rng = _rng(4)
+    G = pcnet.G
+    s = rng.standard_normal((G, G, G))
+    assert np.allclose(pcnet.upsample(s, G), s)                         # N = G samples the grid
+    assert np.allclose(pcnet.upsample(np.full((G, G, G), 2.5), 64), 2.5)
+    g = rng.standard_normal((16, 16, 16))
+    lhs = np.sum(pcnet.upsample(s, 16) * g)
+    rhs = np.sum(s * pcnet.upsample_adjoint(g, 16))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    ss = pcnet.symmetrise(s)
+    assert np.allclose(ss, np.roll(ss[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+    assert np.allclose(pcnet.symmetrise(ss), ss)
+    up = pcnet.upsample(ss, 16)                                           # symmetric stays symmetric
+    assert np.allclose(up, np.roll(up[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+
+
+def test_probe_loss_is_parseval_of_the_residual():
+    """sum (d^2 A - 2 d B + C) / sum C equals sum ||P u - z||^2 / sum ||z||^2 computed in real space."""
+    rng = _rng(5)
+    N = 8
+    R = np.stack([np.eye(3)])
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 3.0
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + lam * v
+    probes = rng.standard_normal((3, N, N, N))
+    A, B, C = pcnet.probe_statistics(apply, N, probes)
+    d = rng.uniform(0.01, 0.1, (N, N, N))
+    d = 0.5 * (d + np.roll(d[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+    num = sum(np.sum((pcnet.precond_apply(d, apply(z)) - z) ** 2) for z in probes)
+    den = sum(np.sum(z ** 2) for z in probes)
+    assert abs(pcnet.probe_loss(d, A, B, C) - num / den) < 1e-10 * (num / den)
+
+
+def test_full_chain_gradients_finite_differences():
+    """Loss through network, symmetrisation, upsampling, exp and the probe quadratic: central
+    differences on a few parameters of every layer."""
+    rng = _rng(6)
+    N, C = 8, 2
+    G = pcnet.G
+    params = pcnet.init_params(C, seed=1, zero_last=False)
+    params = [(w * 0.3, b + 0.01 * rng.standard_normal(b.shape)) for w, b in params]
+    f = 0.2 * rng.standard_normal((G, G, G))
+    A = rng.uniform(0.5, 2.0, (N, N, N))
+    B = rng.uniform(0.1, 0.5, (N, N, N))
+    Cs = rng.uniform(0.5, 1.0, (N, N, N))
+    ker0 = 3.0
+    L, grads, _ = pcnet.loss_and_grads(f, params, N, ker0, A, B, Cs)
+    # a step of 1e-6 stays clear of the ReLU kinks (a few dozen pre-activations lie within 1e-4
+    # of zero); FP64 round-off then limits the agreement to ~1e-5 relative
+    h = 1e-6
+    for layer, idx in [(0, (1, 0, 0, 1, 2)), (1, (0, 1, 2, 2, 0)), (2, (1, 1, 1, 1, 1)), (3, (0, 1, 0, 0, 0))]:
+        w, b = params[layer]
+        wp = [list(p) for p in params]
+        wp[layer][0] = w.copy(); wp[layer][0][idx] += h
+        lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+        wp[layer][0] = w.copy(); wp[layer][0][idx] -= h
+        lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 1e-12, (layer, fd, grads[layer][0][idx])
+    wp = [list(p) for p in params]
+    b3 = params[3][1]
+    wp[3][1] = b3 + h
+    lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+    wp[3][1] = b3 - h
+    lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+    assert abs((lp - lm) / (2 * h) - grads[3][1][0]) <= 5e-5 * abs(grads[3][1][0]) + 1e-12
+
+
+def test_untrained_network_is_inverse_pooled_spectrum():
+    """With the last layer at zero, d = 1 / (pooled |K^| + lambda Ker(0)) up to interpolation."""
+    rng = _rng(7)
+    G = pcnet.G
+    params = pcnet.init_params(4, seed=2)
+    f = rng.standard_normal((G, G, G))
+    f = pcnet.symmetrise(f)
+    o, _ = pcnet.net_forward(f, params)
+    assert np.allclose(o, -f)
+    d = pcnet.diagonal(o, G, 2.0)
+    assert np.allclose(d, np.exp(-f) / 2.0)
