@@ -82,7 +82,8 @@ typedef struct {
     int fell_back;        /* 1 if a preconditioned solve restarted as plain CG */
     int status;           /* firm_status of the solve */
     double rel_res;       /* residual / ||A*b|| that stopped the solver */
-    double true_rel_res;  /* ||A*b - (A*A + lambda) x|| / ||A*b|| at exit with the FP64 product */
+    double true_rel_res;  /* ||A*b - (A*A + lambda) x|| / ||A*b|| with the FP64 product, for the x
+                             written out (FP32 x in firm_cg_solve, FP64 x in firm_cg_solve_f64) */
     double t_ms;          /* wall time of the solve in ms */
 } firm_cg_report;
 
@@ -142,6 +143,9 @@ firm_status firm_apply_AtA_f64(firm_plan plan, const double* x_dev, double* y_de
 
 /* Step 4 (section 3.3-3.4): CG on (A*A + lambda I) x = atb from the initial guess in
  * x_dev (pass zeros for the paper's x0 = 0), in the arithmetic of firm_options.precision.
+ * atb_dev, x_dev: N^3 floats (device); x is FP32 on return in every mode, so with
+ * precision 1 or 2 its residual can exceed the FP64 iterate's by the rounding of x
+ * (about 6e-8 times the condition number): rep->true_rel_res is that of the FP32 x.
  * Precision 0 stops when the residual measured with the FP32 product is <= tol ||atb||
  * (a recursive residual below tol is confirmed by a recomputed one); precision 1 and 2
  * stop on the FP64 residual.  max_iter bounds the CG iterations.  precond_d_dev: NULL for plain CG, else a Fourier diagonal d
@@ -152,6 +156,14 @@ firm_status firm_apply_AtA_f64(firm_plan plan, const double* x_dev, double* y_de
 firm_status firm_cg_solve(firm_plan plan, const float* atb_dev, float* x_dev, double lambda,
                           double tol, int max_iter, const float* precond_d_dev,
                           firm_cg_report* rep);
+
+/* firm_cg_solve with an FP64 right-hand side and solution (atb_dev, x_dev: N^3 doubles,
+ * device; x_dev holds the initial guess).  Needs precision 1 or 2 (FIRM_ERR_STATE for 0);
+ * the FP64 iterate is x itself, so residuals below the FP32 rounding of x are reachable.
+ * Precision 2 takes no preconditioner (FIRM_ERR_ARG), here and in firm_cg_solve. */
+firm_status firm_cg_solve_f64(firm_plan plan, const double* atb_dev, double* x_dev, double lambda,
+                              double tol, int max_iter, const float* precond_d_dev,
+                              firm_cg_report* rep);
 
 /* z_dev = F^{-1}(d . F r) on the periodic N^3 grid (circulant diagonalisation,
  * eq. circ1); d_dev, r_dev, z_dev: N^3 floats (d in centred frequency order). */
@@ -170,6 +182,49 @@ firm_status firm_kernel_spectrum(firm_plan plan, float* khat_dev);
  * voxel units; sigma 0 is a point source.  Noise uses Philox4x32-10 keyed by seed. */
 firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, const double* sigmas,
                               const double* amps, double snr, uint64_t seed, void* b_dev);
+
+/* ---- learned Fourier-diagonal preconditioner ----------------------------------------
+ * A 3D conv net maps f = log(|K^| pooled to 32^3 / Ker(0) + lam_rel) to a log diagonal on the
+ * 32^3 frequency grid: o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
+ * padding, 1 -> 32 -> 32 -> 32 -> 1 channels (c2, c3 on BF16 matrix cores, FP32 accumulation).
+ * d = exp(U sym(o)) / Ker(0) on the N^3 grid (sym: o(u) + o(-u) halved; U: periodic trilinear
+ * interpolation) is the diagonal of z = F^{-1}(d . F r).  Training minimises the probe loss
+ * E ||P (A*A + lambda) z - z||^2 / E ||z||^2, a per-frequency quadratic in d by Parseval. */
+typedef struct firm_pcnet_s* firm_pcnet;
+
+/* Number of network parameters; host parameter arrays hold w1 [32][1][27], b1 [32],
+ * w2 [32][32][27], b2, w3, b3, w4 [1][32][27], b4 [1] in that order (tap = 9a + 3b + c for the
+ * offset (a-1, b-1, c-1)). */
+int64_t firm_pcnet_num_params(void);
+firm_status firm_pcnet_create(firm_pcnet* out, int max_batch, void* stream);
+void firm_pcnet_destroy(firm_pcnet net);
+firm_status firm_pcnet_set_params(firm_pcnet net, const float* params_host);  /* resets Adam */
+firm_status firm_pcnet_get_params(firm_pcnet net, float* params_host);
+/* out_dev [B][32^3] = network output o for features feat_dev [B][32^3] (centred order). */
+firm_status firm_pcnet_forward(firm_pcnet net, const float* feat_dev, float* out_dev, int B);
+/* Mean probe loss of B samples at size N and (if grad_host) the parameter gradients.  A_dev,
+ * B_dev: [B][N^3] probe statistics (centred order) from firm_probe_stats; sumc, ker0: host [B]. */
+firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int B, int N, const float* A_dev,
+                                 const float* B_dev, const double* sumc, const double* ker0, double* loss,
+                                 float* grad_host);
+/* One Adam step (Kingma & Ba 2015) on the mean probe loss. */
+firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int B, int N, const float* A_dev,
+                                  const float* B_dev, const double* sumc, const double* ker0, double lr,
+                                  double* loss);
+const char* firm_pcnet_last_error(firm_pcnet net);
+
+/* Features of the plan's kernel: feat_dev [32^3] = log(mean |K^| over (2N/32)^3 blocks / Ker(0) +
+ * lam_rel), centred frequency order.  Needs N >= 16. */
+firm_status firm_kernel_features(firm_plan plan, double lam_rel, float* feat_dev);
+/* d_dev [N^3] (centred) = exp(U sym(out)) / Ker(0) from a network output out_dev [32^3]. */
+firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, float* d_dev);
+/* Probe statistics on the centred N^3 grid for nprobes real probes z (probes_dev [nprobes][N^3]):
+ * A = sum |F u|^2, B = sum Re(conj(F u) F z) with u = (A*A + lambda) z (FP32 product), and
+ * *sumc = sum ||F z||^2 (host). */
+firm_status firm_probe_stats(firm_plan plan, const float* probes_dev, int nprobes, double lambda, float* A_dev,
+                             float* B_dev, double* sumc);
+/* out_dev[i] = standard normal from Philox4x32-10 keyed by seed, counter (i, offset). */
+firm_status firm_synth_normals(firm_plan plan, uint64_t seed, uint64_t offset, int64_t n, float* out_dev);
 
 /* Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC 2011), the source of
  * the synthetic noise: out = bijection(ctr) keyed by key.  Host function, no device work. */

@@ -74,27 +74,49 @@ def init_params(C=32, seed=0, zero_last=True):
     return params
 
 
-def net_forward(f, params):
-    """o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))); returns o and the cache for backward."""
+def bf16(a):
+    """Round to bfloat16 (round to nearest, ties to even, on the float32 bit pattern), back to float64."""
+    x = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    x = (x + 0x7FFF + ((x >> 16) & 1)) >> 16 << 16
+    return x.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# layers whose operands the matrix cores read in bfloat16 (the two C -> C layers)
+MFMA_LAYERS = (1, 2)
+
+
+def net_forward(f, params, emulate_bf16=False):
+    """o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))); returns o and the cache for backward.
+    emulate_bf16 rounds the inputs and weights of the C -> C layers to bfloat16, where the
+    GPU's matrix cores read them (the cache keeps the unrounded activations)."""
     x0 = f[None]
     h = x0
     cache = []
     for i, (w, b) in enumerate(params):
-        z = conv3d(h, w, b)
+        if emulate_bf16 and i in MFMA_LAYERS:
+            z = conv3d(bf16(h), bf16(w), b)
+        else:
+            z = conv3d(h, w, b)
         cache.append((h, z))
         h = np.maximum(z, 0.0) if i < len(params) - 1 else z
     return -f + h[0], cache
 
 
-def net_backward(do, params, cache):
-    """Gradients of sum(do * o) with respect to the parameters (and the input features)."""
+def net_backward(do, params, cache, emulate_bf16=False):
+    """Gradients of sum(do * o) with respect to the parameters (and the input features).
+    emulate_bf16: the data gradients through the C -> C layers use bfloat16 copies of the incoming
+    gradient and of the weights, as the GPU's matrix cores do; weight gradients stay full precision."""
     grads = [None] * len(params)
     g = do[None]
     for i in range(len(params) - 1, -1, -1):
         h, z = cache[i]
         if i < len(params) - 1:
             g = g * (z > 0)
-        dx, dw, db = conv3d_backward(h, params[i][0], g)
+        _, dw, db = conv3d_backward(h, params[i][0], g)
+        if emulate_bf16 and i in MFMA_LAYERS:
+            dx, _, _ = conv3d_backward(h, bf16(params[i][0]), bf16(g))
+        else:
+            dx, _, _ = conv3d_backward(h, params[i][0], g)
         grads[i] = (dw, db)
         g = dx
     return grads, g[0] - do
@@ -200,16 +222,34 @@ def probe_loss_grad_d(d, A, B, C):
     return (2 * d * A - 2 * B) / np.sum(C)
 
 
-def loss_and_grads(f, params, N, ker0, A, B, C):
+def loss_and_grads(f, params, N, ker0, A, B, C, emulate_bf16=False):
     """Loss of the network on one sample and the gradients of every parameter."""
-    o, cache = net_forward(f, params)
+    o, cache = net_forward(f, params, emulate_bf16)
     d = diagonal(o, N, ker0)
     L = probe_loss(d, A, B, C)
     gd = probe_loss_grad_d(d, A, B, C)
     gs = upsample_adjoint(gd * d, N)            # through exp and U
     go = symmetrise(gs)                          # symmetrise is self-adjoint
-    grads, _ = net_backward(go, params, cache)
+    grads, _ = net_backward(go, params, cache, emulate_bf16)
     return L, grads, d
+
+
+def flatten_params(params):
+    """Host parameter layout of the library: w1 b1 w2 b2 w3 b3 w4 b4."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params])
+
+
+def unflatten_params(vec, C=32):
+    shapes = [(C, 1), (C, C), (C, C), (1, C)]
+    out, k = [], 0
+    for co, ci in shapes:
+        nw = co * ci * 27
+        w = np.asarray(vec[k:k + nw], dtype=np.float64).reshape(co, ci, 3, 3, 3)
+        k += nw
+        b = np.asarray(vec[k:k + co], dtype=np.float64)
+        k += co
+        out.append((w, b))
+    return out
 
 
 def precond_apply(d, r):

@@ -140,11 +140,11 @@ const char* firm_last_error(firm_plan p) {
 
 void firm_plan_destroy(firm_plan p) {
     if (!p) return;
-    void* dev[] = {p->c12, p->nrm, p->group, p->table, p->shifts, p->kb_poly, p->deconv_ker, p->deconv_atb,
+    void* dev[] = {p->S2, p->c12, p->nrm, p->group, p->table, p->shifts, p->kb_poly, p->deconv_ker, p->deconv_atb,
                    p->tw, p->kerc, p->khat, p->T1, p->T2, p->r, p->p, p->q, p->z, p->tmp, p->partials,
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
-                   p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->rhs, p->dvec};
+                   p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->host_scal) (void)hipHostFree(p->host_scal);
@@ -378,6 +378,7 @@ firm_status ensure_fp64(firm_plan p) {
     al(&p->p64, n3);
     al(&p->q64, n3);
     al(&p->y64, n3);
+    al(&p->atb64, n3);
     al(&p->rhs, n3);
     al(&p->dvec, n3);
     if (e != hipSuccess) return firm_fail(p, FIRM_ERR_ALLOC, std::string("FP64 buffers: ") + hipGetErrorString(e));
@@ -511,15 +512,31 @@ firm_status firm_apply_AtA_f64(firm_plan p, const double* x, double* y, double l
     return FIRM_OK;
 }
 
-firm_status firm_cg_solve(firm_plan p, const float* atb, float* x, double lambda, double tol, int max_iter,
-                          const float* d, firm_cg_report* rep) {
+static firm_status cg_args(firm_plan p, const void* atb, const void* x, double lambda, double tol, int max_iter,
+                           const float* d, firm_cg_report* rep) {
     if (!p || !atb || !x) return firm_fail(p, FIRM_ERR_ARG, "null argument");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
     if (!(tol >= 0.0) || !std::isfinite(tol)) return firm_fail(p, FIRM_ERR_ARG, "tol must be finite and >= 0");
     if (max_iter < 0) return firm_fail(p, FIRM_ERR_ARG, "max_iter must be >= 0");
+    if (d && p->precision == 2) return firm_fail(p, FIRM_ERR_ARG, "precision 2 runs plain CG: pass no preconditioner");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
     if (rep) std::memset(rep, 0, sizeof(*rep));
+    return FIRM_OK;
+}
+
+firm_status firm_cg_solve(firm_plan p, const float* atb, float* x, double lambda, double tol, int max_iter,
+                          const float* d, firm_cg_report* rep) {
+    firm_status s = cg_args(p, atb, x, lambda, tol, max_iter, d, rep);
+    if (s != FIRM_OK) return s;
     return cg_solve(p, atb, x, lambda_eff(p, lambda), tol, max_iter, d, rep);
+}
+
+firm_status firm_cg_solve_f64(firm_plan p, const double* atb, double* x, double lambda, double tol, int max_iter,
+                              const float* d, firm_cg_report* rep) {
+    firm_status s = cg_args(p, atb, x, lambda, tol, max_iter, d, rep);
+    if (s != FIRM_OK) return s;
+    if (p->precision == 0) return firm_fail(p, FIRM_ERR_STATE, "precision 0 solves in FP32: use firm_cg_solve");
+    return cg_solve64(p, atb, x, lambda_eff(p, lambda), tol, max_iter, d, rep);
 }
 
 firm_status firm_precond_apply(firm_plan p, const float* d, const float* r, float* z) {
@@ -547,6 +564,54 @@ firm_status firm_synth_slices(firm_plan p, int B, const double* centers, const d
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     (void)hipFree(dbl);
     if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("synth: ") + hipGetErrorString(e));
+    return FIRM_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+firm_status firm_kernel_features(firm_plan p, double lam_rel, float* feat) {
+    if (!p || !feat) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (p->N < 16) return firm_fail(p, FIRM_ERR_ARG, "features need N >= 16 (2N >= 32)");
+    if (!(lam_rel >= 0.0) || !std::isfinite(lam_rel)) return firm_fail(p, FIRM_ERR_ARG, "lam_rel must be >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    FIRM_HIP(p, kernel_features(p, (float)lam_rel, feat));
+    return FIRM_OK;
+}
+
+firm_status firm_probe_stats(firm_plan p, const float* probes, int nprobes, double lambda, float* A, float* B,
+                             double* sumc) {
+    if (!p || !probes || !A || !B || !sumc) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (nprobes < 1) return firm_fail(p, FIRM_ERR_ARG, "nprobes must be >= 1");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    const int64_t N = p->N, n3 = N * N * N;
+    if (!p->S2) FIRM_HIP(p, hipMalloc((void**)&p->S2, (size_t)(N * N * p->QPn) * sizeof(float2)));
+    hipStream_t st = p->stream;
+    FIRM_HIP(p, fill_zero(A, n3 * sizeof(float), st));
+    FIRM_HIP(p, fill_zero(B, n3 * sizeof(float), st));
+    const int nb = 1024;
+    double total = 0.0;
+    for (int k = 0; k < nprobes; ++k) {
+        const float* z = probes + k * n3;
+        FIRM_HIP(p, fft_apply_AtA(p, z, p->tmp, (float)lambda_eff(p, lambda)));
+        FIRM_HIP(p, fft_forward_r2c(p, p->tmp, p->S2));
+        FIRM_HIP(p, fft_forward_r2c(p, z, p->S1));
+        FIRM_HIP(p, probe_accumulate(p, p->S1, p->S2, A, B, p->partials3, nb));
+        FIRM_HIP(p, hipMemcpyAsync(p->host_scal + 16, p->partials3, 16 * sizeof(double), hipMemcpyDeviceToHost, st));
+        std::vector<double> part(nb);
+        FIRM_HIP(p, hipMemcpyAsync(part.data(), p->partials3, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+        FIRM_HIP(p, hipStreamSynchronize(st));
+        for (double v : part) total += v;
+    }
+    *sumc = total;
+    return FIRM_OK;
+}
+
+firm_status firm_synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out) {
+    if (!p || !out || n < 0) return firm_fail(p, FIRM_ERR_ARG, "bad argument");
+    FIRM_HIP(p, synth_normals(p, seed, offset, n, out));
     return FIRM_OK;
 }
 

@@ -322,11 +322,11 @@ __global__ void k_add_f_to_d(double* __restrict__ x, const float* __restrict__ d
     for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) x[i] += (double)d[i];
 }
 // r = atb - y (FP64); partial sums of r^2
-__global__ void __launch_bounds__(VT) k_resid64(const float* __restrict__ atb, const double* __restrict__ y,
+__global__ void __launch_bounds__(VT) k_resid64(const double* __restrict__ atb, const double* __restrict__ y,
                                                 double* __restrict__ r, int64_t n, double* partials) {
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-        const double v = (double)atb[i] - y[i];
+        const double v = atb[i] - y[i];
         r[i] = v;
         acc += v * v;
     }
@@ -372,40 +372,35 @@ __global__ void k_beta64(double* scal) {
 #define L1(k, ...) hipLaunchKernelGGL(k, dim3(VB), dim3(VT), 0, st, __VA_ARGS__)
 #define R1(...) hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, __VA_ARGS__)
 
-// ||atb - (A*A + lam) x||^2 with the FP64 product (x given in FP32); also ||atb||^2.
-static firm_status true_residual64(firm_plan p, const float* atb, const float* x, double lam, double* rr,
-                                   double* bb) {
-    firm_status fs = ensure_fp64(p);
-    if (fs != FIRM_OK) return fs;
+// ||atb - (A*A + lam) x||^2 with the FP64 product, and ||atb||^2 (atb, x: FP64 device arrays;
+// x must not be p->y64 or p->r64).
+static firm_status residual64(firm_plan p, const double* atb, const double* x, double lam, double* rr,
+                              double* bb) {
     const int64_t n = (int64_t)p->N * p->N * p->N;
     hipStream_t st = p->stream;
-    L1(k_d_from_f, p->x64, x, n);
-    CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+    CK(fft_apply_AtA64(p, x, p->y64, lam));
     L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
     R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
-    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    L1(k_dot64, atb, atb, n, p->partials3);
     R1(p->partials3, VB, p->scal, (int)S_BB, -1, nullptr);
     CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     *rr = p->host_scal[S_TRUE];
-    *bb = p->host_scal[S_BB];
+    *bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
     return FIRM_OK;
 }
 
-// FP64 CG: vectors, product and sums in double (khat64 from the FP32 kernel values).
-static firm_status cg_fp64(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+// FP64 CG: vectors, product and sums in double (khat64 from the FP32 kernel values); the
+// iterate xw (FP64, device) holds the initial guess and receives the solution.
+static firm_status cg_fp64(firm_plan p, const double* atb, double* xw, double lam, double tol, int max_iter,
                            firm_cg_report* rep) {
-    auto t0 = std::chrono::steady_clock::now();
-    firm_status fs = ensure_fp64(p);
-    if (fs != FIRM_OK) return fs;
     const int64_t n = (int64_t)p->N * p->N * p->N;
     hipStream_t st = p->stream;
     double* sc = p->scal;
-    L1(k_d_from_f, p->x64, x, n);
-    CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+    CK(fft_apply_AtA64(p, xw, p->y64, lam));
     L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
     R1(p->partials3, VB, sc, (int)S_RR, (int)S_RZ, nullptr);
-    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    L1(k_dot64, atb, atb, n, p->partials3);
     R1(p->partials3, VB, sc, (int)S_BB, -1, nullptr);
     hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(1), 0, st, sc, (int)S_BETA, 0.0);
     CK(fill_zero(p->p64, n * sizeof(double), st));
@@ -422,7 +417,7 @@ static firm_status cg_fp64(firm_plan p, const float* atb, float* x, double lam, 
         L1(k_dot64, p->p64, p->q64, n, p->partials);
         R1(p->partials, VB, sc, (int)S_PQ, -1, nullptr);
         hipLaunchKernelGGL(k_alpha64, dim3(1), dim3(1), 0, st, sc);
-        L1(k_update64, p->x64, p->p64, p->r64, p->q64, n, sc, p->partials3);
+        L1(k_update64, xw, p->p64, p->r64, p->q64, n, sc, p->partials3);
         R1(p->partials3, VB, sc, (int)S_RR, -1, nullptr);
         hipLaunchKernelGGL(k_beta64, dim3(1), dim3(1), 0, st, sc);
         CK(hipMemcpyAsync(p->host_scal, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -431,42 +426,29 @@ static firm_status cg_fp64(firm_plan p, const float* atb, float* x, double lam, 
         rr = p->host_scal[S_RR];
         if (!(p->host_scal[S_PQ] > 0.0) || !std::isfinite(rr)) { result = FIRM_ERR_BREAKDOWN; break; }
     }
-    L1(k_f_from_d, x, p->x64, n);
     if (rep) {
         rep->iters = it;
-        rep->status = result;
         rep->rel_res = std::sqrt(rr / bb);
-    }
-    double trr = 0, tbb = 1;
-    fs = true_residual64(p, atb, x, lam, &trr, &tbb);
-    if (fs != FIRM_OK) return fs;
-    if (rep) {
-        rep->true_rel_res = std::sqrt(trr / (tbb > 0 ? tbb : 1.0));
-        rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
     return result;
 }
 
 // FP64 iterative refinement: r = atb - (A*A + lam) x with the FP64 product and FP64 x; each
 // correction solves (A*A + lam) d = r with FP32 (P)CG to a relative tolerance, x += d.
-static firm_status cg_refine64(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+static firm_status cg_refine64(firm_plan p, const double* atb, double* xw, double lam, double tol, int max_iter,
                                const float* d, firm_cg_report* rep) {
-    auto t0 = std::chrono::steady_clock::now();
-    firm_status fs = ensure_fp64(p);
-    if (fs != FIRM_OK) return fs;
     const int64_t n = (int64_t)p->N * p->N * p->N;
     hipStream_t st = p->stream;
-    L1(k_d_from_f, p->x64, x, n);
-    hipLaunchKernelGGL(k_dot, dim3(VB), dim3(VT), 0, st, atb, atb, n, p->partials3);
+    L1(k_dot64, atb, atb, n, p->partials3);
     R1(p->partials3, VB, p->scal, (int)S_BB, -1, nullptr);
     CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
     const double bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
-    int total = 0, outer = 0, fell_back = 0, refinements = 0;
+    int total = 0, outer = 0, fell_back = 0;
     double rr = 0.0;
     firm_status result = FIRM_OK;
     for (;;) {
-        CK(fft_apply_AtA64(p, p->x64, p->y64, lam));
+        CK(fft_apply_AtA64(p, xw, p->y64, lam));
         L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
         R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
         CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -485,44 +467,79 @@ static firm_status cg_refine64(firm_plan p, const float* atb, float* x, double l
         if (is != FIRM_OK && is != FIRM_ERR_NOT_CONVERGED && is != FIRM_ERR_BREAKDOWN) return is;
         total += ir.iters;
         fell_back |= ir.fell_back;
-        refinements += ir.refinements;
-        L1(k_add_f_to_d, p->x64, p->dvec, n);
+        L1(k_add_f_to_d, xw, p->dvec, n);
         ++outer;
         if (ir.iters == 0) { result = FIRM_ERR_NOT_CONVERGED; break; }  // no progress possible
     }
-    L1(k_f_from_d, x, p->x64, n);
-    CK(hipStreamSynchronize(st));
     if (rep) {
         rep->iters = total;
         rep->refinements = outer;
         rep->fell_back = fell_back;
-        rep->status = result;
         rep->rel_res = std::sqrt(rr / bb);
-        rep->true_rel_res = std::sqrt(rr / bb);
-        rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
-    (void)refinements;
     return result;
 }
 
-firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
-                     const float* d, firm_cg_report* rep) {
-    firm_status r;
-    if (p->precision == 2) {
-        r = cg_fp64(p, atb, x, lam, tol, max_iter, rep);
-    } else if (p->precision == 1) {
-        r = cg_refine64(p, atb, x, lam, tol, max_iter, d, rep);
-    } else {
-        r = cg_core32(p, atb, x, lam, tol, max_iter, d, rep);
-        if (r == FIRM_OK || r == FIRM_ERR_NOT_CONVERGED) {
-            double trr = 0, tbb = 1;
-            firm_status fs = true_residual64(p, atb, x, lam, &trr, &tbb);
-            if (fs != FIRM_OK) return fs;
-            if (rep) rep->true_rel_res = std::sqrt(trr / (tbb > 0 ? tbb : 1.0));
-        }
-    }
+static firm_status finish(firm_plan p, firm_status r, firm_cg_report* rep) {
     if (rep) rep->status = r;
     if (r == FIRM_ERR_NOT_CONVERGED) return firm_fail(p, r, "CG reached max_iter above tol");
     if (r == FIRM_ERR_BREAKDOWN) return firm_fail(p, r, "CG breakdown (non-positive curvature)");
     return r;
+}
+
+static bool solver_ran(firm_status r) {
+    return r == FIRM_OK || r == FIRM_ERR_NOT_CONVERGED || r == FIRM_ERR_BREAKDOWN;
+}
+
+// FP32 in and out: the solution returned is FP32 in every mode, and the reported true residual
+// is that of the FP32 x written out (for precision 1 and 2 it can exceed the FP64 iterate's
+// residual by the rounding of x, about 6e-8 times the condition number).
+firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
+                     const float* d, firm_cg_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    firm_status fs = ensure_fp64(p);
+    if (fs != FIRM_OK) return fs;
+    const int64_t n = (int64_t)p->N * p->N * p->N;
+    hipStream_t st = p->stream;
+    L1(k_d_from_f, p->atb64, atb, n);
+    firm_status r;
+    if (p->precision == 0) {
+        r = cg_core32(p, atb, x, lam, tol, max_iter, d, rep);
+    } else {
+        L1(k_d_from_f, p->x64, x, n);
+        r = p->precision == 2 ? cg_fp64(p, p->atb64, p->x64, lam, tol, max_iter, rep)
+                              : cg_refine64(p, p->atb64, p->x64, lam, tol, max_iter, d, rep);
+        if (solver_ran(r)) L1(k_f_from_d, x, p->x64, n);
+    }
+    if (solver_ran(r)) {
+        L1(k_d_from_f, p->x64, x, n);
+        double trr = 0, tbb = 1;
+        fs = residual64(p, p->atb64, p->x64, lam, &trr, &tbb);
+        if (fs != FIRM_OK) return fs;
+        if (rep) {
+            rep->true_rel_res = std::sqrt(trr / tbb);
+            rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    }
+    return finish(p, r, rep);
+}
+
+// FP64 in and out (precision 1 or 2): x is the FP64 iterate itself.
+firm_status cg_solve64(firm_plan p, const double* atb, double* x, double lam, double tol, int max_iter,
+                       const float* d, firm_cg_report* rep) {
+    auto t0 = std::chrono::steady_clock::now();
+    firm_status fs = ensure_fp64(p);
+    if (fs != FIRM_OK) return fs;
+    firm_status r = p->precision == 2 ? cg_fp64(p, atb, x, lam, tol, max_iter, rep)
+                                      : cg_refine64(p, atb, x, lam, tol, max_iter, d, rep);
+    if (solver_ran(r)) {
+        double trr = 0, tbb = 1;
+        fs = residual64(p, atb, x, lam, &trr, &tbb);
+        if (fs != FIRM_OK) return fs;
+        if (rep) {
+            rep->true_rel_res = std::sqrt(trr / tbb);
+            rep->t_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    }
+    return finish(p, r, rep);
 }

@@ -54,7 +54,7 @@ struct firm_plan_s {
     double2* T1d = nullptr;
     double2* T2d = nullptr;
     double2* tw64 = nullptr;
-    double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *y64 = nullptr;
+    double *x64 = nullptr, *r64 = nullptr, *p64 = nullptr, *q64 = nullptr, *y64 = nullptr, *atb64 = nullptr;
     float *rhs = nullptr, *dvec = nullptr;  // FP32 correction right-hand side and solution
 
     // CG workspaces
@@ -65,6 +65,7 @@ struct firm_plan_s {
     double* host_scal = nullptr; // pinned host mirror
     float* dhalf = nullptr;      // preconditioner diagonal / N^3, FFT order, blocked [q2][q3 group][q1][C]
     float2* S1 = nullptr;        // PCG FFT workspace [N][N][QPn]
+    float2* S2 = nullptr;        // second half-spectrum workspace (probe statistics), on first use
     int QPn = 0;
 
     // gridding workspaces (allocated on first use, kept)
@@ -95,6 +96,11 @@ hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam);
 int fft_cols_per_block(int L, bool dbl);  // pencils per workgroup of the L-point pass
 size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl);
 hipError_t fft_khat_unblock(firm_plan p, float* out);
+hipError_t fft_forward_r2c(firm_plan p, const float* x, float2* out);  // N^3 real -> [N][N][QPn] half spectrum
+hipError_t kernel_features(firm_plan p, float lam_rel, float* feat);
+hipError_t probe_accumulate(firm_plan p, const float2* zh, const float2* uh, float* A, float* B, double* partials,
+                            int nblocks);
+hipError_t synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out);
 hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev);
 hipError_t fft_khat_from_kerc(firm_plan p, float2* w1);        // kerc -> khat (w1: [2N][2N][QP])
 hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, float* chalf);
@@ -126,6 +132,8 @@ hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr,
 // ---- cg.hip ----
 firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,
                      const float* d, firm_cg_report* rep);
+firm_status cg_solve64(firm_plan p, const double* atb, double* x, double lam, double tol, int max_iter,
+                       const float* d, firm_cg_report* rep);
 hipError_t precond_set(firm_plan p, const float* d_centred);
 
 std::vector<int> spread_worklist(int L, int T, int M, double s);

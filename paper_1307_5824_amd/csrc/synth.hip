@@ -165,7 +165,23 @@ __global__ void k_synth_noise(SynthArgs a, const double* power, int nparts) {
     }
 }
 
+// standard normals: out[i] from Philox4x32-10 with counter (i mod 2^32, i / 2^32, offset, 1), Box-Muller
+__global__ void k_normals(uint64_t seed, uint64_t offset, int64_t n, float* out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        Philox4 c{{(uint32_t)i, (uint32_t)(i >> 32), (uint32_t)offset, 1u}};
+        const Philox4 r = philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const float u1 = ((float)r.v[0] + 0.5f) * 2.3283064365386963e-10f;
+        const float u2 = ((float)r.v[1] + 0.5f) * 2.3283064365386963e-10f;
+        out[i] = sqrtf(-2.f * logf(u1)) * cosf(6.283185307179586f * u2);
+    }
+}
+
 }  // namespace
+
+hipError_t synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out) {
+    hipLaunchKernelGGL(k_normals, dim3(4096), dim3(256), 0, p->stream, seed, offset, n, out);
+    return hipGetLastError();
+}
 
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed, float2* b,
                         double* power_dev) {

@@ -64,10 +64,24 @@ def _load():
         "firm_apply_AtA_f64": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_timed": (i, [vp, vp, vp, d, i, vp]),
         "firm_cg_solve": (i, [vp, vp, vp, d, d, i, vp, ctypes.POINTER(FirmCgReport)]),
+        "firm_cg_solve_f64": (i, [vp, vp, vp, d, d, i, vp, ctypes.POINTER(FirmCgReport)]),
         "firm_precond_apply": (i, [vp, vp, vp, vp]),
         "firm_synth_slices": (i, [vp, i, vp, vp, vp, d, ctypes.c_uint64, vp]),
         "firm_last_error": (ctypes.c_char_p, [vp]),
         "firm_philox4x32_10": (None, [vp, vp, vp]),
+        "firm_pcnet_num_params": (i64, []),
+        "firm_pcnet_create": (i, [ctypes.POINTER(vp), i, vp]),
+        "firm_pcnet_destroy": (None, [vp]),
+        "firm_pcnet_set_params": (i, [vp, vp]),
+        "firm_pcnet_get_params": (i, [vp, vp]),
+        "firm_pcnet_forward": (i, [vp, vp, vp, i]),
+        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
+        "firm_pcnet_train_step": (i, [vp, vp, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
+        "firm_pcnet_last_error": (ctypes.c_char_p, [vp]),
+        "firm_kernel_features": (i, [vp, d, vp]),
+        "firm_precond_from_output": (i, [vp, vp, vp]),
+        "firm_probe_stats": (i, [vp, vp, i, d, vp, vp, ctypes.POINTER(d)]),
+        "firm_synth_normals": (i, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -226,13 +240,17 @@ class Plan:
         return out
 
     def cg_solve(self, atb, lam, tol, max_iter, x0=None, precond=None, raise_on_not_converged=False):
-        self._req(atb, self.N ** 3, self._torch.float32)
-        x = self._torch.zeros_like(atb) if x0 is None else x0.clone()
+        """CG on (A*A + lam) x = atb.  A float32 atb runs firm_cg_solve (FP32 x); a float64 atb
+        runs firm_cg_solve_f64 (FP64 x, precision 1 or 2)."""
+        t = self._torch
+        f64 = atb.dtype == t.float64
+        self._req(atb, self.N ** 3, t.float64 if f64 else t.float32)
+        x = t.zeros_like(atb) if x0 is None else x0.to(atb.dtype).clone()
         if precond is not None:
-            self._req(precond, self.N ** 3, self._torch.float32)
+            self._req(precond, self.N ** 3, t.float32)
         rep = FirmCgReport()
-        st = lib.firm_cg_solve(self.h, _ptr(atb), _ptr(x), float(lam), float(tol), int(max_iter),
-                               _ptr(precond), ctypes.byref(rep))
+        fn = lib.firm_cg_solve_f64 if f64 else lib.firm_cg_solve
+        st = fn(self.h, _ptr(atb), _ptr(x), float(lam), float(tol), int(max_iter), _ptr(precond), ctypes.byref(rep))
         if st not in (FIRM_OK, FIRM_ERR_NOT_CONVERGED) or (st != FIRM_OK and raise_on_not_converged):
             raise FirmError(st, last_error(self.h))
         return x, rep.as_dict()
@@ -253,3 +271,113 @@ class Plan:
         self._req(out, self.M * self.P, self._torch.complex64)
         _check(lib.firm_synth_slices(self.h, int(c.shape[0]), cp, sp, ap, float(snr), int(seed), _ptr(out)), self.h)
         return out
+
+
+# ---- learned preconditioner helpers (attached to Plan below)
+
+def _plan_kernel_features(self, lam_rel, out=None):
+    if out is None:
+        out = self._torch.empty((32, 32, 32), dtype=self._torch.float32, device="cuda")
+    _check(lib.firm_kernel_features(self.h, float(lam_rel), _ptr(out)), self.h)
+    return out
+
+
+def _plan_precond_from_output(self, o, out=None):
+    out = self._vol(out)
+    _check(lib.firm_precond_from_output(self.h, _ptr(o), _ptr(out)), self.h)
+    return out
+
+
+def _plan_probe_stats(self, probes, lam):
+    t = self._torch
+    P = probes.shape[0]
+    self._req(probes, P * self.N ** 3, t.float32)
+    A = t.empty((self.N,) * 3, dtype=t.float32, device="cuda")
+    B = t.empty_like(A)
+    sc = ctypes.c_double()
+    _check(lib.firm_probe_stats(self.h, _ptr(probes), int(P), float(lam), _ptr(A), _ptr(B), ctypes.byref(sc)), self.h)
+    return A, B, sc.value
+
+
+def _plan_synth_normals(self, seed, offset, shape):
+    t = self._torch
+    out = t.empty(shape, dtype=t.float32, device="cuda")
+    _check(lib.firm_synth_normals(self.h, int(seed), int(offset), int(out.numel()), _ptr(out)), self.h)
+    return out
+
+
+Plan.kernel_features = _plan_kernel_features
+Plan.precond_from_output = _plan_precond_from_output
+Plan.probe_stats = _plan_probe_stats
+Plan.synth_normals = _plan_synth_normals
+
+
+class PCNet:
+    """The preconditioner network (device-resident FP32 masters, BF16 matrix-core copies)."""
+
+    NPARAM = None
+
+    def __init__(self, max_batch=8, stream=None):
+        import torch
+        self._torch = torch
+        s = stream if stream is not None else _current_stream()
+        h = ctypes.c_void_p()
+        st = lib.firm_pcnet_create(ctypes.byref(h), int(max_batch), s)
+        if st != FIRM_OK:
+            raise FirmError(st, last_error())
+        self.h = h
+        self.max_batch = max_batch
+        PCNet.NPARAM = int(lib.firm_pcnet_num_params())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib.firm_pcnet_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st):
+        if st != FIRM_OK:
+            raise FirmError(st, (lib.firm_pcnet_last_error(self.h) or b"").decode())
+
+    def set_params(self, params):
+        arr = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        assert arr.size == PCNet.NPARAM
+        self._chk(lib.firm_pcnet_set_params(self.h, arr.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_params(self):
+        arr = np.zeros(PCNet.NPARAM, dtype=np.float32)
+        self._chk(lib.firm_pcnet_get_params(self.h, arr.ctypes.data_as(ctypes.c_void_p)))
+        return arr
+
+    def forward(self, feat):
+        t = self._torch
+        B = feat.shape[0] if feat.dim() == 4 else 1
+        out = t.empty((B, 32, 32, 32), dtype=t.float32, device="cuda")
+        self._chk(lib.firm_pcnet_forward(self.h, _ptr(feat), _ptr(out), int(B)))
+        return out
+
+    def loss_grad(self, feat, N, A, Bs, sumc, ker0, with_grad=True):
+        B = feat.shape[0]
+        sc = np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
+        k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
+        loss = ctypes.c_double()
+        g = np.zeros(PCNet.NPARAM, dtype=np.float32) if with_grad else None
+        self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(B), int(N), _ptr(A), _ptr(Bs),
+                                           sc.ctypes.data_as(ctypes.c_void_p), k0.ctypes.data_as(ctypes.c_void_p),
+                                           ctypes.byref(loss), None if g is None else g.ctypes.data_as(ctypes.c_void_p)))
+        return loss.value, g
+
+    def train_step(self, feat, N, A, Bs, sumc, ker0, lr):
+        B = feat.shape[0]
+        sc = np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
+        k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
+        loss = ctypes.c_double()
+        self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(B), int(N), _ptr(A), _ptr(Bs),
+                                            sc.ctypes.data_as(ctypes.c_void_p), k0.ctypes.data_as(ctypes.c_void_p),
+                                            float(lr), ctypes.byref(loss)))
+        return loss.value

@@ -127,21 +127,35 @@ def test_backproject_non_hermitian_real_part(firm):
     assert rel(got, ref) < TOL
 
 
-def _fp32_envelope(apply, b, k, seed=0):
-    """How far CG's k-th iterate moves when every product and vector is rounded to FP32: the
-    oracle's FP64 CG against the same recursion with FP32 rounding applied (plain numpy on the
-    oracle's own operator).  CG amplifies rounding on ill-conditioned systems; an FP32 solver
-    cannot be held closer to FP64 than this."""
+# RMS relative error of an FP32 FFT product on the (2N)^3 = 2^15-point grid: a forward and an
+# inverse transform of 15 radix levels each, ~6e-8 * sqrt(2 * 15) = 3.3e-7.
+FP32_PRODUCT_ERR = 3e-7
+
+
+def _fp32_envelope(apply, b, k, ref, precond=None, seeds=3):
+    """How far (P)CG's k-th iterate moves from the oracle's FP64 iterate ref when the recursion
+    runs in FP32: the same recursion as the oracle's (P)CG, with every vector rounded to FP32
+    and every product (and preconditioner application) carrying a seeded random relative error
+    of FP32_PRODUCT_ERR; the largest deviation over a few seeds.  CG amplifies such errors on
+    ill-conditioned systems; an FP32 solver cannot be held closer to FP64 than this."""
     f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)  # noqa: E731
-    x = np.zeros_like(b); r = f32(b); p = np.zeros_like(b)
-    rr = float(np.sum(r * r)); beta = 0.0
-    for _ in range(k):
-        p = f32(r + beta * p)
-        q = f32(apply(p))
-        a = rr / float(np.sum(p * q))
-        x = f32(x + a * p); r = f32(r - a * q)
-        rn = float(np.sum(r * r)); beta = rn / rr; rr = rn
-    return x
+    worst = 0.0
+    for seed in range(seeds):
+        rng = np.random.default_rng(seed)
+
+        def noisy(v):
+            return f32(v + FP32_PRODUCT_ERR * np.linalg.norm(v) / np.sqrt(v.size) * rng.standard_normal(v.shape))
+        M = (lambda r: r) if precond is None else (lambda r: noisy(precond(r)))
+        x = np.zeros_like(b); r = f32(b); z = M(r); p = np.zeros_like(b)
+        rz = float(np.sum(r * z)); beta = 0.0
+        for _ in range(k):
+            p = f32(z + beta * p)
+            q = noisy(apply(p))
+            a = rz / float(np.sum(p * q))
+            x = f32(x + a * p); r = f32(r - a * q); z = M(r)
+            rn = float(np.sum(r * z)); beta = rn / rz; rz = rn
+        worst = max(worst, rel(x, ref))
+    return worst
 
 
 def _small_workload():
@@ -152,28 +166,51 @@ def _small_workload():
     return inp, wl, b
 
 
-def test_cg_small_workload_fp64_iterates(firm):
+def test_cg_fp64_iterates_match_oracle(firm):
+    """FP64 CG (precision 2, FP64 right-hand side and solution) on the small workload's geometry
+    with the oracle's kernel values: the same FP32 kernel values and FP64 A*b on both sides, so the
+    20th iterate agrees to FP64 rounding amplified by the conditioning (~1e-13), held at 1e-9."""
+    inp, wl, b = _small_workload()
+    N = wl.N
+    Ker = ofirm.kernel_direct(N, inp.rotations).real
+    K32 = ker_to_centred(Ker, N).astype(np.float32)
+    atb_ref = ofirm.back_project(b.astype(np.complex128), N, inp.rotations).real
+    plan = firm.Plan(N, inp.rotations, precision=2)
+    plan.kernel_set(dev(K32))
+    x, rep = plan.cg_solve(dev(atb_ref, torch.float64), wl.lam, 0.0, 20)
+    assert x.dtype == torch.float64 and rep["iters"] == 20
+    Kf = K32[1:, 1:, 1:].astype(np.float64)
+    x_ref = ofirm.cg(lambda v: ofirm.toeplitz_apply_fft(Kf, v).real + wl.lam * v, atb_ref, iters=20)
+    err = rel(host(x), x_ref)
+    print(f"FP64 CG x_20 rel err on equal inputs {err:.3e}", flush=True)
+    assert err < 1e-9
+
+
+def test_cg_small_workload_fp64_end_to_end(firm):
     """The small workload end to end (N=16, 5 blobs, M=200 Haar views, no CTF, noiseless,
-    lambda=1e-3, 20 CG steps from x0 = 0) in FP64 CG: GPU Ker, A*b and x_20 vs the oracle's
-    FP64 CG on its direct-sum kernel.  Window width 8 keeps the gridding error (~1e-7) below
-    what 20 steps amplify past 1e-5."""
+    lambda=1e-3, 20 CG steps from x0 = 0): GPU Ker and A*b (window width 8), FP64 CG, against the
+    oracle's FP64 CG on its direct-sum kernel and back-projection.  The library stores Ker and
+    A*b in FP32; at condition number ~4e7 that storage alone moves the oracle's own x_20 by
+    ~7e-5 (computed here), so x_20 is held at twice that envelope."""
     inp, wl, b = _small_workload()
     N = wl.N
     plan = firm.Plan(N, inp.rotations, kb_width=8, precision=2)
     plan.kernel_precompute()
     atb = plan.backproject(dev(b, torch.complex64))
-    x, rep = plan.cg_solve(atb, wl.lam, 0.0, 20)
-    Ker = ofirm.kernel_direct(N, inp.rotations)
+    x, rep = plan.cg_solve(atb.double(), wl.lam, 0.0, 20)
+    Ker = ofirm.kernel_direct(N, inp.rotations).real
     atb_ref = ofirm.back_project(b.astype(np.complex128), N, inp.rotations).real
     assert rel(host(atb), atb_ref) < TOL
-
-    def apply(v):
-        return ofirm.toeplitz_apply_fft(Ker, v).real + wl.lam * v
-    x_ref = ofirm.cg(apply, atb_ref, iters=20)
     assert rep["iters"] == 20
+
+    def run(K, a):
+        return ofirm.cg(lambda v: ofirm.toeplitz_apply_fft(K, v).real + wl.lam * v, a, iters=20)
+    x_ref = run(Ker, atb_ref)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    env = rel(run(f32(Ker), f32(atb_ref)), x_ref)
     err = rel(host(x), x_ref)
-    print(f"small workload FP64 CG x_20 rel err {err:.3e}", flush=True)
-    assert err < TOL
+    print(f"small workload FP64 CG x_20 rel err {err:.3e}, FP32-storage envelope {env:.3e}", flush=True)
+    assert err < max(TOL, 2 * env)
 
 
 def test_cg_small_workload_fp32_iterates(firm):
@@ -194,7 +231,7 @@ def test_cg_small_workload_fp32_iterates(firm):
     assert rel(host(x5), ofirm.cg(apply, atb_ref, iters=5)) < TOL
     x20, _ = plan.cg_solve(atb, wl.lam, 0.0, 20)
     ref = ofirm.cg(apply, atb_ref, iters=20)
-    env = rel(_fp32_envelope(apply, atb_ref, 20), ref)
+    env = _fp32_envelope(apply, atb_ref, 20, ref)
     err = rel(host(x20), ref)
     print(f"small workload FP32 CG x_20 rel err {err:.3e}, FP32 envelope {env:.3e}", flush=True)
     assert err < max(TOL, 4 * env)
@@ -237,29 +274,60 @@ def test_precond_apply_matches_oracle(firm, N):
 
 
 def test_pcg_unit_diagonal_equals_cg(firm):
-    """d = 1 gives the plain CG iterates (GPU against GPU and against the oracle's CG), on a
-    system well enough conditioned (lambda = 0.1 Ker(0)) that FP32 rounding stays below 1e-5."""
+    """d = 1 gives the plain CG iterates: GPU PCG against GPU CG and both against the oracle's
+    CG, within the FP32 rounding envelope of the recursion (lambda = 0.1 Ker(0), 12 steps)."""
     N, M = 16, 30
     R, _, _, _ = small_geometry(N, M, 71)
     Ker = ofirm.kernel_direct(N, R).real
     plan = firm.Plan(N, R)
     plan.kernel_set(dev(ker_to_centred(Ker, N)))
-    atb = dev(np.random.default_rng(8).standard_normal((N, N, N)))
+    b = np.random.default_rng(8).standard_normal((N, N, N)).astype(np.float32).astype(np.float64)
+    atb = dev(b)
     lam = 0.1 * float(Ker[N - 1, N - 1, N - 1])
     x1, _ = plan.cg_solve(atb, lam, 0.0, 12)
     x2, rep2 = plan.cg_solve(atb, lam, 0.0, 12, precond=torch.ones((N, N, N), device="cuda"))
     assert rep2["iters"] == 12 and rep2["fell_back"] == 0
-    assert rel(host(x2), host(x1)) < TOL
 
     def apply(v):
         return ofirm.toeplitz_apply_fft(Ker, v).real + lam * v
-    assert rel(host(x1), ofirm.cg(apply, host(atb), iters=12)) < TOL
+    ref = ofirm.cg(apply, b, iters=12)
+    env = _fp32_envelope(apply, b, 12, ref, precond=lambda r: r)
+    tol = max(TOL, 4 * env)
+    print(f"unit-diagonal PCG: FP32 envelope {env:.3e}", flush=True)
+    assert rel(host(x1), ref) < tol
+    assert rel(host(x2), ref) < tol
+    assert rel(host(x2), host(x1)) < 2 * tol
+
+
+def test_pcg_iterates_match_oracle(firm):
+    """PCG with a non-trivial even diagonal (the inverse of T. Chan's circulant) against the
+    oracle's FP64 PCG, 10 steps, within the FP32 rounding envelope of that recursion."""
+    N, M = 16, 40
+    R, _, _, _ = small_geometry(N, M, 73)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 0.05 * float(Ker[N - 1, N - 1, N - 1])
+    d = 1.0 / ofirm.chan_circulant_spectrum(Ker, N, lam)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    b = np.random.default_rng(10).standard_normal((N, N, N)).astype(np.float32).astype(np.float64)
+    x, rep = plan.cg_solve(dev(b), lam, 0.0, 10, precond=dev(d))
+    assert rep["iters"] == 10 and rep["fell_back"] == 0
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + lam * v
+    d32 = d.astype(np.float32).astype(np.float64)
+    M_ = ofirm.fourier_diagonal_precond(d32)
+    ref = ofirm.pcg(apply, M_, b, iters=10)
+    env = _fp32_envelope(apply, b, 10, ref, precond=M_)
+    err = rel(host(x), ref)
+    print(f"PCG x_10 rel err {err:.3e}, FP32 envelope {env:.3e}", flush=True)
+    assert err < max(TOL, 4 * env)
 
 
 def test_pcg_chan_diagonal_reduces_iterations(firm):
     """PCG with the inverse of T. Chan's optimal circulant (computed by the oracle) reaches the
-    tolerance in fewer iterations than CG; FP64 refinement (precision 1) brings both to a true
-    residual of 1e-6 that the oracle confirms."""
+    tolerance in fewer iterations than CG; FP64 refinement (precision 1) with FP64 right-hand
+    side and solution brings both to a true residual of 1e-6 that the oracle confirms."""
     N, M = 16, 60
     R, _, _, _ = small_geometry(N, M, 81)
     Ker = ofirm.kernel_direct(N, R).real
@@ -270,18 +338,40 @@ def test_pcg_chan_diagonal_reduces_iterations(firm):
     K32 = ker_to_centred(Ker, N).astype(np.float32)
     plan.kernel_set(dev(K32))
     b = np.random.default_rng(9).standard_normal((N, N, N))
-    atb = dev(b)
+    atb = dev(b, torch.float64)
     x1, r1 = plan.cg_solve(atb, lam, 1e-6, 5000)
     x2, r2 = plan.cg_solve(atb, lam, 1e-6, 5000, precond=dev(d))
     print("cg", r1, "pcg", r2, flush=True)
     assert r1["status"] == 0 and r2["status"] == 0
     assert r2["iters"] < r1["iters"]
     Kf = K32[1:, 1:, 1:].astype(np.float64)
-    b32 = b.astype(np.float32).astype(np.float64)
-    for x in (x1, x2):
+    for x, r in ((x1, r1), (x2, r2)):
         xr = host(x)
-        res = b32 - (ofirm.toeplitz_apply_fft(Kf, xr).real + lam * xr)
-        assert np.linalg.norm(res) / np.linalg.norm(b32) < 2e-6
+        res = b - (ofirm.toeplitz_apply_fft(Kf, xr).real + lam * xr)
+        tr = np.linalg.norm(res) / np.linalg.norm(b)
+        assert tr <= 1e-6 * (1 + 1e-6)
+        assert abs(tr - r["true_rel_res"]) <= 1e-9
+
+
+def test_fp32_output_reports_its_own_residual(firm):
+    """With FP32 output, precision 1 solves to 1e-6 in FP64 but returns x rounded to FP32; the
+    reported true residual is that of the returned x (the oracle recomputes it)."""
+    N, M = 16, 60
+    R, _, _, _ = small_geometry(N, M, 81)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 1e-3 * float(Ker[N - 1, N - 1, N - 1])
+    plan = firm.Plan(N, R, precision=1)
+    K32 = ker_to_centred(Ker, N).astype(np.float32)
+    plan.kernel_set(dev(K32))
+    b32 = np.random.default_rng(9).standard_normal((N, N, N)).astype(np.float32).astype(np.float64)
+    x, rep = plan.cg_solve(dev(b32), lam, 1e-6, 5000)
+    assert x.dtype == torch.float32
+    xr = host(x)
+    Kf = K32[1:, 1:, 1:].astype(np.float64)
+    tr = np.linalg.norm(b32 - (ofirm.toeplitz_apply_fft(Kf, xr).real + lam * xr)) / np.linalg.norm(b32)
+    print(f"FP32-rounded solution residual {tr:.3e}, FP64 iterate {rep['rel_res']:.3e}", flush=True)
+    assert rep["rel_res"] <= 1e-6
+    assert abs(tr - rep["true_rel_res"]) <= 1e-6 * tr
 
 
 def test_apply_fp64_matches_oracle(firm):

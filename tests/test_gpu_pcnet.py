@@ -1,0 +1,173 @@
+"""GPU parity of the learned-preconditioner kernels against the FP64 oracle.
+
+The oracle emulates the GPU's bfloat16 rounding points (the operands of the two matrix-core
+layers, forward and backward-data); what remains is FP32 accumulation order, so forward
+outputs, losses and gradients are compared at 1e-4 relative.  Features, diagonals and probe
+statistics involve no bfloat16 and are compared at 1e-5.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import ker_to_centred, rel, small_geometry  # noqa: E402
+from oracle import firm as ofirm  # noqa: E402
+from oracle import pcnet as opc  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def firm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1307_5824_amd import firm as f
+    return f
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _params(seed):
+    p = opc.init_params(32, seed=seed, zero_last=False)
+    rng = np.random.default_rng(seed + 100)
+    return [(w, 0.05 * rng.standard_normal(b.shape)) for w, b in p]
+
+
+def test_forward_matches_oracle(firm):
+    """Network output for two random feature volumes (bf16 rounding points emulated)."""
+    params = _params(1)
+    f = 0.5 * np.random.default_rng(2).standard_normal((2, 32, 32, 32))
+    vec = opc.flatten_params(params).astype(np.float32)
+    params32 = opc.unflatten_params(vec)                 # the FP32 masters the GPU holds
+    net = firm.PCNet(max_batch=2)
+    net.set_params(vec)
+    out = host(net.forward(dev(f)))
+    for b in range(2):
+        ref, _ = opc.net_forward(f[b].astype(np.float32).astype(np.float64), params32, emulate_bf16=True)
+        assert rel(out[b], ref) < 1e-4
+
+
+def test_loss_and_gradients_match_oracle(firm):
+    """Probe loss and every parameter gradient for a batch of two samples at N = 16."""
+    N = 16
+    rng = np.random.default_rng(3)
+    params = _params(4)
+    vec = opc.flatten_params(params).astype(np.float32)
+    params32 = opc.unflatten_params(vec)
+    f = (0.3 * rng.standard_normal((2, 32, 32, 32))).astype(np.float32)
+    A = rng.uniform(0.5, 2.0, (2, N, N, N)).astype(np.float32)
+    Bs = rng.uniform(0.1, 0.6, (2, N, N, N)).astype(np.float32)
+    sumc = np.array([1.7e3, 2.2e3])
+    ker0 = np.array([2.0, 3.5])
+    net = firm.PCNet(max_batch=2)
+    net.set_params(vec)
+    loss, g = net.loss_grad(dev(f), N, dev(A), dev(Bs), sumc, ker0)
+    ref_loss, ref_g = 0.0, None
+    for b in range(2):
+        # C enters the loss only through sum C: a constant field with that sum
+        C = np.full((N, N, N), sumc[b] / N ** 3)
+        L, grads, _ = opc.loss_and_grads(f[b].astype(np.float64), params32, N, ker0[b], A[b].astype(np.float64),
+                                         Bs[b].astype(np.float64), C, emulate_bf16=True)
+        ref_loss += L / 2
+        flat = opc.flatten_params(grads) / 2
+        ref_g = flat if ref_g is None else ref_g + flat
+    assert abs(loss - ref_loss) < 1e-5 * abs(ref_loss)
+    # per-layer comparison (gradients differ in scale between layers)
+    k = 0
+    for (w, b) in params32:
+        for arr in (w, b):
+            n = arr.size
+            assert rel(g[k:k + n], ref_g[k:k + n]) < 1e-3, k
+            k += n
+
+
+@pytest.mark.parametrize("N", [16, 32])
+def test_kernel_features_match_oracle(firm, N):
+    R, _, _, _ = small_geometry(N, 5, 200 + N)
+    Ker = ofirm.kernel_direct(N, R).real
+    K32 = ker_to_centred(Ker, N).astype(np.float32)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(K32))
+    feat = host(plan.kernel_features(1e-2))
+    c = ofirm.circulant_first_column(K32[1:, 1:, 1:].astype(np.float64), N)
+    khat = np.fft.fftn(c).real / (2 * N) ** 3
+    ref = opc.pool_features(khat, float(K32[N, N, N]), 1e-2)
+    assert np.max(np.abs(feat - ref)) < 1e-4
+
+
+def test_precond_from_output_matches_oracle(firm):
+    N = 32
+    R, _, _, _ = small_geometry(N, 3, 7)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(ker_to_centred(ofirm.kernel_direct(N, R).real, N)))
+    o = np.random.default_rng(5).standard_normal((32, 32, 32))
+    d = host(plan.precond_from_output(dev(o)))
+    ker0 = float(np.float32(ofirm.kernel_direct(N, R).real[N - 1, N - 1, N - 1]))
+    ref = opc.diagonal(o.astype(np.float32).astype(np.float64), N, ker0)
+    assert rel(d, ref) < 1e-5
+
+
+def test_probe_statistics_match_oracle(firm):
+    N = 16
+    R, _, _, _ = small_geometry(N, 6, 9)
+    Ker = ofirm.kernel_direct(N, R).real
+    K32 = ker_to_centred(Ker, N).astype(np.float32)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(K32))
+    probes = np.random.default_rng(11).standard_normal((3, N, N, N)).astype(np.float32)
+    lam = 0.5
+    A, B, sumc = plan.probe_stats(dev(probes), lam)
+    Kf = K32[1:, 1:, 1:].astype(np.float64)
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Kf, v).real + lam * v
+    Ar, Br, Cr = opc.probe_statistics(apply, N, probes.astype(np.float64))
+    assert rel(host(A), Ar) < 1e-5
+    assert rel(host(B), Br) < 1e-5
+    assert abs(sumc - Cr.sum()) < 1e-6 * Cr.sum()
+
+
+def test_training_reduces_loss_and_pcg_beats_cg(firm):
+    """A short training run on kernels of random view sets (N = 32) lowers the probe loss, and on a
+    held-out view set PCG with the trained diagonal needs fewer iterations than plain CG to 1e-5."""
+    from paper_1307_5824_amd import synth
+    N, M = 32, 600
+    lam_rel = 1e-2
+    rng = np.random.default_rng(21)
+    net = firm.PCNet(max_batch=4)
+    net.set_params(opc.flatten_params(opc.init_params(32, seed=5)).astype(np.float32))
+    data = []
+    for s in range(5):
+        R = synth.mixed_rotations(M, float(rng.uniform(0, 20)), 0.1, rng)
+        plan = firm.Plan(N, R, lambda_relative=1)
+        plan.kernel_precompute()
+        feat = plan.kernel_features(lam_rel)
+        probes = plan.synth_normals(1234 + s, 0, (4, N, N, N))
+        A, B, sumc = plan.probe_stats(probes, lam_rel)
+        data.append((feat, A, B, sumc, plan.kernel_get()[N, N, N].item(), plan))
+    train, held = data[:4], data[4]
+    feats = torch.stack([d[0] for d in train])
+    As = torch.stack([d[1] for d in train])
+    Bs = torch.stack([d[2] for d in train])
+    sumc = [d[3] for d in train]
+    ker0 = [d[4] for d in train]
+    l0, _ = net.loss_grad(feats, N, As, Bs, sumc, ker0, with_grad=False)
+    for it in range(60):
+        net.train_step(feats, N, As, Bs, sumc, ker0, 2e-3)
+    l1, _ = net.loss_grad(feats, N, As, Bs, sumc, ker0, with_grad=False)
+    print(f"probe loss {l0:.4f} -> {l1:.4f}", flush=True)
+    assert l1 < l0
+    feat, A, B, sc, k0, plan = held
+    atb = torch.randn((N, N, N), device="cuda")
+    _, r_cg = plan.cg_solve(atb, lam_rel, 1e-5, 3000)
+    d = plan.precond_from_output(net.forward(feat[None]))
+    _, r_pcg = plan.cg_solve(atb, lam_rel, 1e-5, 3000, precond=d)
+    print("cg", r_cg["iters"], "learned pcg", r_pcg["iters"], flush=True)
+    assert r_pcg["iters"] < r_cg["iters"]

@@ -142,3 +142,19 @@ def test_untrained_network_is_inverse_pooled_spectrum():
     assert np.allclose(o, -f)
     d = pcnet.diagonal(o, G, 2.0)
     assert np.allclose(d, np.exp(-f) / 2.0)
+
+
+def test_bf16_rounding():
+    """Round-to-nearest-even to 8 significant bits: exact for representable values, ties to even."""
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -8, -2.5, 0.0])
+    got = pcnet.bf16(vals)
+    assert list(got) == [1.0, 1.0, 1.0 + 2 ** -7, 1.0 + 2 ** -6, -2.5, 0.0]
+
+
+def test_flatten_roundtrip():
+    params = pcnet.init_params(32, seed=3, zero_last=False)
+    vec = pcnet.flatten_params(params)
+    assert vec.size == 57121
+    back = pcnet.unflatten_params(vec)
+    for (w, b), (w2, b2) in zip(params, back):
+        assert np.array_equal(w, w2) and np.array_equal(b, b2)
