@@ -76,6 +76,32 @@ def cpu_baseline(N, seed=0):
                       f"(numpy single-threaded FFTs, random even kernel): {dt:.1f} s"}
 
 
+def counter_workload(args, firm, synth, torch):
+    """Products at the workload's N on a random even kernel, then one plain device copy of
+    COPY_BYTES: the copy's FETCH_SIZE / WRITE_SIZE per byte calibrate the counters."""
+    N = synth.WORKLOADS[args.workload].N
+    R = [[1.0, 0, 0, 0, 1.0, 0, 0, 0, 1.0]]
+    plan = firm.Plan(N, R)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    K = torch.randn((2 * N,) * 3, device="cuda", generator=g)
+    K = 0.5 * (K + torch.flip(K, dims=(0, 1, 2)).roll((1, 1, 1), dims=(0, 1, 2)))
+    plan.kernel_set(K.contiguous())
+    x = torch.randn((N, N, N), device="cuda", generator=g)
+    y = torch.empty_like(x)
+    for _ in range(args.apply_reps):
+        plan.apply_AtA(x, 0.1, y)
+    src = torch.ones(COPY_BYTES // 4, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_workload": f"N={N}", "applies": args.apply_reps, "copy_bytes": COPY_BYTES}),
+          flush=True)
+
+
+COPY_BYTES = 256 * 1024 * 1024
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +113,9 @@ def main():
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["all", "apply"], default="all",
+                    help="apply: only the N^3 products on a random even kernel plus a 256 MiB device copy "
+                         "(the workload of the hardware-counter runs and their calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU layout is a "
@@ -99,6 +128,9 @@ def main():
     from paper_1307_5824_amd import firm, synth
 
     torch.cuda.set_device(0)
+    if args.only == "apply":
+        counter_workload(args, firm, synth, torch)
+        return
     inp = synth.make_inputs(args.workload)
     wl = inp.workload
     N = wl.N
@@ -128,15 +160,17 @@ def main():
         torch.cuda.synchronize()
         return [e[i].elapsed_time(e[i + 1]) for i in range(4)], rep
 
-    for _ in range(args.warmup):
-        step()
+    for i in range(args.warmup):
+        ph, _ = step()
+        print(f"warmup {i}: phases ms {[round(v, 1) for v in ph]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     phases, reps = [], []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         ph, rep = step()
         phases.append(ph)
         reps.append(rep)
+        print(f"step {i}: phases ms {[round(v, 1) for v in ph]}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ph = np.mean(np.array(phases), axis=0)

@@ -10,9 +10,19 @@
 // tile (or one tile and a range of images): it tests every image plane of its
 // range against the tile's circumscribed sphere, enumerates the disk points of
 // the surviving images whose cell floor(t + L/2) lies in the tile, and
-// accumulates their full W^3 stencils into a (T + W)^3 LDS tile with LDS
-// atomics; the tile is then added to the global grid with one atomic per cell.
-// Each point is spread exactly once.  Only the half disk (k1 > 0, or k1 = 0 and
+// accumulates their full W^3 stencils into a (T + W)^3 LDS tile; the tile is
+// then added to the global grid with one atomic per cell.  Each point is spread
+// exactly once.
+//
+// The LDS accumulation uses no atomics (LDS float atomics run at a fraction of
+// the plain read/write rate on this chip).  Each wavefront owns a slab of rows
+// (first tile axis) of the padded tile.  The per-point window weights are
+// computed once, one thread per point, and staged in LDS; then every wavefront
+// walks the staged points whose W rows meet its slab, with its lanes on the
+// W x W footprint of the other two axes: all W rows are read, updated and
+// written back inside the slab.  Within one instruction the lanes' cells are
+// distinct and no two wavefronts write the same row, so the plain
+// read-modify-write is race-free.  Only the half disk (k1 > 0, or k1 = 0 and
 // k2 > 0) is spread: its partner -k is folded in (Ker is real and even; for A*b
 // the pair (k, -k) gives the real part exactly), and k = 0 is added afterwards
 // in closed form.
@@ -23,7 +33,6 @@
 #include "firm_internal.h"
 
 #define KB_DEG 10
-#define SP_THREADS 256
 #define SP_QCAP 1024
 
 namespace {
@@ -57,13 +66,41 @@ __device__ __forceinline__ void kb_weights(const float* __restrict__ poly, float
     }
 }
 
-template <int T, int W, bool CPLX>
-__global__ void __launch_bounds__(SP_THREADS) k_spread(SpreadArgs a) {
+// Smallest LDS row pitch >= PT at which the W x W footprint cells j2 * pitch + j3 of one
+// instruction fall in distinct banks (64 banks of 4 bytes).
+constexpr int row_pitch(int PT, int W) {
+    for (int rp = PT; rp < PT + 32; ++rp) {
+        bool ok = true;
+        for (int a = 0; a < W * W && ok; ++a)
+            for (int b = a + 1; b < W * W && ok; ++b)
+                if (((a / W) * rp + a % W) % 64 == ((b / W) * rp + b % W) % 64) ok = false;
+        if (ok) return rp;
+    }
+    return PT;
+}
+
+template <int T, int W, bool CPLX, int NTH>
+__global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
+    constexpr int SP_THREADS = NTH, SP_WAVES = NTH / 64;
     constexpr int PT = T + W;
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;
-    constexpr int NV = CPLX ? 2 : 1;
-    __shared__ float tile[NCELL * NV];
+    constexpr int H = (PT + SP_WAVES - 1) / SP_WAVES;  // rows per wavefront slab
+    constexpr int RP = row_pitch(PT, W);               // LDS pitch of a tile row (bank-conflict free)
+    constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
+    constexpr int NR = SP_WAVES * H;                   // planes, padded to whole slabs
+    constexpr int NV = CPLX ? 2 : 1;                   // real and imaginary parts in separate tiles
+    // staged point: for each wavefront its H slab-row weights (0 outside the window), then the
+    // window weights of axes 1 and 2; stride in floats
+    constexpr int PSTR = ((SP_WAVES * H + 2 * W) + 3) / 4 * 4;
+    static_assert(W <= 8, "window width");
+    constexpr int SP_PB = 96;                          // points staged per batch (two tiles per CU)
+    __shared__ __align__(16) float tile[NV * NR * PP];
+    __shared__ __align__(16) float pt_w[SP_PB * PSTR];
+    __shared__ int pt_lo[SP_PB];
+    __shared__ float2 pt_v[CPLX ? SP_PB : 1];
+    constexpr int NK = PT - W + 1;                     // possible first rows of a window
+    __shared__ int pt_key[SP_PB], pt_slot[SP_PB], bstart[NK + 1];
     __shared__ int img_m[SP_THREADS];
     __shared__ int img_k1[SP_THREADS], img_k2[SP_THREADS];
     __shared__ int queue[SP_QCAP];
@@ -76,7 +113,7 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread(SpreadArgs a) {
     const int L = a.L, N = a.N;
     const double halfL = 0.5 * L;
 
-    for (int i = tid; i < NCELL * NV; i += SP_THREADS) tile[i] = 0.f;
+    for (int i = tid; i < NV * NR * PP; i += SP_THREADS) tile[i] = 0.f;
     if (tid == 0) any = 0;
 
     const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
@@ -131,66 +168,152 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread(SpreadArgs a) {
             }
             __syncthreads();
             if (tid == 0 && qn > 0) any = 1;
-            for (int qi = tid; qi < qn; qi += SP_THREADS) {
-                const int e = queue[qi];
-                const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
-                const int m = img_m[sl];
-                const double* c = a.c12 + 6 * (int64_t)m;
+            const int wv = tid >> 6, lane = tid & 63;
+            const int r0 = wv * H;                                   // this wave's rows [r0, r0 + H)
+            for (int pb = 0; pb < qn; pb += SP_PB) {
+                const int nb = min(SP_PB, qn - pb);
+                // stage the batch: each of its threads computes one point's tile-relative window
+                // start and weights; wave 0 ranks the points by their first row (counting sort
+                // with ballots); each point is then written to its rank, so that the points
+                // meeting a wavefront's slab form one contiguous range
                 float ph[3][W];
-                int lo[3];
+                int lo[3] = {0, 0, 0};
+                float scale = 1.f;
+                float2 pval = make_float2(0.f, 0.f);
+                if (tid < nb) {
+                    const int e = queue[pb + tid];
+                    const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
+                    const int m = img_m[sl];
+                    const double* c = a.c12 + 6 * (int64_t)m;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
-                    // stencil stays inside the padded tile for every width
-                    const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
-                    const double left = tau - 0.5 * W;
-                    const int b0 = (int)floor(left) + 1;
-                    const float f = (float)((double)b0 - left);  // in (0, 1]
-                    kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
-                    lo[d] = b0 - (tt[d] * T - PADLO);
-                }
-                const int g = a.group ? a.group[m] : 0;
-                const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
-                float vr, vi = 0.f;
-                if (!CPLX) {
-                    vr = 2.f * h * h;
-                } else {
-                    // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
-                    const int idx = a.rowstart[k1 + N / 2] + k2;
-                    const float2 bp = a.b[(int64_t)m * a.P + idx];
-                    const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
-                    const float sr = bp.x + bm.x, si = bp.y - bm.y;
-                    float cs = 1.f, sn = 0.f;
-                    if (a.shifts) {
-                        const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
-                                                              k2 * a.shifts[2 * (int64_t)m + 1]) / N;
-                        cs = (float)cos(th);
-                        sn = (float)sin(th);
+                    for (int d = 0; d < 3; ++d) {
+                        // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
+                        // stencil stays inside the padded tile for every width
+                        const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
+                        const double left = tau - 0.5 * W;
+                        const int b0 = (int)floor(left) + 1;
+                        const float f = (float)((double)b0 - left);  // in (0, 1]
+                        kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
+                        // in [0, PT - W] for every point of the tile (clamped position); the bound
+                        // also keeps the LDS accesses inside the tile should rounding ever differ
+                        lo[d] = min(max(b0 - (tt[d] * T - PADLO), 0), PT - W);
                     }
-                    vr = h * (cs * sr - sn * si);
-                    vi = h * (cs * si + sn * sr);
+                    const int g = a.group ? a.group[m] : 0;
+                    const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
+                    if constexpr (!CPLX) {
+                        scale = 2.f * h * h;
+                    } else {
+                        // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
+                        const int idx = a.rowstart[k1 + N / 2] + k2;
+                        const float2 bp = a.b[(int64_t)m * a.P + idx];
+                        const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
+                        const float sr = bp.x + bm.x, si = bp.y - bm.y;
+                        float cs = 1.f, sn = 0.f;
+                        if (a.shifts) {
+                            const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
+                                                                  k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+                            cs = (float)cos(th);
+                            sn = (float)sin(th);
+                        }
+                        pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
+                    }
+                    pt_key[tid] = lo[0];
                 }
+                __syncthreads();
+                if (tid < 64) {
+                    constexpr int NCH = (SP_PB + 63) / 64;
+                    const int ln = tid;
+                    const uint64_t lt = (1ull << ln) - 1ull;
+                    int key[NCH];
 #pragma unroll
-                for (int j1 = 0; j1 < W; ++j1) {
+                    for (int ch = 0; ch < NCH; ++ch) key[ch] = ch * 64 + ln < nb ? pt_key[ch * 64 + ln] : -1;
+                    int run = 0;
+                    for (int v = 0; v < NK; ++v) {
+                        if (ln == 0) bstart[v] = run;
 #pragma unroll
-                    for (int j2 = 0; j2 < W; ++j2) {
-                        const float w12 = ph[0][j1] * ph[1][j2];
-                        const int base = ((lo[0] + j1) * PT + (lo[1] + j2)) * PT + lo[2];
+                        for (int ch = 0; ch < NCH; ++ch) {
+                            const uint64_t msk = __ballot(key[ch] == v);
+                            if (key[ch] == v) pt_slot[ch * 64 + ln] = run + __popcll(msk & lt);
+                            run += __popcll(msk);
+                        }
+                    }
+                    if (ln == 0) bstart[NK] = run;
+                }
+                __syncthreads();
+                if (tid < nb) {
+                    const int d = pt_slot[tid];
+                    float* q = pt_w + d * PSTR;
 #pragma unroll
-                        for (int j3 = 0; j3 < W; ++j3) {
-                            const float w = w12 * ph[2][j3];
-                            if (!CPLX) {
-                                __hip_atomic_fetch_add(&tile[base + j3], vr * w, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                            } else {
-                                __hip_atomic_fetch_add(&tile[2 * (base + j3)], vr * w, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
-                                __hip_atomic_fetch_add(&tile[2 * (base + j3) + 1], vi * w, __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                    for (int r = 0; r < SP_WAVES * H; ++r) {  // row r of the padded tile
+                        const int j1 = r - lo[0];
+                        float w = 0.f;
+#pragma unroll
+                        for (int j = 0; j < W; ++j) w = (j1 == j) ? ph[0][j] : w;
+                        q[r] = scale * w;
+                    }
+#pragma unroll
+                    for (int j = 0; j < W; ++j) {
+                        q[SP_WAVES * H + j] = ph[1][j];
+                        q[SP_WAVES * H + W + j] = ph[2][j];
+                    }
+                    pt_lo[d] = lo[0] | (lo[1] << 8) | (lo[2] << 16);
+                    if constexpr (CPLX) pt_v[d] = pval;
+                }
+                __syncthreads();
+                // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1]; the staged data of
+                // point pi + 1 is read while point pi is added
+                const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
+                const int pbeg = vlo <= vhi ? bstart[vlo] : 0, pend = vlo <= vhi ? bstart[vhi + 1] : 0;
+                constexpr int A2 = SP_WAVES * H, A3 = SP_WAVES * H + W;
+                const int jl = lane < W * W ? lane : 0;
+                const int j2 = jl / W, j3 = jl - (jl / W) * W;  // footprint cell of this lane
+                const int p0 = pbeg < pend ? pbeg : 0;
+                int lw = pt_lo[p0];
+                float rw[H], a2 = pt_w[p0 * PSTR + A2 + j2], a3 = pt_w[p0 * PSTR + A3 + j3];
+#pragma unroll
+                for (int k = 0; k < H; ++k) rw[k] = pt_w[p0 * PSTR + r0 + k];
+                float2 pv = CPLX ? pt_v[p0] : make_float2(0.f, 0.f);
+                for (int pi = pbeg; pi < pend; ++pi) {
+                    const int pn = pi + 1 < pend ? pi + 1 : pi;
+                    const float* qn_ = pt_w + pn * PSTR;
+                    const int lw_n = pt_lo[pn];
+                    float rw_n[H];
+#pragma unroll
+                    for (int k = 0; k < H; ++k) rw_n[k] = qn_[r0 + k];
+                    const float a2_n = qn_[A2 + j2], a3_n = qn_[A3 + j3];
+                    const float2 pv_n = CPLX ? pt_v[pn] : make_float2(0.f, 0.f);
+                    const int l0 = lw & 255, l1 = (lw >> 8) & 255, l2 = lw >> 16;
+                    if (lane < W * W) {
+                        // every row of the slab is read, updated and written back (weight 0 for the
+                        // rows outside the point's window): no branches between reads and writes
+                        const float w23 = a2 * a3;
+                        const int cb = r0 * PP + (l1 + j2) * RP + l2 + j3;
+                        if constexpr (!CPLX) {
+                            float v[H];
+#pragma unroll
+                            for (int k = 0; k < H; ++k) v[k] = tile[cb + k * PP];
+#pragma unroll
+                            for (int k = 0; k < H; ++k) tile[cb + k * PP] = fmaf(rw[k], w23, v[k]);
+                        } else {
+                            const float wr = w23 * pv.x, wi = w23 * pv.y;
+                            float vr[H], vi[H];
+#pragma unroll
+                            for (int k = 0; k < H; ++k) {
+                                vr[k] = tile[cb + k * PP];
+                                vi[k] = tile[NR * PP + cb + k * PP];
+                            }
+#pragma unroll
+                            for (int k = 0; k < H; ++k) {
+                                tile[cb + k * PP] = fmaf(rw[k], wr, vr[k]);
+                                tile[NR * PP + cb + k * PP] = fmaf(rw[k], wi, vi[k]);
                             }
                         }
                     }
+                    lw = lw_n; a2 = a2_n; a3 = a3_n; pv = pv_n;
+#pragma unroll
+                    for (int k = 0; k < H; ++k) rw[k] = rw_n[k];
                 }
+                __syncthreads();
             }
             __syncthreads();
         }
@@ -200,16 +323,17 @@ __global__ void __launch_bounds__(SP_THREADS) k_spread(SpreadArgs a) {
     const int o0 = tt[0] * T - PADLO, o1 = tt[1] * T - PADLO, o2 = tt[2] * T - PADLO;
     for (int i = tid; i < NCELL; i += SP_THREADS) {
         const int l0 = i / (PT * PT), l1 = (i / PT) % PT, l2 = i % PT;
+        const int li = l0 * PP + l1 * RP + l2;
         // grid index = position mod L, position = cell - L/2
         const int g0 = ((o0 + l0 - L / 2) % L + L) % L;
         const int g1 = ((o1 + l1 - L / 2) % L + L) % L;
         const int g2 = ((o2 + l2 - L / 2) % L + L) % L;
         const int64_t gi = ((int64_t)g0 * L + g1) * L + g2;
         if (!CPLX) {
-            const float v = tile[i];
+            const float v = tile[li];
             if (v != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, v);
         } else {
-            const float vr = tile[2 * i], vi = tile[2 * i + 1];
+            const float vr = tile[li], vi = tile[NR * PP + li];
             float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
             if (vr != 0.f) unsafeAtomicAdd(gp, vr);
             if (vi != 0.f) unsafeAtomicAdd(gp + 1, vi);
@@ -280,7 +404,9 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ o, int64
 
 int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
 
-template <int T, bool CPLX>
+// Ker (real tile): 8 wavefronts with 3-row slabs; A*b (two tiles, re and im): 4 with 5-row slabs,
+// so that two workgroups fit the LDS of a compute unit in both cases.
+template <int T, bool CPLX, int NTH = CPLX ? 256 : 512>
 hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* grid, const float2* b) {
     SpreadArgs a;
     a.N = p->N; a.M = p->M; a.L = L; a.nt = (L + T - 1) / T;
@@ -290,11 +416,11 @@ hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* g
     a.b = b; a.shifts = p->shifts; a.rowstart = p->rowstart; a.P = p->P;
     if (nwork == 0) return hipSuccess;
     switch (p->kbw) {
-        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
-        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
-        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
-        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
-        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX>), dim3(nwork), dim3(SP_THREADS), 0, p->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
