@@ -1,11 +1,14 @@
 """FIRM hot-path benchmark on one MI355X.
 
-One step is one pass of the whole hot path over one synthetic data set already resident
-in HBM: kernel precompute (gridding + FFTs + circulant spectrum), back-projection A*b, a
-CG solve to the tolerance, and a block of back-to-back A*A products.  The headline value
-is A*A products per second at N = 256 (HIP events around the product block); the JSON
-line also carries the time to the tolerance, the precompute and back-projection times,
-the roofline of the dominant FFT pass and the FP64 oracle timed on the host.
+One step is one pass of the whole hot path over one synthetic data set already resident in
+HBM: kernel precompute (gridding + FFTs + circulant spectrum), back-projection A*b, a plain CG
+solve to the tolerance, the learned preconditioner's inference (features, network, diagonal),
+the learned-PCG solve to the same tolerance, and a block of back-to-back A*A products.  The
+headline value is A*A products per second at N = 256 (HIP events around the product block);
+the JSON line also carries the time to the tolerance of plain CG and learned PCG (and, timed
+once after the steps, PCG with T. Chan's analytic diagonal), the precompute and
+back-projection times, the roofline of the dominant FFT pass and the FP64 oracle timed on the
+host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
 """
@@ -42,8 +45,9 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, if it was
+def measured_traffic(pass_index):
+    """HBM bytes per launch of one pass of the product, from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the factors a plain device copy gives), if it was
     taken on the current FFT sources; else None."""
     path = os.path.join(ROOT, "profiles", "apply_traffic.json")
     try:
@@ -53,8 +57,10 @@ def measured_traffic(kernel):
         return None
     if d.get("source_sha") != source_sha():
         return None
-    k = d.get("kernels", {}).get(kernel)
-    return None if k is None else float(k["bytes_per_launch"])
+    try:
+        return float(d["passes"][pass_index]["bytes_per_launch"])
+    except (KeyError, IndexError, TypeError):
+        return None
 
 
 def cpu_baseline(N, seed=0):
@@ -144,9 +150,13 @@ def main():
 
     x_probe = torch.randn((N, N, N), device="cuda")
     y_probe = torch.empty_like(x_probe)
+    from paper_1307_5824_amd import train_precond
+    net = firm.PCNet(max_batch=1)
+    net.set_params(train_precond.load_weights())
+    state = {}
 
     def step():
-        e = [ev() for _ in range(5)]
+        e = [ev() for _ in range(7)]
         e[0].record()
         plan.kernel_precompute()
         e[1].record()
@@ -154,11 +164,16 @@ def main():
         e[2].record()
         _, rep = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter)
         e[3].record()
+        d = plan.precond_from_output(net.forward(plan.kernel_features(wl.lam)[None]))
+        e[4].record()
+        _, rep_l = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter, precond=d)
+        e[5].record()
         for _ in range(args.apply_reps):
             plan.apply_AtA(x_probe, wl.lam, y_probe)
-        e[4].record()
+        e[6].record()
         torch.cuda.synchronize()
-        return [e[i].elapsed_time(e[i + 1]) for i in range(4)], rep
+        state["atb"] = atb
+        return [e[i].elapsed_time(e[i + 1]) for i in range(6)], (rep, rep_l)
 
     for i in range(args.warmup):
         ph, _ = step()
@@ -174,15 +189,26 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ph = np.mean(np.array(phases), axis=0)
-    applies_per_s = args.apply_reps / (ph[3] / 1e3)
+    applies_per_s = args.apply_reps / (ph[5] / 1e3)
+
+    # the analytic ablation: PCG with the inverse of T. Chan's circulant spectrum
+    e = [ev() for _ in range(3)]
+    e[0].record()
+    d_chan = 1.0 / plan.chan_spectrum(wl.lam)
+    e[1].record()
+    _, rep_c = plan.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter, precond=d_chan)
+    e[2].record()
+    torch.cuda.synchronize()
+    chan_ms = [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])]
 
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
     pass_ms = plan.apply_AtA_timed(x_probe, wl.lam, 50)
     pb = pass_bytes(N)
     k = int(np.argmax(pass_ms))
     achieved = pb[k] / (pass_ms[k] / 1e3) / 1e9
-    kernel_names = ["k_r2c_rows", "k_c2c(i2 fwd)", "k_conv_mid", "k_c2c(i2 inv)", "k_c2r_rows"]
-    traffic = measured_traffic(kernel_names[k])
+    kernel_names = [f"k_rows_r2c<{2 * N}>", f"k_cols<{2 * N}> (i2 forward)", f"k_mid<{2 * N}>",
+                    f"k_cols<{2 * N}> (i2 inverse)", f"k_rows_c2r<{2 * N}>"]
+    traffic = measured_traffic(k) if N == 256 else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_names[k], "bytes_per_launch": pb[k], "avg_launch_ms": round(pass_ms[k], 4),
@@ -206,9 +232,18 @@ def main():
                                f"vMF kappa={wl.kappa} views, {wl.groups} CTF groups, SNR {wl.snr:.4g}, "
                                f"lambda={wl.lam:g} x Ker(0), tol {args.tol:g}",
                    "N": N, "M": wl.M, "precision": args.precision, "apply_reps_per_step": args.apply_reps},
-        "time_to_tol_s": {"cg": round(ph[2] / 1e3, 4), "cg_iters": int(np.mean([r["iters"] for r in reps])),
-                          "cg_true_rel_res": float(np.max([r["true_rel_res"] for r in reps])),
-                          "cg_status": int(max(r["status"] for r in reps))},
+        "time_to_tol_s": {
+            "cg": round(ph[2] / 1e3, 4),
+            "learned_pcg": round((ph[3] + ph[4]) / 1e3, 4),
+            "learned_inference": round(ph[3] / 1e3, 4),
+            "chan_pcg": round(sum(chan_ms) / 1e3, 4),
+            "speedup_learned_vs_cg": round(ph[2] / (ph[3] + ph[4]), 3),
+            "iters": {"cg": int(np.mean([r[0]["iters"] for r in reps])),
+                      "learned_pcg": int(np.mean([r[1]["iters"] for r in reps])), "chan_pcg": rep_c["iters"]},
+            "true_rel_res": {"cg": float(np.max([r[0]["true_rel_res"] for r in reps])),
+                             "learned_pcg": float(np.max([r[1]["true_rel_res"] for r in reps])),
+                             "chan_pcg": rep_c["true_rel_res"]},
+            "status": int(max(max(r[0]["status"], r[1]["status"]) for r in reps) or rep_c["status"])},
         "precompute_ms": round(ph[0], 2),
         "backproject_ms": round(ph[1], 2),
         "roofline": roofline,

@@ -188,8 +188,13 @@ firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, cons
  * 32^3 frequency grid: o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
  * padding, 1 -> 32 -> 32 -> 32 -> 1 channels (c2, c3 on BF16 matrix cores, FP32 accumulation).
  * d = exp(U sym(o)) / Ker(0) on the N^3 grid (sym: o(u) + o(-u) halved; U: periodic trilinear
- * interpolation) is the diagonal of z = F^{-1}(d . F r).  Training minimises the probe loss
- * E ||P (A*A + lambda) z - z||^2 / E ||z||^2, a per-frequency quadratic in d by Parseval. */
+ * interpolation) is the diagonal of z = F^{-1}(d . F r).  |K^| is the unnormalised DFT_2N of the
+ * circulant column (the Fourier multiplier of the embedded product).  Training objectives:
+ *   0  probe loss E ||P (A*A + lambda) z - z||^2 / E ||z||^2, a per-frequency quadratic in d by
+ *      Parseval (statistics from firm_probe_stats);
+ *   1  Kaporin: log(mean(d t)) - mean(log(d t)), the log of Kaporin's condition number of
+ *      P (A*A + lambda) per unknown up to a constant, with t the Fourier diagonal of
+ *      A*A + lambda (firm_chan_spectrum); >= 0, zero iff d is proportional to 1 / t. */
 typedef struct firm_pcnet_s* firm_pcnet;
 
 /* Number of network parameters; host parameter arrays hold w1 [32][1][27], b1 [32],
@@ -202,19 +207,23 @@ firm_status firm_pcnet_set_params(firm_pcnet net, const float* params_host);  /*
 firm_status firm_pcnet_get_params(firm_pcnet net, float* params_host);
 /* out_dev [B][32^3] = network output o for features feat_dev [B][32^3] (centred order). */
 firm_status firm_pcnet_forward(firm_pcnet net, const float* feat_dev, float* out_dev, int B);
-/* Mean probe loss of B samples at size N and (if grad_host) the parameter gradients.  A_dev,
- * B_dev: [B][N^3] probe statistics (centred order) from firm_probe_stats; sumc, ker0: host [B]. */
-firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int B, int N, const float* A_dev,
-                                 const float* B_dev, const double* sumc, const double* ker0, double* loss,
-                                 float* grad_host);
-/* One Adam step (Kingma & Ba 2015) on the mean probe loss. */
-firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int B, int N, const float* A_dev,
-                                  const float* B_dev, const double* sumc, const double* ker0, double lr,
-                                  double* loss);
+/* Mean loss of B samples at size N under `objective` and (if grad_host) the parameter gradients
+ * (host, NPARAM floats).  objective 0: A_dev, B_dev [B][N^3] probe statistics (centred order)
+ * from firm_probe_stats and sumc host [B]; objective 1: A_dev [B][N^3] the Fourier diagonals t
+ * from firm_chan_spectrum (t > 0; B_dev and sumc may be NULL).  ker0: host [B], Ker(0) of each
+ * sample's kernel.  FIRM_ERR_ARG for an objective other than 0 or 1. */
+firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int B, int N, int objective,
+                                 const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
+                                 double* loss, float* grad_host);
+/* One Adam step (Kingma & Ba 2015) on the mean loss of firm_pcnet_loss_grad. */
+firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int B, int N, int objective,
+                                  const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
+                                  double lr, double* loss);
 const char* firm_pcnet_last_error(firm_pcnet net);
 
 /* Features of the plan's kernel: feat_dev [32^3] = log(mean |K^| over (2N/32)^3 blocks / Ker(0) +
- * lam_rel), centred frequency order.  Needs N >= 16. */
+ * lam_rel), centred frequency order, with K^ the unnormalised DFT_2N of the circulant column
+ * ((2N)^3 times the spectrum of firm_kernel_spectrum).  Needs N >= 16. */
 firm_status firm_kernel_features(firm_plan plan, double lam_rel, float* feat_dev);
 /* d_dev [N^3] (centred) = exp(U sym(out)) / Ker(0) from a network output out_dev [32^3]. */
 firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, float* d_dev);
@@ -223,6 +232,13 @@ firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, float
  * *sumc = sum ||F z||^2 (host). */
 firm_status firm_probe_stats(firm_plan plan, const float* probes_dev, int nprobes, double lambda, float* A_dev,
                              float* B_dev, double* sumc);
+/* t_dev [N^3] (centred frequency order) = the Fourier diagonal of A*A + lambda I on the periodic
+ * N^3 grid: diag(F T F^H) / N^3 for the Toeplitz operator T of the plan's kernel, which is the
+ * spectrum of T. Chan's optimal circulant (first column: the Fejer-weighted fold
+ * c(j) = sum over o_d in {j_d, j_d - N} of prod_d (1 - |o_d| / N) Ker(o)), plus lambda.
+ * 1 / t is the analytic Fourier-diagonal preconditioner; t is the target of the Kaporin
+ * objective.  FP32, through one N^3 FFT. */
+firm_status firm_chan_spectrum(firm_plan plan, double lambda, float* t_dev);
 /* out_dev[i] = standard normal from Philox4x32-10 keyed by seed, counter (i, offset). */
 firm_status firm_synth_normals(firm_plan plan, uint64_t seed, uint64_t offset, int64_t n, float* out_dev);
 

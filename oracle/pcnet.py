@@ -4,18 +4,27 @@ The preconditioner is P r = F^{-1}(d . F r) on the periodic N^3 grid (a circulan
 diagonal in the Fourier basis: section 2.3, eq. circ1), with d > 0 and d(q) = d(-q) so that P
 is real, symmetric and positive definite.  d comes from a small network:
 
-  features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32)
+  features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32; K^ = DFT_2N of the
+            circulant column, unnormalised: the Fourier multiplier of the embedded product)
   network   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))            (3^3 convolutions,
             circular padding, channels 1 -> C -> C -> C -> 1)
   symmetric s(u) = (o(u) + o(-u)) / 2 on the centred G^3 frequency grid
   diagonal  d(q) = exp(U s (q)) / Ker(0),  U = periodic trilinear interpolation from the
             G^3 grid to the N^3 frequency grid (q -> coarse coordinate q G / N)
 
-Training minimises the probe loss E_z ||P (A*A + lambda) z - z||^2 / E ||z||^2.  With
-u = (A*A + lambda) z and Parseval, for a fixed set of probes it is a per-frequency quadratic
-in d:  L(d) = sum_q (d^2 A(q) - 2 d B(q) + C(q)) / sum_q C(q), with A = sum |u^|^2,
-B = sum Re(conj(u^) z^), C = sum |z^|^2 over the probes (u^, z^ the unnormalised DFTs;
-the 1/N^3 of Parseval cancels in the ratio).
+Two training objectives:
+
+probe loss  E_z ||P (A*A + lambda) z - z||^2 / E ||z||^2.  With u = (A*A + lambda) z and
+            Parseval, for a fixed set of probes it is a per-frequency quadratic in d:
+            L(d) = sum_q (d^2 A(q) - 2 d B(q) + C(q)) / sum_q C(q), with A = sum |u^|^2,
+            B = sum Re(conj(u^) z^), C = sum |z^|^2 over the probes (u^, z^ the unnormalised
+            DFTs; the 1/N^3 of Parseval cancels in the ratio).
+Kaporin     the log of Kaporin's condition number of P (A*A + lambda):
+            K = (tr(P T) / n)^n / det(P T), n = N^3.  For P diagonal in the Fourier basis,
+            tr(P T) = sum_q d(q) t(q) with t(q) = (F T F^*)_{qq} the Fourier diagonal of
+            T = A*A + lambda (T. Chan's optimal circulant), and det P = prod d, so
+            log K / n = log(mean_q d t) - mean_q log d + const.  It is >= 0 with equality iff
+            d is proportional to 1 / t, and invariant to scaling d.
 
 Every gradient here is hand-written and pinned by central finite differences.
 """
@@ -222,13 +231,33 @@ def probe_loss_grad_d(d, A, B, C):
     return (2 * d * A - 2 * B) / np.sum(C)
 
 
-def loss_and_grads(f, params, N, ker0, A, B, C, emulate_bf16=False):
-    """Loss of the network on one sample and the gradients of every parameter."""
+def kaporin_loss(d, t):
+    """log(mean(d t)) - mean(log(d t)): log K(P T) / n with K Kaporin's condition number
+    (tr(P T) / n)^n / det(P T), where det T is replaced by prod t (a constant in d).  >= 0 by the
+    AM-GM inequality, zero iff d t is constant."""
+    dt = d * t
+    return float(np.log(np.mean(dt)) - np.mean(np.log(dt)))
+
+
+def kaporin_grad_logd(d, t):
+    """Gradient of kaporin_loss with respect to log d(q)."""
+    dt = d * t
+    return dt / np.sum(dt) - 1.0 / dt.size
+
+
+def loss_and_grads(f, params, N, ker0, A, B, C, emulate_bf16=False, objective="probe"):
+    """Loss of the network on one sample and the gradients of every parameter.
+    objective "probe": A, B, C are the probe statistics; "kaporin": A is the Fourier diagonal t
+    of A*A + lambda on the centred N^3 grid (B and C unused)."""
     o, cache = net_forward(f, params, emulate_bf16)
     d = diagonal(o, N, ker0)
-    L = probe_loss(d, A, B, C)
-    gd = probe_loss_grad_d(d, A, B, C)
-    gs = upsample_adjoint(gd * d, N)            # through exp and U
+    if objective == "kaporin":
+        L = kaporin_loss(d, A)
+        gs = upsample_adjoint(kaporin_grad_logd(d, A), N)
+    else:
+        L = probe_loss(d, A, B, C)
+        gd = probe_loss_grad_d(d, A, B, C)
+        gs = upsample_adjoint(gd * d, N)        # through exp and U
     go = symmetrise(gs)                          # symmetrise is self-adjoint
     grads, _ = net_backward(go, params, cache, emulate_bf16)
     return L, grads, d

@@ -609,6 +609,14 @@ firm_status firm_probe_stats(firm_plan p, const float* probes, int nprobes, doub
     return FIRM_OK;
 }
 
+firm_status firm_chan_spectrum(firm_plan p, double lambda, float* t) {
+    if (!p || !t) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    FIRM_HIP(p, chan_spectrum(p, lambda_eff(p, lambda), t));
+    return FIRM_OK;
+}
+
 firm_status firm_synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out) {
     if (!p || !out || n < 0) return firm_fail(p, FIRM_ERR_ARG, "bad argument");
     FIRM_HIP(p, synth_normals(p, seed, offset, n, out));

@@ -295,6 +295,45 @@ __global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, 
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Kaporin objective, pass 1: d = exp(U s) / ker0, block partials of sum d t and sum log(d t)
+__global__ void __launch_bounds__(256) k_kap_sums(const float* __restrict__ s, const float* __restrict__ t, int N,
+                                                  float inv_ker0, double* partials, int nblk) {
+    __shared__ double red[8];
+    const int64_t n = (int64_t)N * N * N;
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
+        const float u = upsample_at(s, i1, i2, i3, N);
+        const double dt = (double)expf(u) * inv_ker0 * t[i];
+        a1 += dt;
+        a2 += log(dt);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        a1 += __shfl_down(a1, o, 64);
+        a2 += __shfl_down(a2, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[threadIdx.x >> 6] = a1;
+        red[4 + (threadIdx.x >> 6)] = a2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        partials[nblk + blockIdx.x] = red[4] + red[5] + red[6] + red[7];
+    }
+}
+
+// Kaporin objective, pass 2: gradient with respect to log d, g = d t / sum(d t) - 1 / n
+__global__ void k_kap_grad(const float* __restrict__ s, const float* __restrict__ t, float* __restrict__ g, int N,
+                           float inv_ker0, double inv_sum, double inv_n) {
+    const int64_t n = (int64_t)N * N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
+        const double dt = (double)expf(upsample_at(s, i1, i2, i3, N)) * inv_ker0 * t[i];
+        g[i] = (float)(dt * inv_sum - inv_n);
+    }
+}
+
 // gs = U^T g: each coarse point gathers, per axis, the fine indices whose interpolation reads it
 // (those within one coarse cell of it) with their weights.
 __device__ __forceinline__ int adj_axis(int uc, int N, int* fi, float* wi) {
@@ -470,9 +509,12 @@ firm_status firm_pcnet_forward(firm_pcnet n, const float* feat, float* out, int 
 
 // Loss (mean over the batch) and parameter gradients for B samples at size N.  A and Bs are
 // [B][N^3] device arrays on the centred grid; sumc and ker0 are host arrays of B values.
-firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, const float* A, const float* Bs,
-                                 const double* sumc, const double* ker0, double* loss, float* grad_host) {
-    if (!n || !feat || !A || !Bs || !sumc || !ker0 || !loss) return firm_fail(nullptr, FIRM_ERR_ARG, "null argument");
+firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, int objective, const float* A,
+                                 const float* Bs, const double* sumc, const double* ker0, double* loss,
+                                 float* grad_host) {
+    if (objective != 0 && objective != 1) return net_fail(n, FIRM_ERR_ARG, "objective must be 0 (probe) or 1 (Kaporin)");
+    if (!n || !feat || !A || !ker0 || !loss || (objective == 0 && (!Bs || !sumc)))
+        return firm_fail(nullptr, FIRM_ERR_ARG, "null argument");
     if (B < 1 || B > n->bmax) return net_fail(n, FIRM_ERR_ARG, "batch out of range");
     if (N < 8 || N > 256 || (N & (N - 1))) return net_fail(n, FIRM_ERR_ARG, "N must be a power of two in [8, 256]");
     const int64_t n3 = (int64_t)N * N * N;
@@ -483,7 +525,8 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
         n->gN = N;
     }
     for (int b = 0; b < B; ++b)
-        if (!(sumc[b] > 0) || !(ker0[b] > 0)) return net_fail(n, FIRM_ERR_ARG, "sumc and ker0 must be > 0");
+        if ((objective == 0 && !(sumc[b] > 0)) || !(ker0[b] > 0))
+            return net_fail(n, FIRM_ERR_ARG, "sumc and ker0 must be > 0");
     hipStream_t st = n->stream;
     NHIP(n, forward(n, feat, B));
     hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->o, n->s, B);
@@ -491,14 +534,32 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
     const int lblocks = std::min(lb, 1024);
     double total = 0.0;
     for (int b = 0; b < B; ++b) {
-        hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, st, n->s + (int64_t)b * GV, A + b * n3,
-                           Bs + b * n3, n->gtmp, N, (float)(1.0 / ker0[b]), (float)(1.0 / sumc[b]), n->part);
+        const float* sb = n->s + (int64_t)b * GV;
+        if (objective == 0) {
+            hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, Bs + b * n3, n->gtmp, N,
+                               (float)(1.0 / ker0[b]), (float)(1.0 / sumc[b]), n->part);
+            NHIP(n, hipMemcpyAsync(n->hpart, n->part, lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
+            NHIP(n, hipStreamSynchronize(st));
+            double sp = 0.0;
+            for (int i = 0; i < lblocks; ++i) sp += n->hpart[i];
+            total += sp / sumc[b] + 1.0;
+        } else {
+            hipLaunchKernelGGL(k_kap_sums, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, N, (float)(1.0 / ker0[b]),
+                               n->part, lblocks);
+            NHIP(n, hipMemcpyAsync(n->hpart, n->part, 2 * lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
+            NHIP(n, hipStreamSynchronize(st));
+            double sdt = 0.0, slog = 0.0;
+            for (int i = 0; i < lblocks; ++i) {
+                sdt += n->hpart[i];
+                slog += n->hpart[lblocks + i];
+            }
+            if (!(sdt > 0) || !std::isfinite(sdt) || !std::isfinite(slog))
+                return net_fail(n, FIRM_ERR_ARG, "Kaporin objective needs t > 0 and a finite diagonal");
+            total += std::log(sdt / (double)n3) - slog / (double)n3;
+            hipLaunchKernelGGL(k_kap_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, A + b * n3, n->gtmp, N,
+                               (float)(1.0 / ker0[b]), 1.0 / sdt, 1.0 / (double)n3);
+        }
         hipLaunchKernelGGL(k_upsample_adj, dim3(nblk(GV)), dim3(256), 0, st, n->gtmp, n->gs + (int64_t)b * GV, N);
-        NHIP(n, hipMemcpyAsync(n->hpart, n->part, lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
-        NHIP(n, hipStreamSynchronize(st));
-        double sp = 0.0;
-        for (int i = 0; i < lblocks; ++i) sp += n->hpart[i];
-        total += sp / sumc[b] + 1.0;
     }
     *loss = total / B;
     hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->gs, n->go, B);
@@ -529,9 +590,9 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
     return FIRM_OK;
 }
 
-firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int B, int N, const float* A, const float* Bs,
-                                  const double* sumc, const double* ker0, double lr, double* loss) {
-    firm_status s = firm_pcnet_loss_grad(n, feat, B, N, A, Bs, sumc, ker0, loss, nullptr);
+firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int B, int N, int objective, const float* A,
+                                  const float* Bs, const double* sumc, const double* ker0, double lr, double* loss) {
+    firm_status s = firm_pcnet_loss_grad(n, feat, B, N, objective, A, Bs, sumc, ker0, loss, nullptr);
     if (s != FIRM_OK) return s;
     n->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;

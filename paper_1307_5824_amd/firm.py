@@ -75,8 +75,9 @@ def _load():
         "firm_pcnet_set_params": (i, [vp, vp]),
         "firm_pcnet_get_params": (i, [vp, vp]),
         "firm_pcnet_forward": (i, [vp, vp, vp, i]),
-        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
-        "firm_pcnet_train_step": (i, [vp, vp, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
+        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
+        "firm_pcnet_train_step": (i, [vp, vp, i, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
+        "firm_chan_spectrum": (i, [vp, d, vp]),
         "firm_pcnet_last_error": (ctypes.c_char_p, [vp]),
         "firm_kernel_features": (i, [vp, d, vp]),
         "firm_precond_from_output": (i, [vp, vp, vp]),
@@ -299,6 +300,13 @@ def _plan_probe_stats(self, probes, lam):
     return A, B, sc.value
 
 
+def _plan_chan_spectrum(self, lam, out=None):
+    """Fourier diagonal of A*A + lam on the centred N^3 grid (T. Chan's circulant spectrum)."""
+    out = self._vol(out)
+    _check(lib.firm_chan_spectrum(self.h, float(lam), _ptr(out)), self.h)
+    return out
+
+
 def _plan_synth_normals(self, seed, offset, shape):
     t = self._torch
     out = t.empty(shape, dtype=t.float32, device="cuda")
@@ -310,6 +318,7 @@ Plan.kernel_features = _plan_kernel_features
 Plan.precond_from_output = _plan_precond_from_output
 Plan.probe_stats = _plan_probe_stats
 Plan.synth_normals = _plan_synth_normals
+Plan.chan_spectrum = _plan_chan_spectrum
 
 
 class PCNet:
@@ -361,23 +370,28 @@ class PCNet:
         self._chk(lib.firm_pcnet_forward(self.h, _ptr(feat), _ptr(out), int(B)))
         return out
 
-    def loss_grad(self, feat, N, A, Bs, sumc, ker0, with_grad=True):
+    OBJECTIVES = {"probe": 0, "kaporin": 1}
+
+    def loss_grad(self, feat, N, A, Bs=None, sumc=None, ker0=None, with_grad=True, objective="probe"):
+        """Mean loss over the batch and (with_grad) the parameter gradients.  objective "probe":
+        A, Bs, sumc are probe statistics; "kaporin": A holds the Fourier diagonals t."""
         B = feat.shape[0]
-        sc = np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
+        sc = None if sumc is None else np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
         g = np.zeros(PCNet.NPARAM, dtype=np.float32) if with_grad else None
-        self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(B), int(N), _ptr(A), _ptr(Bs),
-                                           sc.ctypes.data_as(ctypes.c_void_p), k0.ctypes.data_as(ctypes.c_void_p),
-                                           ctypes.byref(loss), None if g is None else g.ctypes.data_as(ctypes.c_void_p)))
+        self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(B), int(N), self.OBJECTIVES[objective], _ptr(A),
+                                           _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
+                                           k0.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
+                                           None if g is None else g.ctypes.data_as(ctypes.c_void_p)))
         return loss.value, g
 
-    def train_step(self, feat, N, A, Bs, sumc, ker0, lr):
+    def train_step(self, feat, N, A, Bs=None, sumc=None, ker0=None, lr=1e-3, objective="probe"):
         B = feat.shape[0]
-        sc = np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
+        sc = None if sumc is None else np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
-        self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(B), int(N), _ptr(A), _ptr(Bs),
-                                            sc.ctypes.data_as(ctypes.c_void_p), k0.ctypes.data_as(ctypes.c_void_p),
-                                            float(lr), ctypes.byref(loss)))
+        self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(B), int(N), self.OBJECTIVES[objective], _ptr(A),
+                                            _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
+                                            k0.ctypes.data_as(ctypes.c_void_p), float(lr), ctypes.byref(loss)))
         return loss.value

@@ -166,10 +166,28 @@ def _small_workload():
     return inp, wl, b
 
 
+def _fp64_envelope(apply, b, k, ref, eta=1e-15, seeds=3):
+    """How far FP64 CG's k-th iterate moves when every product carries a seeded random relative
+    error eta (FP64 FFT rounding, ~1e-15): on an ill-conditioned system CG loses orthogonality
+    and this grows exponentially with k, so two correct FP64 implementations that differ only
+    in rounding order drift apart by about this much."""
+    worst = 0.0
+    for seed in range(seeds):
+        rng = np.random.default_rng(seed)
+
+        def noisy(v):
+            y = apply(v)
+            return y + eta * np.linalg.norm(y) / np.sqrt(y.size) * rng.standard_normal(y.shape)
+        worst = max(worst, rel(ofirm.cg(noisy, b, iters=k), ref))
+    return worst
+
+
 def test_cg_fp64_iterates_match_oracle(firm):
     """FP64 CG (precision 2, FP64 right-hand side and solution) on the small workload's geometry
-    with the oracle's kernel values: the same FP32 kernel values and FP64 A*b on both sides, so the
-    20th iterate agrees to FP64 rounding amplified by the conditioning (~1e-13), held at 1e-9."""
+    with the oracle's kernel values: the same FP32 kernel values and FP64 A*b on both sides.  The
+    10th iterate agrees to 1e-9 (the FP64 rounding envelope there is ~1e-13); at the 20th the
+    system (condition ~4e7) has amplified FP64 rounding to ~1e-5, so x_20 is held to 4x the
+    oracle's own FP64 rounding envelope."""
     inp, wl, b = _small_workload()
     N = wl.N
     Ker = ofirm.kernel_direct(N, inp.rotations).real
@@ -177,13 +195,18 @@ def test_cg_fp64_iterates_match_oracle(firm):
     atb_ref = ofirm.back_project(b.astype(np.complex128), N, inp.rotations).real
     plan = firm.Plan(N, inp.rotations, precision=2)
     plan.kernel_set(dev(K32))
-    x, rep = plan.cg_solve(dev(atb_ref, torch.float64), wl.lam, 0.0, 20)
-    assert x.dtype == torch.float64 and rep["iters"] == 20
     Kf = K32[1:, 1:, 1:].astype(np.float64)
-    x_ref = ofirm.cg(lambda v: ofirm.toeplitz_apply_fft(Kf, v).real + wl.lam * v, atb_ref, iters=20)
-    err = rel(host(x), x_ref)
-    print(f"FP64 CG x_20 rel err on equal inputs {err:.3e}", flush=True)
-    assert err < 1e-9
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Kf, v).real + wl.lam * v
+    for k, floor in ((10, 1e-9), (20, None)):
+        x, rep = plan.cg_solve(dev(atb_ref, torch.float64), wl.lam, 0.0, k)
+        assert x.dtype == torch.float64 and rep["iters"] == k
+        ref = ofirm.cg(apply, atb_ref, iters=k)
+        err = rel(host(x), ref)
+        env = _fp64_envelope(apply, atb_ref, k, ref)
+        print(f"FP64 CG x_{k} rel err on equal inputs {err:.3e}, FP64 envelope {env:.3e}", flush=True)
+        assert err < (floor if floor is not None else max(1e-9, 4 * env))
 
 
 def test_cg_small_workload_fp64_end_to_end(firm):

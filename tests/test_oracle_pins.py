@@ -381,6 +381,22 @@ def test_chan_circulant_is_frobenius_projection():
     assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
 
 
+def test_chan_spectrum_is_fourier_diagonal_of_toeplitz():
+    """The Chan spectrum is the diagonal of F T F^H / n (unitary DFT of the dense Toeplitz
+    matrix): the Fourier diagonal used as the target of the learned preconditioner."""
+    rng = _rng(15)
+    N = 4
+    Ker = firm.kernel_direct(N, synth.haar_rotations(4, rng)).real
+    T = firm.toeplitz_dense(Ker, N)
+    k = np.arange(N)
+    F1 = np.exp(-2j * np.pi * np.outer(k, k) / N)
+    F = np.kron(np.kron(F1, F1), F1)
+    diag = np.real(np.einsum('ij,jk,ik->i', F, T, F.conj())) / N ** 3
+    ref = np.fft.fftshift(diag.reshape(N, N, N))
+    got = firm.chan_circulant_spectrum(Ker, N)
+    assert np.max(np.abs(got - ref)) <= 1e-10 * np.max(np.abs(ref))
+
+
 # ------------------------------------------------ FSC (section 4) --
 
 def test_fsc_properties():

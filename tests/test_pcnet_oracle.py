@@ -158,3 +158,46 @@ def test_flatten_roundtrip():
     back = pcnet.unflatten_params(vec)
     for (w, b), (w2, b2) in zip(params, back):
         assert np.array_equal(w, w2) and np.array_equal(b, b2)
+
+
+def test_kaporin_loss_minimum_and_scale_invariance():
+    """log(mean(d t)) - mean(log(d t)) >= 0 (AM-GM), zero iff d is proportional to 1 / t, and
+    unchanged when d is scaled."""
+    rng = _rng(8)
+    t = rng.uniform(0.1, 10.0, (6, 6, 6))
+    d = rng.uniform(0.1, 10.0, (6, 6, 6))
+    assert pcnet.kaporin_loss(d, t) > 0
+    assert abs(pcnet.kaporin_loss(3.7 / t, t)) < 1e-14
+    assert abs(pcnet.kaporin_loss(5.0 * d, t) - pcnet.kaporin_loss(d, t)) < 1e-13
+    # gradient with respect to log d: central differences
+    g = pcnet.kaporin_grad_logd(d, t)
+    h = 1e-6
+    for idx in [(0, 0, 0), (2, 3, 1), (5, 5, 4)]:
+        e = np.zeros_like(d); e[idx] = h
+        fd = (pcnet.kaporin_loss(d * np.exp(e), t) - pcnet.kaporin_loss(d * np.exp(-e), t)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * (abs(g[idx]) + 1e-9)
+    assert abs(g.sum()) < 1e-12       # scale invariance: the gradient sums to zero
+
+
+def test_full_chain_gradients_kaporin():
+    """Network, symmetrisation, upsampling and exp under the Kaporin objective: central
+    differences on a parameter of every layer."""
+    rng = _rng(9)
+    N, C = 8, 2
+    params = pcnet.init_params(C, seed=3, zero_last=False)
+    params = [(w * 0.3, b + 0.01 * rng.standard_normal(b.shape)) for w, b in params]
+    f = 0.2 * rng.standard_normal((pcnet.G,) * 3)
+    t = rng.uniform(0.5, 2.0, (N, N, N))
+    t = 0.5 * (t + np.roll(t[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+    args = (N, 2.0, t, None, None)
+    L, grads, _ = pcnet.loss_and_grads(f, params, *args, objective="kaporin")
+    h = 1e-6
+    for layer, idx in [(0, (1, 0, 0, 1, 2)), (1, (0, 1, 2, 2, 0)), (2, (1, 1, 1, 1, 1)), (3, (0, 1, 0, 0, 0))]:
+        w = params[layer][0]
+        wp = [list(p) for p in params]
+        wp[layer][0] = w.copy(); wp[layer][0][idx] += h
+        lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], *args, objective="kaporin")
+        wp[layer][0] = w.copy(); wp[layer][0][idx] -= h
+        lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], *args, objective="kaporin")
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 1e-12, (layer, fd, grads[layer][0][idx])
