@@ -272,7 +272,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->kerc, (size_t)(N2 * N2 * N2)));
     chk(dalloc(&p->khat, blocked_spectrum_elems(2 * N, 2 * N, N + 1, false)));
     chk(dalloc(&p->T1, (size_t)((int64_t)N * N * p->QP)));
-    chk(dalloc(&p->T2, (size_t)((int64_t)N * N2 * p->QP)));
+    chk(dalloc(&p->T2, (size_t)fft_t2_elems(N, false)));
     chk(dalloc(&p->r, (size_t)n3));
     chk(dalloc(&p->p, (size_t)n3));
     chk(dalloc(&p->q, (size_t)n3));
@@ -371,7 +371,7 @@ firm_status ensure_fp64(firm_plan p) {
     };
     al(&p->khat64, blocked_spectrum_elems(2 * N, 2 * N, N + 1, true));
     al(&p->T1d, N * N * p->QP);
-    al(&p->T2d, N * N2 * p->QP);
+    al(&p->T2d, (size_t)fft_t2_elems((int)N, true));
     al(&p->tw64, (size_t)FIRM_TWN);
     al(&p->x64, n3);
     al(&p->r64, n3);

@@ -24,6 +24,12 @@ struct FftThr {
     static constexpr int value = (LS % 16 == 8) ? FftCfg<LS / 16, double2>::THREADS : FftCfg<LS / 16, float2>::THREADS;
 };
 
+// waves per SIMD that two workgroups of that size need (the VGPR budget of the middle pass)
+template <int LS>
+struct FftTwoBlocks {
+    static constexpr int value = FftThr<LS>::value / 128;
+};
+
 enum MapKind { MAP_FIRST = 0, MAP_CIRC = 1, MAP_CENTER = 2 };
 enum EpiKind { EPI_STORE = 0, EPI_REAL_BLOCKED = 1, EPI_KER = 2, EPI_ATB = 3 };
 
@@ -77,16 +83,23 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // z = x_a + i x_b (zero-padded from n_in to L); X_a(q) = (Z(q) + conj Z(L-q)) / 2,
 // X_b(q) = (Z(q) - conj Z(L-q)) / 2i; modes q < n_keep are stored.
 // PRO: the rows are p = src + beta * pvec (CG direction update), written back to pvec.
-template <int L, bool PRO, class S>
+template <int L, bool PRO, class S, bool HIN>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typename VecOf<S>::V* __restrict__ dst,
            int out_pitch, int n_keep, S sg, const typename VecOf<S>::V* __restrict__ tw, S* pvec,
            const double* beta_dev, const int* active) {
+    // HIN: rows zero-padded from L/2 (known at compile time: the first stage's zero inputs fold)
     using V = typename VecOf<S>::V;
     constexpr int C = FftCfg<L, V>::C, T = L / 8;
     using P = Pen<L, C, true>;
+    constexpr bool TWL = sizeof(S) == 4;
     __shared__ V lds[P::LDS];
+    __shared__ V twl[TWL ? FIRM_TWN : 1];
     if (cg_inactive(active)) return;
+    if (TWL)
+        for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
+    const V* twp = TWL ? twl : tw;
+    if (HIN) n_in = L / 2;
     const int c = P::c(), j = P::j();
     const int pr = blockIdx.x * C + c;
     const bool valid = pr < (nrows >> 1);
@@ -97,7 +110,7 @@ k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typenam
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
         S a = 0, b = 0;
-        if (valid && e < n_in) {
+        if (!(HIN && t >= 4) && valid && e < n_in) {
             const int64_t g = (int64_t)(2 * pr) * in_pitch + e;
             a = src[g];
             b = src[g + in_pitch];
@@ -110,7 +123,8 @@ k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typenam
         }
         v[t] = mkv<V>(a, b);
     }
-    fft_reg<L, C, true>(v, lds, tw, sg);
+    if (TWL) __syncthreads();  // the twiddle table is in place
+    fft_reg<L, C, true>(v, lds, twp, sg);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 8; ++t) lds[P::idx(j + t * T, c)] = v[t];
@@ -131,7 +145,7 @@ k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typenam
 
 // Half spectra (modes 0..L/2 of two real rows) -> real rows, first n_out samples.
 // y = scale * x + lam * xadd.  DOT: also a block partial of sum(xadd * y) in FP64.
-template <int L, bool DOT, class S>
+template <int L, bool DOT, class S, bool HOUT>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch, S* __restrict__ dst, int out_pitch,
            int n_out, S sg, S scale, S lam, const S* __restrict__ xadd, const typename VecOf<S>::V* __restrict__ tw,
@@ -139,9 +153,14 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
     using V = typename VecOf<S>::V;
     constexpr int C = FftCfg<L, V>::C, T = L / 8, NT = FftCfg<L, V>::THREADS;
     using P = Pen<L, C, true>;
-    __shared__ V lds[P::LDS];
-    __shared__ double red[NT / 64];
+    constexpr bool TWL = sizeof(S) == 4;
+    static_assert(P::LDS * sizeof(V) >= (NT / 64) * sizeof(double), "reduction scratch");
+    __shared__ V lds[P::LDS];  // exchange buffer; after the transform, the DOT reduction's scratch
+    __shared__ V twl[TWL ? FIRM_TWN : 1];
     if (cg_inactive(active)) return;
+    if (TWL)
+        for (int i = threadIdx.x; i < FIRM_TWN; i += NT) twl[i] = tw[i];
+    const V* twp = TWL ? twl : tw;
     const int c = P::c(), j = P::j();
     const int pr = blockIdx.x * C + c;
     const bool valid = pr < (nrows >> 1);
@@ -159,13 +178,14 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
         }
         v[t] = z;
     }
-    fft_reg<L, C, true>(v, lds, tw, sg);
+    if (TWL) __syncthreads();  // the twiddle table is in place
+    fft_reg<L, C, true>(v, lds, twp, sg);
     double acc = 0.0;
     if (valid) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             const int e = j + t * T;
-            if (e < n_out) {
+            if (HOUT ? t < 4 : e < n_out) {  // HOUT: the first L/2 samples (n_out = L/2)
 #pragma unroll
                 for (int rr = 0; rr < 2; ++rr) {
                     const int64_t g = (int64_t)(2 * pr + rr) * out_pitch + e;
@@ -181,45 +201,58 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
         }
     }
     if (DOT) {
-        const double s = block_sum<NT>(acc, red);
+        __syncthreads();  // every wavefront has finished reading the exchange buffer
+        const double s = block_sum<NT>(acc, reinterpret_cast<double*>(lds));
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
 }
 
 // Complex pencils along one axis.  Block -> (outer o, column group); CONTIG means the
 // transformed axis is contiguous (lanes along elements), otherwise lanes run along columns.
-template <int L, bool CONTIG, int MAP, int EPI, class S>
+template <int L, bool CONTIG, int MAP, int EPI, class S, int PADK>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_cols(const typename VecOf<S>::V* __restrict__ src, void* __restrict__ dstv, int ncols, int64_t s_outer,
-       int64_t s_col, int64_t s_elem, int64_t d_outer, int64_t d_col, int64_t d_elem, int n_in, int n_out, S sg,
-       const typename VecOf<S>::V* __restrict__ tw, EpiArgs ep, const int* active) {
+       int64_t s_col, int64_t s_elem, int64_t d_outer, int64_t d_col, int64_t d_elem, int64_t s_group,
+       int64_t d_group, int n_in, int n_out, S sg, const typename VecOf<S>::V* __restrict__ tw, EpiArgs ep,
+       const int* active) {
+    // PADK 1: input zero-padded from L/2; 2: only the first L/2 outputs kept (MAP_FIRST); known at
+    // compile time so that the first / last stage folds
     using V = typename VecOf<S>::V;
     constexpr int C = FftCfg<L, V>::C, T = L / 8;
     using P = Pen<L, C, CONTIG>;
+    constexpr bool TWL = sizeof(S) == 4 && !CONTIG;
     __shared__ V lds[P::LDS];
+    __shared__ V twl[TWL ? FIRM_TWN : 1];
     if (cg_inactive(active)) return;
+    if (TWL)
+        for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
+    const V* twp = TWL ? twl : tw;
+    if (PADK == 1) n_in = L / 2;
+    if (PADK == 2) n_out = L / 2;
     const int ng = (ncols + C - 1) / C;
     const int o = blockIdx.x / ng;
     const int g = blockIdx.x - o * ng;
     const int c = P::c(), j = P::j();
     const int col = g * C + c;
     const bool valid = col < ncols;
-    const V* s0 = src + o * s_outer + (int64_t)col * s_col;
+    const V* s0 = src + o * s_outer + (int64_t)g * s_group + (int64_t)c * s_col;
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
-        v[t] = (valid && e < n_in) ? s0[e * s_elem] : mkv<V>(0, 0);
+        v[t] = (!(PADK == 1 && t >= 4) && valid && e < n_in) ? s0[e * s_elem] : mkv<V>(0, 0);
     }
-    fft_reg<L, C, CONTIG>(v, lds, tw, sg);
+    if (TWL) __syncthreads();  // the twiddle table is in place
+    fft_reg<L, C, CONTIG>(v, lds, twp, sg);
     if (!valid) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
+        if (PADK == 2 && t >= 4) continue;
         bool zero;
         const int u = out_index<MAP>(j + t * T, L, n_out, zero);
         if (u < 0) continue;
         const V val = zero ? mkv<V>(0, 0) : v[t];
-        const int64_t gi = o * d_outer + (int64_t)col * d_col + (int64_t)u * d_elem;
+        const int64_t gi = o * d_outer + (int64_t)g * d_group + (int64_t)c * d_col + (int64_t)u * d_elem;
         if constexpr (EPI == EPI_STORE) {
             reinterpret_cast<V*>(dstv)[gi] = val;
         } else if constexpr (EPI == EPI_REAL_BLOCKED) {
@@ -239,41 +272,53 @@ k_cols(const typename VecOf<S>::V* __restrict__ src, void* __restrict__ dstv, in
 // Middle pass of the product: along axis 1, zero-pad the first n_in entries, forward
 // transform, multiply by the real spectrum (blocked layout [outer][group][element][C]),
 // inverse transform, keep the first n_in.
-template <int L, class S>
+template <int L, class S, bool HALF>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, int ncols, int64_t s_outer,
-      int64_t s_elem, int n_in, const typename VecOf<S>::V* __restrict__ tw, const int* active) {
+      int64_t s_elem, int64_t s_group, int n_in, const typename VecOf<S>::V* __restrict__ tw, const int* active) {
+    // HALF: the pencils are zero-padded (n_in = L / 2) and only their first half is kept, which
+    // the compiler folds into the first and last stages
     using V = typename VecOf<S>::V;
     constexpr int C = FftCfg<L, V>::C, T = L / 8;
     using P = Pen<L, C, false>;
+    // FP32: the twiddle table is copied to LDS (short-latency reads, fewer live registers); the
+    // FP64 form keeps it in global memory (its registers already bound the occupancy)
+    constexpr bool TWL = sizeof(S) == 4;
     __shared__ V lds[P::LDS];
+    __shared__ V twl[TWL ? FIRM_TWN : 1];
     if (cg_inactive(active)) return;
+    if (TWL)
+        for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
+    const V* twp = TWL ? twl : tw;
+    const int nin = HALF ? L / 2 : n_in;
     const int ng = (ncols + C - 1) / C;
     const int o = blockIdx.x / ng;
     const int g = blockIdx.x - o * ng;
     const int c = P::c(), j = P::j();
     const int col = g * C + c;
     const bool valid = col < ncols;
-    V* d0 = data + o * s_outer + col;
+    V* d0 = data + o * s_outer + (int64_t)g * s_group + c;
     const S* k0 = spec + ((int64_t)o * ng + g) * L * C + c;
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
-        v[t] = (valid && e < n_in) ? d0[e * s_elem] : mkv<V>(0, 0);
+        if (HALF && t >= 4) v[t] = mkv<V>(0, 0);  // e >= L / 2
+        else v[t] = (valid && e < nin) ? d0[e * s_elem] : mkv<V>(0, 0);
     }
-    fft_reg<L, C, false>(v, lds, tw, (S)-1);
+    if (TWL) __syncthreads();  // the twiddle table is in place
+    fft_reg<L, C, false>(v, lds, twp, (S)-1);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const S k = k0[(j + t * T) * C];
         v[t] = mkv<V>(v[t].x * k, v[t].y * k);
     }
-    fft_reg<L, C, false>(v, lds, tw, (S)1);
+    fft_reg<L, C, false>(v, lds, twp, (S)1);
     if (!valid) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
-        if (e < n_in) d0[e * s_elem] = v[t];
+        if (HALF ? t < 4 : e < nin) d0[e * s_elem] = v[t];
     }
 }
 
@@ -295,8 +340,12 @@ hipError_t launch_r2c(hipStream_t st, const S* src, int nrows, int in_pitch, int
                       const double* beta = nullptr, const int* active = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = ceil_div(nrows / 2, Cfg::C);
-    hipLaunchKernelGGL((k_rows_r2c<L, PRO, S>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch, n_in,
-                       dst, out_pitch, n_keep, sg, tw, pvec, beta, active);
+    if (2 * n_in == L)
+        hipLaunchKernelGGL((k_rows_r2c<L, PRO, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
+                           n_in, dst, out_pitch, n_keep, sg, tw, pvec, beta, active);
+    else
+        hipLaunchKernelGGL((k_rows_r2c<L, PRO, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+                           in_pitch, n_in, dst, out_pitch, n_keep, sg, tw, pvec, beta, active);
     return hipGetLastError();
 }
 
@@ -306,8 +355,12 @@ hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows
                       double* partials = nullptr, const int* active = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = ceil_div(nrows / 2, Cfg::C);
-    hipLaunchKernelGGL((k_rows_c2r<L, DOT, S>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch, dst,
-                       out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active);
+    if (2 * n_out == L)
+        hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
+                           dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active);
+    else
+        hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+                           in_pitch, dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active);
     return hipGetLastError();
 }
 
@@ -315,22 +368,41 @@ template <int L, bool CONTIG, int MAP, int EPI, class S = float>
 hipError_t launch_cols(hipStream_t st, const typename VecOf<S>::V* src, void* dst, int nouter, int ncols,
                        int64_t s_outer, int64_t s_col, int64_t s_elem, int64_t d_outer, int64_t d_col,
                        int64_t d_elem, int n_in, int n_out, S sg, const typename VecOf<S>::V* tw,
-                       EpiArgs ep = EpiArgs(), const int* active = nullptr) {
+                       EpiArgs ep = EpiArgs(), const int* active = nullptr, int64_t s_group = -1,
+                       int64_t d_group = -1) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = nouter * ceil_div(ncols, Cfg::C);
-    hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst, ncols,
-                       s_outer, s_col, s_elem, d_outer, d_col, d_elem, n_in, n_out, sg, tw, ep, active);
+    // column group strides: by default the columns are one strided sequence (group = C columns)
+    if (s_group < 0) s_group = (int64_t)Cfg::C * s_col;
+    if (d_group < 0) d_group = (int64_t)Cfg::C * d_col;
+    if (MAP == MAP_FIRST && EPI == EPI_STORE && 2 * n_in == L)
+        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 1>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+                           ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
+                           tw, ep, active);
+    else if (MAP == MAP_FIRST && EPI == EPI_STORE && 2 * n_out == L)
+        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 2>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+                           ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
+                           tw, ep, active);
+    else
+        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 0>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+                           ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
+                           tw, ep, active);
     return hipGetLastError();
 }
 
 template <int L, class S = float>
 hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec, int nouter, int ncols,
                       int64_t s_outer, int64_t s_elem, int n_in, const typename VecOf<S>::V* tw,
-                      const int* active = nullptr) {
+                      const int* active = nullptr, int64_t s_group = -1) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = nouter * ceil_div(ncols, Cfg::C);
-    hipLaunchKernelGGL((k_mid<L, S>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, ncols, s_outer, s_elem,
-                       n_in, tw, active);
+    if (s_group < 0) s_group = Cfg::C;
+    if (2 * n_in == L)
+        hipLaunchKernelGGL((k_mid<L, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, ncols, s_outer,
+                           s_elem, s_group, n_in, tw, active);
+    else
+        hipLaunchKernelGGL((k_mid<L, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, ncols, s_outer,
+                           s_elem, s_group, n_in, tw, active);
     return hipGetLastError();
 }
 
@@ -355,18 +427,20 @@ hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, fl
     else
         RET_IF((launch_r2c<L, false>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw)));
     if (ev) RET_IF(hipEventRecord(ev[1], st));
-    // B: along i2 for every (i1, q3): T1[i1][i2][q3] (N) -> T2[i1][q2][q3] (2N)
-    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T1, p->T2, N, N + 1, (int64_t)N * QP, 1, QP,
-                                                          (int64_t)L * QP, 1, QP, N, L, -1.f, p->tw, EpiArgs(),
-                                                          active)));
+    // T2 is blocked [q2][q3 group][i1][C] (C = the pencils per workgroup), so that every pencil
+    // group of the middle pass is one contiguous block
+    constexpr int C = FftCfg<L, float2>::C;
+    const int64_t ng = (N + 1 + C - 1) / C, sg_ = (int64_t)N * C, se_ = ng * (int64_t)N * C;
+    // B: along i2 for every (i1, q3): T1[i1][i2][q3] (N) -> T2[q2][g][i1][c] (2N)
+    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T1, p->T2, N, N + 1, (int64_t)N * QP, 1, QP, C, 1,
+                                                          se_, N, L, -1.f, p->tw, EpiArgs(), active, -1, sg_)));
     if (ev) RET_IF(hipEventRecord(ev[2], st));
     // C: along i1 for every (q2, q3): forward, times K^, inverse, keep i1 < N
-    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, QP, (int64_t)L * QP, N, p->tw, active)));
+    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_)));
     if (ev) RET_IF(hipEventRecord(ev[3], st));
-    // D: inverse along q2, keep i2 < N: T2[i1][q2][q3] -> T1[i1][i2][q3]
-    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, (int64_t)L * QP, 1, QP,
-                                                          (int64_t)N * QP, 1, QP, L, N, 1.f, p->tw, EpiArgs(),
-                                                          active)));
+    // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
+    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
+                                                          QP, L, N, 1.f, p->tw, EpiArgs(), active, sg_, -1)));
     if (ev) RET_IF(hipEventRecord(ev[4], st));
     // E: inverse along q3 (half spectrum -> real), crop, + lam x
     if (cg)
@@ -383,11 +457,15 @@ hipError_t apply_passes64(firm_plan p, const double* x, double* y, double lam) {
     const int N = L / 2, QP = p->QP;
     hipStream_t st = p->stream;
     RET_IF((launch_r2c<L, false, double>(st, x, N * N, N, N, p->T1d, QP, N + 1, -1.0, p->tw64)));
+    constexpr int C = FftCfg<L, double2>::C;  // T2d blocked like T2, with the FP64 pencil count
+    const int64_t ng = (N + 1 + C - 1) / C, sg_ = (int64_t)N * C, se_ = ng * (int64_t)N * C;
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE, double>(st, p->T1d, p->T2d, N, N + 1, (int64_t)N * QP, 1,
-                                                                  QP, (int64_t)L * QP, 1, QP, N, L, -1.0, p->tw64)));
-    RET_IF((launch_mid<L, double>(st, p->T2d, p->khat64, L, N + 1, QP, (int64_t)L * QP, N, p->tw64)));
-    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE, double>(st, p->T2d, p->T1d, N, N + 1, (int64_t)L * QP, 1,
-                                                                  QP, (int64_t)N * QP, 1, QP, L, N, 1.0, p->tw64)));
+                                                                  QP, C, 1, se_, N, L, -1.0, p->tw64, EpiArgs(),
+                                                                  nullptr, -1, sg_)));
+    RET_IF((launch_mid<L, double>(st, p->T2d, p->khat64, L, N + 1, se_, C, N, p->tw64, nullptr, sg_)));
+    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE, double>(st, p->T2d, p->T1d, N, N + 1, C, 1, se_,
+                                                                  (int64_t)N * QP, 1, QP, L, N, 1.0, p->tw64,
+                                                                  EpiArgs(), nullptr, sg_, -1)));
     return launch_c2r<L, false, double>(st, p->T1d, N * N, QP, y, N, N, 1.0, 1.0, lam, x, p->tw64);
 }
 
@@ -511,6 +589,11 @@ int cols_per_block_t(bool dbl) { return dbl ? FftCfg<L, double2>::C : FftCfg<L, 
 int fft_cols_per_block(int L, bool dbl) {
     DISPATCH_L(L, cols_per_block_t, dbl);
     return 0;
+}
+
+int64_t fft_t2_elems(int N, bool dbl) {
+    const int C = fft_cols_per_block(2 * N, dbl);
+    return (int64_t)2 * N * N * (((N + 1 + C - 1) / C) * C);
 }
 
 size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl) {

@@ -94,6 +94,7 @@ firm_status firm_fail(firm_plan p, firm_status s, const std::string& msg);
 // ---- fft.hip launchers (return hipError_t of the launch) ----
 hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam);
 int fft_cols_per_block(int L, bool dbl);  // pencils per workgroup of the L-point pass
+int64_t fft_t2_elems(int N, bool dbl);    // complex elements of the blocked T2 [2N][groups][N][C]
 size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl);
 hipError_t fft_khat_unblock(firm_plan p, float* out);
 hipError_t fft_forward_r2c(firm_plan p, const float* x, float2* out);  // N^3 real -> [N][N][QPn] half spectrum
