@@ -260,58 +260,75 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
                     if constexpr (CPLX) pt_v[d] = pval;
                 }
                 __syncthreads();
-                // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1]; the staged data of
-                // point pi + 1 is read while point pi is added
+                // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1], taken two at a time;
+                // when the two footprints are disjoint both points' rows are read before either is
+                // written back (two independent read-modify-write chains in flight)
                 const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
                 const int pbeg = vlo <= vhi ? bstart[vlo] : 0, pend = vlo <= vhi ? bstart[vhi + 1] : 0;
                 constexpr int A2 = SP_WAVES * H, A3 = SP_WAVES * H + W;
                 const int jl = lane < W * W ? lane : 0;
                 const int j2 = jl / W, j3 = jl - (jl / W) * W;  // footprint cell of this lane
-                const int p0 = pbeg < pend ? pbeg : 0;
-                int lw = pt_lo[p0];
-                float rw[H], a2 = pt_w[p0 * PSTR + A2 + j2], a3 = pt_w[p0 * PSTR + A3 + j3];
+                const bool act = lane < W * W;
+                struct Pt {
+                    int cb, l1, l2;
+                    float rw[H];
+                    float w23;
+                    float2 v;
+                };
+                auto load = [&](int pi, Pt& q) {
+                    const float* w = pt_w + pi * PSTR;
+                    const int lw = pt_lo[pi];
+                    q.l1 = (lw >> 8) & 255;
+                    q.l2 = lw >> 16;
+                    q.cb = r0 * PP + (q.l1 + j2) * RP + q.l2 + j3;
 #pragma unroll
-                for (int k = 0; k < H; ++k) rw[k] = pt_w[p0 * PSTR + r0 + k];
-                float2 pv = CPLX ? pt_v[p0] : make_float2(0.f, 0.f);
-                for (int pi = pbeg; pi < pend; ++pi) {
-                    const int pn = pi + 1 < pend ? pi + 1 : pi;
-                    const float* qn_ = pt_w + pn * PSTR;
-                    const int lw_n = pt_lo[pn];
-                    float rw_n[H];
+                    for (int k = 0; k < H; ++k) q.rw[k] = w[r0 + k];
+                    q.w23 = w[A2 + j2] * w[A3 + j3];
+                    q.v = CPLX ? pt_v[pi] : make_float2(0.f, 0.f);
+                };
+                // rows of the slab: read, then add weight * value (weight 0 outside the window)
+                auto rd = [&](const Pt& q, float (&vr)[H], float (&vi)[H]) {
 #pragma unroll
-                    for (int k = 0; k < H; ++k) rw_n[k] = qn_[r0 + k];
-                    const float a2_n = qn_[A2 + j2], a3_n = qn_[A3 + j3];
-                    const float2 pv_n = CPLX ? pt_v[pn] : make_float2(0.f, 0.f);
-                    const int l0 = lw & 255, l1 = (lw >> 8) & 255, l2 = lw >> 16;
-                    if (lane < W * W) {
-                        // every row of the slab is read, updated and written back (weight 0 for the
-                        // rows outside the point's window): no branches between reads and writes
-                        const float w23 = a2 * a3;
-                        const int cb = r0 * PP + (l1 + j2) * RP + l2 + j3;
-                        if constexpr (!CPLX) {
-                            float v[H];
+                    for (int k = 0; k < H; ++k) {
+                        vr[k] = tile[q.cb + k * PP];
+                        if (CPLX) vi[k] = tile[NR * PP + q.cb + k * PP];
+                    }
+                };
+                auto wr = [&](const Pt& q, const float (&vr)[H], const float (&vi)[H]) {
+                    if constexpr (!CPLX) {
 #pragma unroll
-                            for (int k = 0; k < H; ++k) v[k] = tile[cb + k * PP];
+                        for (int k = 0; k < H; ++k) tile[q.cb + k * PP] = fmaf(q.rw[k], q.w23, vr[k]);
+                    } else {
+                        const float sr = q.w23 * q.v.x, si = q.w23 * q.v.y;
 #pragma unroll
-                            for (int k = 0; k < H; ++k) tile[cb + k * PP] = fmaf(rw[k], w23, v[k]);
+                        for (int k = 0; k < H; ++k) {
+                            tile[q.cb + k * PP] = fmaf(q.rw[k], sr, vr[k]);
+                            tile[NR * PP + q.cb + k * PP] = fmaf(q.rw[k], si, vi[k]);
+                        }
+                    }
+                };
+                for (int pi = pbeg; pi < pend; pi += 2) {
+                    const bool two = pi + 1 < pend;
+                    Pt a, b;
+                    load(pi, a);
+                    load(two ? pi + 1 : pi, b);
+                    const bool apart = two && (abs(a.l1 - b.l1) >= W || abs(a.l2 - b.l2) >= W);
+                    float ar[H], ai[H], br[H], bi[H];
+                    if (act) {
+                        if (apart) {
+                            rd(a, ar, ai);
+                            rd(b, br, bi);
+                            wr(a, ar, ai);
+                            wr(b, br, bi);
                         } else {
-                            const float wr = w23 * pv.x, wi = w23 * pv.y;
-                            float vr[H], vi[H];
-#pragma unroll
-                            for (int k = 0; k < H; ++k) {
-                                vr[k] = tile[cb + k * PP];
-                                vi[k] = tile[NR * PP + cb + k * PP];
-                            }
-#pragma unroll
-                            for (int k = 0; k < H; ++k) {
-                                tile[cb + k * PP] = fmaf(rw[k], wr, vr[k]);
-                                tile[NR * PP + cb + k * PP] = fmaf(rw[k], wi, vi[k]);
+                            rd(a, ar, ai);
+                            wr(a, ar, ai);
+                            if (two) {
+                                rd(b, br, bi);
+                                wr(b, br, bi);
                             }
                         }
                     }
-                    lw = lw_n; a2 = a2_n; a3 = a3_n; pv = pv_n;
-#pragma unroll
-                    for (int k = 0; k < H; ++k) rw[k] = rw_n[k];
                 }
                 __syncthreads();
             }
