@@ -162,7 +162,7 @@ def main():
         e[1].record()
         atb = plan.backproject(b)
         e[2].record()
-        _, rep = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter)
+        x, rep = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter)
         e[3].record()
         d = plan.precond_from_output(net.forward(plan.kernel_features(wl.lam)[None]))
         e[4].record()
@@ -173,6 +173,7 @@ def main():
         e[6].record()
         torch.cuda.synchronize()
         state["atb"] = atb
+        state["x"] = x
         return [e[i].elapsed_time(e[i + 1]) for i in range(6)], (rep, rep_l)
 
     for i in range(args.warmup):
@@ -200,6 +201,23 @@ def main():
     e[2].record()
     torch.cuda.synchronize()
     chan_ms = [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])]
+
+    # the forward projector on the reconstruction, and the data residual ||A x - b|| / ||b||
+    # (slice by slice in blocks, so that no second full copy of b is formed)
+    e = [ev() for _ in range(2)]
+    e[0].record()
+    bx = plan.forward_project(state["x"])
+    e[1].record()
+    torch.cuda.synchronize()
+    fwd_ms = e[0].elapsed_time(e[1])
+    num = den = 0.0
+    for i in range(0, wl.M, 8192):
+        j = min(wl.M, i + 8192)
+        num += torch.linalg.norm(bx[i:j] - b[i:j]).double().item() ** 2
+        den += torch.linalg.norm(b[i:j]).double().item() ** 2
+    del bx
+    data_res = (num / den) ** 0.5
+    print(f"forward projection {fwd_ms:.1f} ms, data residual {data_res:.4f}", file=sys.stderr, flush=True)
 
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
     pass_ms = plan.apply_AtA_timed(x_probe, wl.lam, 50)
@@ -246,6 +264,8 @@ def main():
             "status": int(max(max(r[0]["status"], r[1]["status"]) for r in reps) or rep_c["status"])},
         "precompute_ms": round(ph[0], 2),
         "backproject_ms": round(ph[1], 2),
+        "forward_project_ms": round(fwd_ms, 2),
+        "data_rel_residual": round(data_res, 5),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

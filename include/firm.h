@@ -124,6 +124,17 @@ firm_status firm_kernel_set(firm_plan plan, const float* ker_dev);
  * spread uses the pair (k, -k) as b(k) + conj(b(-k)). */
 firm_status firm_backproject(firm_plan plan, const void* b_dev, float* atb_dev);
 
+/* The forward projector (eq. forward-projector) with the imaging model of section 3.1:
+ * b_dev (device, M x P complex64, disk order) receives
+ *   b(k, m) = h_m(|k|) exp(-i <omega_k, s_m>) sum_n V(n) exp(-i <n, xi_{k,m}>)
+ * for V_dev (device, N^3 floats, centred order: voxel i is n = i - N/2), i.e. the slices
+ * that images of V at the plan's rotations, shifts and CTFs would have.  It is the adjoint of
+ * firm_backproject: for real V and any b, <V, firm_backproject(b)> = Re <forward(V), b>.
+ * Evaluated as a type-2 non-uniform FFT with the plan's Kaiser-Bessel window on the (2N)^3
+ * grid (relative error ~1e-6 at width 7).  Every element of b_dev is written; the result
+ * satisfies b(-k) = conj b(k).  Uses the gridding workspaces (allocated on first use). */
+firm_status firm_forward_project(firm_plan plan, const float* V_dev, void* b_dev);
+
 /* y_dev = (A*A + lambda I) x_dev through the circulant embedding (eq. property,
  * embedding_circulant, circ1): pad to (2N)^3, FFT, multiply by the kernel
  * spectrum, inverse FFT, crop.  x_dev, y_dev: N^3 floats, must not alias.

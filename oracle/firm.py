@@ -84,17 +84,15 @@ def _chunks(total, size):
         yield a, min(total, a + size)
 
 
-def forward_project(V, rotations, h=None, chunk=4096):
-    """(A V)(k, m) = sum_n V_n exp(-i <n, xi_{k,m}>) h_m(||omega_k||)  (eq. forward-projector).
+def forward_project_at(V, xi, chunk=4096):
+    """sum_n V_n exp(-i <n, xi_j>) at arbitrary points xi (J, 3): the sum of eq. forward-projector.
 
     The sum over n is the separable product of the three per-axis phase
     factors exp(-i n_d xi_d); it is contracted one axis at a time.
     """
     V = np.asarray(V)
     N = V.shape[0]
-    xi = sample_points(N, rotations)
-    M, P, _ = xi.shape
-    pts = xi.reshape(-1, 3)
+    pts = np.asarray(xi, dtype=np.float64).reshape(-1, 3)
     n = voxel_coords(N)
     out = np.empty(pts.shape[0], dtype=np.complex128)
     for a, b in _chunks(pts.shape[0], chunk):
@@ -104,6 +102,15 @@ def forward_project(V, rotations, h=None, chunk=4096):
         t = np.einsum("abc,jc->jab", V, e3)            # sum over n3
         t = np.einsum("jab,jb->ja", t, e2)             # sum over n2
         out[a:b] = np.einsum("ja,ja->j", t, e1)        # sum over n1
+    return out
+
+
+def forward_project(V, rotations, h=None, chunk=4096):
+    """(A V)(k, m) = sum_n V_n exp(-i <n, xi_{k,m}>) h_m(||omega_k||)  (eq. forward-projector)."""
+    N = np.asarray(V).shape[0]
+    xi = sample_points(N, rotations)
+    M, P, _ = xi.shape
+    out = forward_project_at(V, xi.reshape(-1, 3), chunk)
     out = out.reshape(M, P)
     if h is not None:
         out = out * h

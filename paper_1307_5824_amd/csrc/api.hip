@@ -466,6 +466,14 @@ firm_status firm_backproject(firm_plan p, const void* b, float* atb) {
     return FIRM_OK;
 }
 
+firm_status firm_forward_project(firm_plan p, const float* V, void* b) {
+    if (!p || !V || !b) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    firm_status s = ensure_grid_ws(p);
+    if (s != FIRM_OK) return s;
+    FIRM_HIP(p, forward_project(p, V, (float2*)b));
+    return FIRM_OK;
+}
+
 firm_status firm_apply_AtA(firm_plan p, const float* x, float* y, double lambda) {
     if (!p || !x || !y) return firm_fail(p, FIRM_ERR_ARG, "null argument");
     if (x == y) return firm_fail(p, FIRM_ERR_ARG, "x and y must not alias");

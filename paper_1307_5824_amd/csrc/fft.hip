@@ -568,6 +568,22 @@ hipError_t fwd_r2c_passes(firm_plan p, const float* x, float2* out) {
                                                        (int64_t)N * QPn, N, N, -1.f, p->tw);
 }
 
+// Forward-projection grid, L = 2N: N^3 real u (array index i, zero-padded to L per axis) ->
+// X[q1][q2][q3] = sum_i u_i exp(-2 pi i <i, q> / L) for q1, q2 in [0, L), q3 in [0, N] (pitch QP).
+template <int L>
+hipError_t projgrid_passes(firm_plan p, const float* u, float2* t1, float2* w, float2* X) {
+    const int N = L / 2, QP = p->QP;
+    hipStream_t st = p->stream;
+    // axis 3: rows of N real -> modes 0..N of the padded transform, t1[i1][i2][q3]
+    RET_IF((launch_r2c<L, false, float>(st, u, N * N, N, N, t1, QP, N + 1, -1.f, p->tw)));
+    // axis 2: t1[i1][i2][q3] -> w[i1][q2][q3]
+    RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, t1, w, N, N + 1, (int64_t)N * QP, 1, QP,
+                                                          (int64_t)L * QP, 1, QP, N, L, -1.f, p->tw)));
+    // axis 1: w[i1][q2][q3] -> X[q1][q2][q3]
+    return launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, w, X, L, N + 1, QP, 1, (int64_t)L * QP, QP, 1,
+                                                       (int64_t)L * QP, N, L, -1.f, p->tw);
+}
+
 template <int L>
 int cols_per_block_t(bool dbl) { return dbl ? FftCfg<L, double2>::C : FftCfg<L, float2>::C; }
 
@@ -651,6 +667,11 @@ hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z
 
 hipError_t fft_forward_r2c(firm_plan p, const float* x, float2* out) {
     DISPATCH_L(p->N, fwd_r2c_passes, p, x, out);
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_project_grid(firm_plan p, const float* u, float2* t1, float2* w, float2* X) {
+    DISPATCH_L(2 * p->N, projgrid_passes, p, u, t1, w, X);
     return hipErrorInvalidValue;
 }
 

@@ -108,6 +108,7 @@ hipError_t fft_khat_from_kerc(firm_plan p, float2* w1);        // kerc -> khat (
 hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, float* chalf);
 hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2, float* atb,
                         const double* k0term);
+hipError_t fft_project_grid(firm_plan p, const float* u, float2* t1, float2* w, float2* X);  // L x L x QP
 hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z, const int* active = nullptr,
                        double* partials = nullptr);
 hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam);
@@ -126,6 +127,9 @@ hipError_t kerc_from_centred(firm_plan p, const float* in);
 hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t s);
 hipError_t kerc_to_double(firm_plan p, double* out);
 firm_status ensure_fp64(firm_plan p);  // api.hip: FP64 buffers and khat64
+
+// ---- project.hip ----
+hipError_t forward_project(firm_plan p, const float* V, float2* b);
 
 // ---- synth.hip ----
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,

@@ -1,0 +1,313 @@
+// Forward projector of libfirm (eq. forward-projector): slices of a volume at the sample
+// points xi_{k,m} = R_m^{-1}(omega_k, 0), with the CTF and the image shift applied,
+//
+//   b(k, m) = h_m(|k|) exp(-i <omega_k, s_m>) sum_n V(n) exp(-i <n, xi_{k,m}>).
+//
+// This is the adjoint of the back-projection (spread.hip; it re-centres by
+// exp(+i <omega_k, s_m>)), evaluated as a type-2 non-uniform FFT on the same grid (L = 2N),
+// with the same Kaiser-Bessel window and the same cell convention:
+//   1. u(n) = V(n) / phihat(n1) phihat(n2) phihat(n3)      (the window's transform)
+//   2. G(g) = sum_n u(n) exp(-2 pi i <n, g> / L), g in [0, L)^3 (three FFT passes; real u,
+//      so only q3 in [0, N] is formed, the rest is conj G(-g))
+//   3. b = sum over the W^3 window cells of weight * G(cell), one thread per sample point.
+// Step 3 walks the grid in T^3 tiles, the transpose of the gridding spread: a workgroup loads
+// its (T + W)^3 padded tile of G into LDS once, finds the sample points whose cell lies in
+// the tile (plane test, then the disk points near the plane), and each thread gathers one
+// point's W^3 window from LDS.  Every point belongs to exactly one tile, so every output is
+// written once, with no atomics.  The half disk (k1 > 0, or k1 = 0 and k2 > 0) is gathered;
+// b(-k) = conj b(k) for real V, and b(0) = h(0) sum V is formed exactly.
+#include <algorithm>
+#include <cmath>
+
+#include "firm_internal.h"
+
+#define KB_DEG 10
+#define PJ_TILE 12
+#define PJ_QCAP 2048
+#define PJ_THREADS 256
+#define PJ_PREP_BLOCKS 1024
+
+namespace {
+
+struct ProjArgs {
+    int N, M, L, nt, P, Q, QP;
+    double s;
+    const double* c12;
+    const float* nrm;
+    const int32_t* group;
+    const float* table;
+    const float* poly;
+    const int4* work;
+    const float2* X;       // [q1][q2][q3], q3 in [0, N], pitch QP
+    const double* shifts;
+    const int* rowstart;
+    float2* b;
+};
+
+template <int W>
+__device__ __forceinline__ void kb_weights(const float* __restrict__ poly, float x, float* out) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        const float* c = poly + j * (KB_DEG + 1);
+        float v = c[KB_DEG];
+#pragma unroll
+        for (int d = KB_DEG - 1; d >= 0; --d) v = fmaf(v, x, c[d]);
+        out[j] = v;
+    }
+}
+
+// u = V / (phihat(n1) phihat(n2) phihat(n3)) and per-block FP64 partial sums of V.
+__global__ void __launch_bounds__(256) k_fp_prep(const float* __restrict__ V, const float* __restrict__ dec, int N,
+                                                 float* __restrict__ u, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const int64_t n3 = (int64_t)N * N * N;
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n3; i += (int64_t)gridDim.x * 256) {
+        const int i3 = (int)(i % N), i2 = (int)((i / N) % N), i1 = (int)(i / ((int64_t)N * N));
+        const float v = V[i];
+        acc += (double)v;
+        u[i] = v * dec[i1] * dec[i2] * dec[i3];
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// b(0, m) = h_m(0) sum V; every block forms the same sum of the partials in the same order.
+__global__ void __launch_bounds__(256) k_fp_k0(const double* __restrict__ partials, int nblk,
+                                               const int32_t* __restrict__ group, const float* __restrict__ table,
+                                               int Q, int M, int P, float2* __restrict__ b) {
+    __shared__ double red[4];
+    __shared__ float total;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += 256) acc += partials[i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) total = (float)((red[0] + red[1]) + (red[2] + red[3]));
+    __syncthreads();
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= M) return;
+    const int g = group ? group[m] : 0;
+    const float h = table ? table[(int64_t)g * Q] : 1.f;
+    b[(int64_t)m * P + (P - 1) / 2] = make_float2(h * total, 0.f);
+}
+
+// G at grid index q from the half spectrum X of the array-index transform: the volume sits at
+// n = i - N/2, so G(q) = i^(q1 + q2 + q3) X(q) (L is a multiple of 4), and X(q) = conj X(-q).
+__device__ __forceinline__ float2 grid_value(const float2* __restrict__ X, int L, int N, int QP, int q0, int q1,
+                                             int q2) {
+    float2 v;
+    if (q2 <= N) {
+        v = X[((int64_t)q0 * L + q1) * QP + q2];
+    } else {
+        const int r0 = q0 == 0 ? 0 : L - q0, r1 = q1 == 0 ? 0 : L - q1;
+        v = X[((int64_t)r0 * L + r1) * QP + (L - q2)];
+        v.y = -v.y;
+    }
+    switch ((q0 + q1 + q2) & 3) {
+        case 1: return make_float2(-v.y, v.x);
+        case 2: return make_float2(-v.x, -v.y);
+        case 3: return make_float2(v.y, -v.x);
+        default: return v;
+    }
+}
+
+// One queued point: view m and disk point (k1, k2) of the half disk.
+template <int T, int W>
+__device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __restrict__ tile, const int* tt, int m,
+                                             int k1, int k2) {
+    constexpr int PT = T + W;
+    constexpr int PADLO = (W + 1) / 2 - 1;
+    const int N = a.N;
+    const double halfL = 0.5 * a.L;
+    const double* c = a.c12 + 6 * (int64_t)m;
+    float ph[3][W];
+    int lo[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        // window start and weights exactly as the gridding spread forms them
+        const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)a.L);
+        const double left = tau - 0.5 * W;
+        const int b0 = (int)floor(left) + 1;
+        const float f = (float)((double)b0 - left);  // in (0, 1]
+        kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
+        lo[d] = min(max(b0 - (tt[d] * T - PADLO), 0), PT - W);
+    }
+    // one window plane per iteration (W^2 LDS loads in flight); the plane weight rotates
+    // through w0 so that no register array is indexed at run time
+    float ar = 0.f, ai = 0.f;
+    float w0[W];
+#pragma unroll
+    for (int t = 0; t < W; ++t) w0[t] = ph[0][t];
+    const float2* pl = tile + (lo[0] * PT + lo[1]) * PT + lo[2];
+#pragma unroll 1
+    for (int j0 = 0; j0 < W; ++j0, pl += PT * PT) {
+        const float wp = w0[0];
+#pragma unroll
+        for (int t = 0; t < W - 1; ++t) w0[t] = w0[t + 1];
+#pragma unroll
+        for (int j1 = 0; j1 < W; ++j1) {
+            const float2* row = pl + j1 * PT;
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int j2 = 0; j2 < W; ++j2) {
+                const float2 g = row[j2];
+                sr = fmaf(ph[2][j2], g.x, sr);
+                si = fmaf(ph[2][j2], g.y, si);
+            }
+            const float w = wp * ph[1][j1];
+            ar = fmaf(w, sr, ar);
+            ai = fmaf(w, si, ai);
+        }
+    }
+    const int g = a.group ? a.group[m] : 0;
+    const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
+    float cs = 1.f, sn = 0.f;
+    if (a.shifts) {
+        const double th =
+            6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] + k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+        cs = (float)cos(th);
+        sn = (float)sin(th);
+    }
+    // h exp(-i theta) (ar + i ai), and its conjugate at -k
+    const float2 v = make_float2(h * (ar * cs + ai * sn), h * (ai * cs - ar * sn));
+    const int idx = a.rowstart[k1 + N / 2] + k2;
+    a.b[(int64_t)m * a.P + idx] = v;
+    a.b[(int64_t)m * a.P + (a.P - 1 - idx)] = make_float2(v.x, -v.y);
+}
+
+template <int T, int W, int NTH>
+__global__ void __launch_bounds__(NTH) k_project(ProjArgs a) {
+    constexpr int PT = T + W;                  // padded tile edge (window starts in [0, T])
+    constexpr int PADLO = (W + 1) / 2 - 1;
+    constexpr int NCELL = PT * PT * PT;
+    __shared__ float2 tile[NCELL];
+    __shared__ int img_m[NTH], img_k1[NTH], img_k2[NTH];
+    // queued points (view, packed k1 k2), kept across candidate chunks and image blocks and
+    // gathered once the queue could not take another chunk
+    __shared__ int q_m[PJ_QCAP], q_k[PJ_QCAP];
+    __shared__ int nimg, qn;
+
+    const int tid = threadIdx.x;
+    const int4 wk = a.work[blockIdx.x];
+    const int nt = a.nt;
+    const int tt[3] = {wk.x / (nt * nt), (wk.x / nt) % nt, wk.x % nt};
+    const int L = a.L, N = a.N;
+    const double halfL = 0.5 * L;
+
+    // the padded tile of G: LDS cell l holds grid index (tt * T - PADLO + l - L/2) mod L
+    const int o0 = tt[0] * T - PADLO - L / 2, o1 = tt[1] * T - PADLO - L / 2, o2 = tt[2] * T - PADLO - L / 2;
+    for (int i = tid; i < NCELL; i += NTH) {
+        const int l0 = i / (PT * PT), l1 = (i / PT) % PT, l2 = i % PT;
+        const int q0 = ((o0 + l0) % L + L) % L, q1 = ((o1 + l1) % L + L) % L, q2 = ((o2 + l2) % L + L) % L;
+        tile[i] = grid_value(a.X, L, N, a.QP, q0, q1, q2);
+    }
+    if (tid == 0) qn = 0;
+
+    const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
+    const double Rt = T * 0.8660254037844386 + 1e-3;
+    const double rk = Rt / a.s;
+    const int S = (int)floor(2.0 * rk) + 3;
+    const int SS = S * S;
+    const int N2 = N * N;
+
+    for (int mb = wk.y; mb < wk.z; mb += NTH) {
+        __syncthreads();
+        if (tid == 0) nimg = 0;
+        __syncthreads();
+        // images whose plane meets the tile's circumscribed sphere, with the corner of the
+        // S x S square of disk points around the projection of the tile centre
+        const int m = mb + tid;
+        if (m < wk.z) {
+            const float* n = a.nrm + 4 * (int64_t)m;
+            const double dist = fabs(tc[0] * n[0] + tc[1] * n[1] + tc[2] * n[2]);
+            if (dist <= Rt + 1e-3) {
+                const double* c = a.c12 + 6 * (int64_t)m;
+                const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
+                const double u2 = (tc[0] * c[3] + tc[1] * c[4] + tc[2] * c[5]) / a.s;
+                const int sl = atomicAdd(&nimg, 1);
+                img_m[sl] = m;
+                img_k1[sl] = (int)ceil(u1 - rk) - 1;
+                img_k2[sl] = (int)ceil(u2 - rk) - 1;
+            }
+        }
+        __syncthreads();
+        const int total = nimg * SS;
+        for (int base = 0; base < total; base += NTH) {
+            // one candidate per thread: at most NTH points join the queue per chunk
+            const int i = base + tid;
+            if (i < total) {
+                const int sl = i / SS, cc = i - sl * SS;
+                const int k1 = img_k1[sl] + cc / S, k2 = img_k2[sl] + cc % S;
+                if ((k1 > 0 || (k1 == 0 && k2 > 0)) && 4 * (k1 * k1 + k2 * k2) <= N2) {
+                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                    bool in = true;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
+                        int cell = (int)floor(tau);
+                        cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+                        in = in && (cell / T == tt[d]);
+                    }
+                    if (in) {
+                        const int qi = atomicAdd(&qn, 1);
+                        q_m[qi] = img_m[sl];
+                        q_k[qi] = ((k1 + 256) << 9) | (k2 + 256);
+                    }
+                }
+            }
+            __syncthreads();  // the chunk is queued (and the tile is in place)
+            const int nq = qn;
+            __syncthreads();  // every thread has read qn before the next chunk adds to it
+            if (nq > PJ_QCAP - NTH) {
+                for (int qi = tid; qi < nq; qi += NTH)
+                    gather_point<T, W>(a, tile, tt, q_m[qi], ((q_k[qi] >> 9) & 511) - 256, (q_k[qi] & 511) - 256);
+                __syncthreads();
+                if (tid == 0) qn = 0;
+                __syncthreads();
+            }
+        }
+    }
+    __syncthreads();
+    const int nq = qn;
+    for (int qi = tid; qi < nq; qi += NTH)
+        gather_point<T, W>(a, tile, tt, q_m[qi], ((q_k[qi] >> 9) & 511) - 256, (q_k[qi] & 511) - 256);
+}
+
+}  // namespace
+
+// b (M x P complex64, disk order) = forward projection of V (N^3, centred order).
+// Workspaces: p->tmp (u), p->T1, p->ws1, p->grid (the caller has sized the gridding workspaces).
+hipError_t forward_project(firm_plan p, const float* V, float2* b) {
+    const int N = p->N, L = 2 * N;
+    if (spread_tile_cplx() != PJ_TILE) return hipErrorInvalidValue;
+    hipStream_t st = p->stream;
+    const int nblk = std::min<int>(PJ_PREP_BLOCKS, p->npart);
+    hipLaunchKernelGGL(k_fp_prep, dim3(nblk), dim3(256), 0, st, V, p->deconv_atb, N, p->tmp, p->partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fp_k0, dim3((p->M + 255) / 256), dim3(256), 0, st, p->partials, nblk, p->group, p->table,
+                       p->Q, p->M, p->P, b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    float2* X = reinterpret_cast<float2*>(p->grid);
+    if ((e = fft_project_grid(p, p->tmp, p->T1, reinterpret_cast<float2*>(p->ws1), X)) != hipSuccess) return e;
+    if (p->ntiles_atb == 0) return hipSuccess;
+    ProjArgs a;
+    a.N = N; a.M = p->M; a.L = L; a.nt = (L + PJ_TILE - 1) / PJ_TILE; a.P = p->P; a.Q = p->Q; a.QP = p->QP;
+    a.s = 2.0;
+    a.c12 = p->c12; a.nrm = p->nrm; a.group = p->group; a.table = p->table; a.poly = p->kb_poly;
+    a.work = reinterpret_cast<const int4*>(p->tiles_atb);
+    a.X = X; a.shifts = p->shifts; a.rowstart = p->rowstart; a.b = b;
+    const dim3 grid(p->ntiles_atb), blk(PJ_THREADS);
+    switch (p->kbw) {
+        case 4: hipLaunchKernelGGL((k_project<PJ_TILE, 4, PJ_THREADS>), grid, blk, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_project<PJ_TILE, 5, PJ_THREADS>), grid, blk, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_project<PJ_TILE, 6, PJ_THREADS>), grid, blk, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_project<PJ_TILE, 7, PJ_THREADS>), grid, blk, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_project<PJ_TILE, 8, PJ_THREADS>), grid, blk, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}

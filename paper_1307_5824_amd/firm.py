@@ -60,6 +60,7 @@ def _load():
         "firm_kernel_set": (i, [vp, vp]),
         "firm_kernel_spectrum": (i, [vp, vp]),
         "firm_backproject": (i, [vp, vp, vp]),
+        "firm_forward_project": (i, [vp, vp, vp]),
         "firm_apply_AtA": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_f64": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_timed": (i, [vp, vp, vp, d, i, vp]),
@@ -215,6 +216,15 @@ class Plan:
         out = self._vol(out)
         self._req(out, self.N ** 3, self._torch.float32)
         _check(lib.firm_backproject(self.h, _ptr(b), _ptr(out)), self.h)
+        return out
+
+    def forward_project(self, V, out=None):
+        """Slices b (M x P complex64) of the volume V at the plan's views, CTFs and shifts."""
+        self._req(V, self.N ** 3, self._torch.float32)
+        if out is None:
+            out = self._torch.empty((self.M, self.P), dtype=self._torch.complex64, device=V.device)
+        self._req(out, self.M * self.P, self._torch.complex64)
+        _check(lib.firm_forward_project(self.h, _ptr(V), _ptr(out)), self.h)
         return out
 
     def apply_AtA(self, x, lam, out=None):
