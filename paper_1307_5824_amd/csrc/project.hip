@@ -24,8 +24,9 @@
 #define KB_DEG 10
 #define PJ_TILE 12
 #define PJ_QCAP 2048
-#define PJ_THREADS 256
+#define PJ_THREADS 512
 #define PJ_PREP_BLOCKS 1024
+#define PJ_VPT 2
 
 namespace {
 
@@ -160,16 +161,17 @@ __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __
             const float w = wp * ph[1][j1];
             ar = fmaf(w, sr, ar);
             ai = fmaf(w, si, ai);
+            // at most half a plane of loads in flight: keeps the gather within 128 registers
+            if (j1 == W / 2) __builtin_amdgcn_sched_barrier(0);
         }
     }
     const int g = a.group ? a.group[m] : 0;
     const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
     float cs = 1.f, sn = 0.f;
     if (a.shifts) {
-        const double th =
-            6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] + k2 * a.shifts[2 * (int64_t)m + 1]) / N;
-        cs = (float)cos(th);
-        sn = (float)sin(th);
+        // theta = 2 pi x, x = <k, s_m> / N reduced to [-1/2, 1/2] in FP64, then an FP32 sincospi
+        const double x = (k1 * a.shifts[2 * (int64_t)m] + k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+        sincospif(2.f * (float)(x - rint(x)), &sn, &cs);
     }
     // h exp(-i theta) (ar + i ai), and its conjugate at -k
     const float2 v = make_float2(h * (ar * cs + ai * sn), h * (ai * cs - ar * sn));
@@ -179,15 +181,15 @@ __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __
 }
 
 template <int T, int W, int NTH>
-__global__ void __launch_bounds__(NTH) k_project(ProjArgs a) {
+__global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
     constexpr int PT = T + W;                  // padded tile edge (window starts in [0, T])
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;
+    constexpr int IMGCAP = (PJ_VPT + 1) * NTH;
     __shared__ float2 tile[NCELL];
-    __shared__ int img_m[NTH], img_k1[NTH], img_k2[NTH];
-    // queued points (view, packed k1 k2), kept across candidate chunks and image blocks and
-    // gathered once the queue could not take another chunk
-    __shared__ int q_m[PJ_QCAP], q_k[PJ_QCAP];
+    __shared__ int img_m[IMGCAP], img_r[IMGCAP];  // surviving views and their first candidate row
+    // queued points (view slot, k1, k2), -1 for an unused entry
+    __shared__ int queue[PJ_QCAP];
     __shared__ int nimg, qn;
 
     const int tid = threadIdx.x;
@@ -204,76 +206,131 @@ __global__ void __launch_bounds__(NTH) k_project(ProjArgs a) {
         const int q0 = ((o0 + l0) % L + L) % L, q1 = ((o1 + l1) % L + L) % L, q2 = ((o2 + l2) % L + L) % L;
         tile[i] = grid_value(a.X, L, N, a.QP, q0, q1, q2);
     }
-    if (tid == 0) qn = 0;
+    if (tid == 0) { qn = 0; nimg = 0; }
 
     const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
     const double Rt = T * 0.8660254037844386 + 1e-3;
     const double rk = Rt / a.s;
-    const int S = (int)floor(2.0 * rk) + 3;
-    const int SS = S * S;
+    const int S = (int)floor(2.0 * rk) + 3;  // candidate rows per view
     const int N2 = N * N;
-
-    for (int mb = wk.y; mb < wk.z; mb += NTH) {
-        __syncthreads();
-        if (tid == 0) nimg = 0;
-        __syncthreads();
-        // images whose plane meets the tile's circumscribed sphere, with the corner of the
-        // S x S square of disk points around the projection of the tile centre
-        const int m = mb + tid;
-        if (m < wk.z) {
-            const float* n = a.nrm + 4 * (int64_t)m;
-            const double dist = fabs(tc[0] * n[0] + tc[1] * n[1] + tc[2] * n[2]);
-            if (dist <= Rt + 1e-3) {
-                const double* c = a.c12 + 6 * (int64_t)m;
-                const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
-                const double u2 = (tc[0] * c[3] + tc[1] * c[4] + tc[2] * c[5]) / a.s;
-                const int sl = atomicAdd(&nimg, 1);
-                img_m[sl] = m;
-                img_k1[sl] = (int)ceil(u1 - rk) - 1;
-                img_k2[sl] = (int)ceil(u2 - rk) - 1;
-            }
-        }
-        __syncthreads();
-        const int total = nimg * SS;
-        for (int base = 0; base < total; base += NTH) {
-            // one candidate per thread: at most NTH points join the queue per chunk
-            const int i = base + tid;
-            if (i < total) {
-                const int sl = i / SS, cc = i - sl * SS;
-                const int k1 = img_k1[sl] + cc / S, k2 = img_k2[sl] + cc % S;
-                if ((k1 > 0 || (k1 == 0 && k2 > 0)) && 4 * (k1 * k1 + k2 * k2) <= N2) {
-                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    bool in = true;
+    // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
+    // rounding of the row intervals; the edge tiles also own the clamped cells beyond the grid
+    constexpr double MARGIN = 1e-3, FAR = 1e30;
+    double blo[3], bhi[3];
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
-                        int cell = (int)floor(tau);
-                        cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
-                        in = in && (cell / T == tt[d]);
-                    }
-                    if (in) {
-                        const int qi = atomicAdd(&qn, 1);
-                        q_m[qi] = img_m[sl];
-                        q_k[qi] = ((k1 + 256) << 9) | (k2 + 256);
-                    }
+    for (int d = 0; d < 3; ++d) {
+        blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
+        bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
+    }
+
+    auto flush = [&](int n) {
+        for (int qi = tid; qi < n; qi += NTH) {
+            const int e = queue[qi];
+            if (e >= 0) gather_point<T, W>(a, tile, tt, img_m[e >> 17], (e >> 9) & 255, (e & 511) - 256);
+        }
+    };
+
+    int m0 = wk.y;
+    while (m0 < wk.z) {  // m0 is uniform
+        __syncthreads();  // the counters are reset, the tile is in place
+        // 1. views whose plane meets the tile's circumscribed sphere, at least NTH of them
+        //    (or all that remain), PJ_VPT views per thread per round so that the loads of a
+        //    round overlap
+        int ni = 0;
+        do {
+            float4 nv[PJ_VPT];
+#pragma unroll
+            for (int v = 0; v < PJ_VPT; ++v) {
+                const int m = m0 + v * NTH + tid;
+                nv[v] = m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m)
+                                 : make_float4(0.f, 0.f, 0.f, 1e30f);
+            }
+#pragma unroll
+            for (int v = 0; v < PJ_VPT; ++v) {
+                const int m = m0 + v * NTH + tid;
+                const double dist = fabs(tc[0] * nv[v].x + tc[1] * nv[v].y + tc[2] * nv[v].z);
+                if (m < wk.z && dist <= Rt + 1e-3) {
+                    const double* c = a.c12 + 6 * (int64_t)m;
+                    const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
+                    const int sl = atomicAdd(&nimg, 1);
+                    img_m[sl] = m;
+                    img_r[sl] = (int)ceil(u1 - rk) - 1;
                 }
             }
-            __syncthreads();  // the chunk is queued (and the tile is in place)
-            const int nq = qn;
-            __syncthreads();  // every thread has read qn before the next chunk adds to it
-            if (nq > PJ_QCAP - NTH) {
-                for (int qi = tid; qi < nq; qi += NTH)
-                    gather_point<T, W>(a, tile, tt, q_m[qi], ((q_k[qi] >> 9) & 511) - 256, (q_k[qi] & 511) - 256);
+            m0 += PJ_VPT * NTH;
+            __syncthreads();
+            ni = nimg;
+            __syncthreads();  // read by every thread before the next round adds to it
+        } while (ni < NTH && m0 < wk.z);
+        // 2. one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three
+        //    slabs, plus the disk and half-disk bounds), then the exact cell test per point.
+        //    Queue space is reserved per thread; a reservation that does not fit is retried
+        //    after the full queue has been gathered.
+        const int units = ni * S;
+        for (int base = 0; base < units; base += NTH) {
+            const int u = base + tid;
+            int sl = 0, k1 = 0, klo = 0, cnt = 0;
+            if (u < units) {
+                sl = u / S;
+                k1 = img_r[sl] + (u - sl * S);
+                if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                    const int kd = (int)sqrt((double)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                    double lo = -kd, hi = kd;
+                    bool ok = true;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double al = a.s * k1 * c[d] + halfL, be = a.s * c[3 + d];
+                        if (fabs(be) < 1e-9) {
+                            ok = ok && al >= blo[d] && al <= bhi[d];
+                        } else {
+                            const double t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
+                            lo = fmax(lo, fmin(t1, t2));
+                            hi = fmin(hi, fmax(t1, t2));
+                        }
+                    }
+                    klo = (int)ceil(lo);
+                    if (k1 == 0) klo = max(klo, 1);
+                    // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                    cnt = ok && hi >= klo ? min((int)floor(hi) - klo + 1, 32) : 0;
+                }
+            }
+            bool pend = cnt > 0;
+            while (true) {
+                if (pend) {
+                    const int pos = atomicAdd(&qn, cnt);
+                    if (pos + cnt <= PJ_QCAP) {
+                        const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                        for (int j = 0; j < cnt; ++j) {
+                            const int k2 = klo + j;
+                            bool in = 4 * (k1 * k1 + k2 * k2) <= N2;
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
+                                int cell = (int)floor(tau);
+                                cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+                                in = in && (cell / T == tt[d]);
+                            }
+                            queue[pos + j] = in ? (sl << 17) | (k1 << 9) | (k2 + 256) : -1;
+                        }
+                        pend = false;
+                    } else {
+                        for (int j = pos; j < PJ_QCAP; ++j) queue[j] = -1;
+                    }
+                }
+                if (!__syncthreads_or(pend)) break;
+                flush(PJ_QCAP);  // the queue is full
                 __syncthreads();
                 if (tid == 0) qn = 0;
                 __syncthreads();
             }
         }
+        // 3. the view slots are refilled next round: gather what is queued
+        const int nq = qn;  // every reservation of the last chunk fitted (read after its barrier)
+        flush(nq);
+        __syncthreads();
+        if (tid == 0) { qn = 0; nimg = 0; }
     }
-    __syncthreads();
-    const int nq = qn;
-    for (int qi = tid; qi < nq; qi += NTH)
-        gather_point<T, W>(a, tile, tt, q_m[qi], ((q_k[qi] >> 9) & 511) - 256, (q_k[qi] & 511) - 256);
 }
 
 }  // namespace
