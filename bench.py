@@ -219,6 +219,19 @@ def main():
     data_res = (num / den) ** 0.5
     print(f"forward projection {fwd_ms:.1f} ms, data residual {data_res:.4f}", file=sys.stderr, flush=True)
 
+    # Step 1 from real-space images: the generator's images (projections of the same blobs at
+    # the same views and shifts, pixel noise at the same SNR, no CTF) -> slices
+    e = [ev() for _ in range(3)]
+    e[0].record()
+    imgs = plan.synth_images(inp.centers, inp.sigmas, inp.amps, snr=wl.snr, seed=wl.index + 2)
+    e[1].record()
+    b_img = plan.images_to_slices(imgs)
+    e[2].record()
+    torch.cuda.synchronize()
+    synth_img_ms, img2sl_ms = e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])
+    del imgs, b_img
+    print(f"images: synth {synth_img_ms:.1f} ms, images_to_slices {img2sl_ms:.1f} ms", file=sys.stderr, flush=True)
+
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
     pass_ms = plan.apply_AtA_timed(x_probe, wl.lam, 50)
     pb = pass_bytes(N)
@@ -266,6 +279,8 @@ def main():
         "backproject_ms": round(ph[1], 2),
         "forward_project_ms": round(fwd_ms, 2),
         "data_rel_residual": round(data_res, 5),
+        "images_to_slices_ms": round(img2sl_ms, 2),
+        "synth_images_ms": round(synth_img_ms, 2),
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

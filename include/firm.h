@@ -185,6 +185,25 @@ firm_status firm_precond_apply(firm_plan plan, const float* d_dev, const float* 
  * order).  It is real because Ker is real and even. */
 firm_status firm_kernel_spectrum(firm_plan plan, float* khat_dev);
 
+/* Step 1 of the algorithm (section 3.4): slices from images.  images_dev: device, M x N x N
+ * floats (image m, row i1, column i2; pixel i sits at x = i - N/2).  b_dev (device, M x P
+ * complex64, disk order) receives the centred 2D DFT of section 2.2 at the disk points,
+ *   b(k, m) = sum_x J_m(x) exp(-2 pi i <k, x> / N),
+ * with the periodic value at the boundary points k_d = +N/2.  The images are taken as
+ * recorded (no CTF or shift correction; firm_backproject re-centres).  Batched real FFTs in
+ * groups of images through a workspace of at most 1 GiB (allocated on first use). */
+firm_status firm_images_to_slices(firm_plan plan, const float* images_dev, void* b_dev);
+
+/* Synthetic real-space images: images_dev (M x N x N floats, layout of firm_images_to_slices)
+ * = projections of a sum of B Gaussian blobs along the plan's views (section 3.1: each blob
+ * a exp(-||x - c||^2 / (2 s^2)) projects to a sqrt(2 pi) s exp(-||x - p||^2 / (2 s^2)) with p
+ * the first two coordinates of R_m c), translated by the plan's shifts (image J(x - s_m)),
+ * plus white Gaussian pixel noise at the given SNR (mean clean pixel power / noise variance;
+ * snr <= 0 or infinite: none).  No CTF.  sigma > 0 required; B in [1, 320].  Noise uses
+ * Philox4x32-10 keyed by seed. */
+firm_status firm_synth_images(firm_plan plan, int B, const double* centers, const double* sigmas,
+                              const double* amps, double snr, uint64_t seed, float* images_dev);
+
 /* Synthetic slices for benchmarks and tests: b_dev (M x P complex64) = CTF-filtered,
  * translated Fourier slices of a sum of B Gaussian blobs given in closed form by the
  * projection-slice theorem (eq. continuous_fps), plus complex white noise with the

@@ -53,16 +53,19 @@ def slices(N, rotations, centers, sigmas, amps, h=None, shifts=None):
     return b
 
 
-def projection_image(N, R, centers, sigmas, amps):
+def projection_image(N, R, centers, sigmas, amps, shift=None):
     """Real-space projection (P_R phi)(x1, x2) = integral of phi(R^{-1} x) dx3 on the pixel grid
-    x in [-N/2, N/2)^2 (section 3.1), for blobs with s_b > 0."""
+    x in [-N/2, N/2)^2 (section 3.1), for blobs with s_b > 0.  With a shift s the image is that
+    of a particle off-centre by s, J(x - s) (the images that section 3.1 re-shifts to their
+    centres)."""
     x = firm.voxel_coords(N)
     g1, g2 = np.meshgrid(x, x, indexing="ij")
     img = np.zeros((N, N))
     R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    sh = np.zeros(2) if shift is None else np.asarray(shift, dtype=np.float64).reshape(2)
     for c, s, a in zip(np.asarray(centers).reshape(-1, 3), np.ravel(sigmas), np.ravel(amps)):
         rc = R @ np.asarray(c, dtype=np.float64)
-        d2 = (g1 - rc[0]) ** 2 + (g2 - rc[1]) ** 2
+        d2 = (g1 - rc[0] - sh[0]) ** 2 + (g2 - rc[1] - sh[1]) ** 2
         img += a * np.sqrt(2.0 * np.pi) * s * np.exp(-d2 / (2.0 * s * s))
     return img
 

@@ -144,7 +144,8 @@ void firm_plan_destroy(firm_plan p) {
                    p->tw, p->kerc, p->khat, p->T1, p->T2, p->r, p->p, p->q, p->z, p->tmp, p->partials,
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
-                   p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec};
+                   p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec,
+                   p->img_ws};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->host_scal) (void)hipHostFree(p->host_scal);
@@ -551,6 +552,45 @@ firm_status firm_precond_apply(firm_plan p, const float* d, const float* r, floa
     if (!p || !d || !r || !z) return firm_fail(p, FIRM_ERR_ARG, "null argument");
     FIRM_HIP(p, precond_set(p, d));
     FIRM_HIP(p, fft_precond(p, p->dhalf, r, z));
+    return FIRM_OK;
+}
+
+firm_status firm_images_to_slices(firm_plan p, const float* images, void* b) {
+    if (!p || !images || !b) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    const size_t per = (size_t)p->N * p->QPn * sizeof(float2);
+    const int G = (int)std::max<size_t>(1, std::min<size_t>((size_t)p->M, (size_t(1) << 30) / per));
+    firm_status s = ensure_ws(p, &p->img_ws, &p->img_ws_bytes, (size_t)G * per);
+    if (s != FIRM_OK) return s;
+    float2* ws = (float2*)p->img_ws;
+    const int64_t npix = (int64_t)p->N * p->N;
+    for (int m0 = 0; m0 < p->M; m0 += G) {
+        const int g = std::min(G, p->M - m0);
+        FIRM_HIP(p, fft_images_r2c(p, images + (int64_t)m0 * npix, g, ws));
+        FIRM_HIP(p, images_gather(p, ws, g, m0, (float2*)b));
+    }
+    return FIRM_OK;
+}
+
+firm_status firm_synth_images(firm_plan p, int B, const double* centers, const double* sigmas, const double* amps,
+                              double snr, uint64_t seed, float* images) {
+    if (!p || !images || (B > 0 && (!centers || !sigmas || !amps))) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (B < 1 || B > 320) return firm_fail(p, FIRM_ERR_ARG, "B must be in [1, 320]");
+    std::vector<double> bl((size_t)B * 5);
+    for (int i = 0; i < B; ++i) {
+        if (!(sigmas[i] > 0.0) || !std::isfinite(sigmas[i]))
+            return firm_fail(p, FIRM_ERR_ARG, "image blobs need sigma > 0");
+        for (int d = 0; d < 3; ++d) bl[5 * i + d] = centers[3 * i + d];
+        bl[5 * i + 3] = sigmas[i];
+        bl[5 * i + 4] = amps[i] * std::sqrt(2.0 * M_PI) * sigmas[i];
+    }
+    const int64_t nscr = synth_images_scratch(p->N, p->M);
+    double* dbl = nullptr;
+    FIRM_HIP(p, hipMalloc((void**)&dbl, (bl.size() + (size_t)nscr) * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dbl, bl.data(), bl.size() * sizeof(double), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = synth_images(p, B, dbl, snr, seed, images, dbl + bl.size(), nscr);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(dbl);
+    if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("synth images: ") + hipGetErrorString(e));
     return FIRM_OK;
 }
 

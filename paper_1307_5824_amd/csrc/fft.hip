@@ -584,6 +584,17 @@ hipError_t projgrid_passes(firm_plan p, const float* u, float2* t1, float2* w, f
                                                        (int64_t)L * QP, N, L, -1.f, p->tw);
 }
 
+// G real N x N images (L = N, row pitch N) -> half spectra out[g][q1][q2], q2 in [0, N/2]
+// (pitch QPn): rows, then columns, both forward.
+template <int L>
+hipError_t img_r2c_passes(firm_plan p, const float* img, int G, float2* out) {
+    const int N = L, H = N / 2 + 1, QPn = p->QPn;
+    hipStream_t st = p->stream;
+    RET_IF((launch_r2c<L, false, float>(st, img, G * N, N, N, out, QPn, H, -1.f, p->tw)));
+    return launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, out, out, G, H, (int64_t)N * QPn, 1, QPn,
+                                                       (int64_t)N * QPn, 1, QPn, N, N, -1.f, p->tw);
+}
+
 template <int L>
 int cols_per_block_t(bool dbl) { return dbl ? FftCfg<L, double2>::C : FftCfg<L, float2>::C; }
 
@@ -667,6 +678,11 @@ hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z
 
 hipError_t fft_forward_r2c(firm_plan p, const float* x, float2* out) {
     DISPATCH_L(p->N, fwd_r2c_passes, p, x, out);
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_images_r2c(firm_plan p, const float* img, int G, float2* out) {
+    DISPATCH_L(p->N, img_r2c_passes, p, img, G, out);
     return hipErrorInvalidValue;
 }
 

@@ -80,6 +80,7 @@ struct firm_plan_s {
     int* host_flags = nullptr; // pinned mirror
     double* partials2 = nullptr;
     double* partials3 = nullptr;
+    void* img_ws = nullptr; size_t img_ws_bytes = 0;  // image spectra workspace (Step 1), on first use
 };
 
 // status helpers (api.cpp)
@@ -109,6 +110,7 @@ hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, 
 hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2, float* atb,
                         const double* k0term);
 hipError_t fft_project_grid(firm_plan p, const float* u, float2* t1, float2* w, float2* X);  // L x L x QP
+hipError_t fft_images_r2c(firm_plan p, const float* img, int G, float2* out);  // G x N x QPn half spectra
 hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z, const int* active = nullptr,
                        double* partials = nullptr);
 hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam);
@@ -130,6 +132,12 @@ firm_status ensure_fp64(firm_plan p);  // api.hip: FP64 buffers and khat64
 
 // ---- project.hip ----
 hipError_t forward_project(firm_plan p, const float* V, float2* b);
+
+// ---- images.hip ----
+hipError_t images_gather(firm_plan p, const float2* spec, int G, int m0, float2* b);
+hipError_t synth_images(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed, float* img,
+                        double* partials, int64_t npart);
+int64_t synth_images_scratch(int N, int M);  // doubles of device scratch synth_images needs
 
 // ---- synth.hip ----
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,

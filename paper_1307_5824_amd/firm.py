@@ -61,6 +61,7 @@ def _load():
         "firm_kernel_spectrum": (i, [vp, vp]),
         "firm_backproject": (i, [vp, vp, vp]),
         "firm_forward_project": (i, [vp, vp, vp]),
+        "firm_images_to_slices": (i, [vp, vp, vp]),
         "firm_apply_AtA": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_f64": (i, [vp, vp, vp, d]),
         "firm_apply_AtA_timed": (i, [vp, vp, vp, d, i, vp]),
@@ -68,6 +69,7 @@ def _load():
         "firm_cg_solve_f64": (i, [vp, vp, vp, d, d, i, vp, ctypes.POINTER(FirmCgReport)]),
         "firm_precond_apply": (i, [vp, vp, vp, vp]),
         "firm_synth_slices": (i, [vp, i, vp, vp, vp, d, ctypes.c_uint64, vp]),
+        "firm_synth_images": (i, [vp, i, vp, vp, vp, d, ctypes.c_uint64, vp]),
         "firm_last_error": (ctypes.c_char_p, [vp]),
         "firm_philox4x32_10": (None, [vp, vp, vp]),
         "firm_pcnet_num_params": (i64, []),
@@ -271,6 +273,27 @@ class Plan:
         self._req(r, self.N ** 3, self._torch.float32)
         out = self._vol(out)
         _check(lib.firm_precond_apply(self.h, _ptr(d), _ptr(r), _ptr(out)), self.h)
+        return out
+
+    def images_to_slices(self, images, out=None):
+        """Slices b (M x P complex64) from real images (M x N x N float32): Step 1."""
+        self._req(images, self.M * self.N * self.N, self._torch.float32)
+        if out is None:
+            out = self._torch.empty((self.M, self.P), dtype=self._torch.complex64, device=images.device)
+        self._req(out, self.M * self.P, self._torch.complex64)
+        _check(lib.firm_images_to_slices(self.h, _ptr(images), _ptr(out)), self.h)
+        return out
+
+    def synth_images(self, centers, sigmas, amps, snr=float("inf"), seed=0, out=None):
+        """Real-space projection images (M x N x N float32) of a blob volume at the plan's views
+        and shifts, with white pixel noise at the given SNR."""
+        c, cp = _host(np.asarray(centers).reshape(-1, 3), np.float64)
+        s, sp = _host(np.ravel(sigmas), np.float64)
+        a, ap = _host(np.ravel(amps), np.float64)
+        if out is None:
+            out = self._torch.empty((self.M, self.N, self.N), dtype=self._torch.float32, device="cuda")
+        self._req(out, self.M * self.N * self.N, self._torch.float32)
+        _check(lib.firm_synth_images(self.h, int(c.shape[0]), cp, sp, ap, float(snr), int(seed), _ptr(out)), self.h)
         return out
 
     def synth_slices(self, centers, sigmas, amps, snr=float("inf"), seed=0, out=None):

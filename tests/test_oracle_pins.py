@@ -134,6 +134,37 @@ def test_projection_slice_blobs_real_space():
         assert np.linalg.norm(f - b[m]) / np.linalg.norm(f) < 1e-3
 
 
+def test_shifted_projection_image_matches_fourier_closed_form():
+    """The image of a particle off-centre by s (real space, J(x - s)) has the centred DFT
+    exp(-i <omega, s>) times the unshifted slice: the real-space generator's shift sign agrees
+    with the Fourier closed form's, up to the sampling-aliasing floor."""
+    rng = _rng(11)
+    N = 32
+    c, s, a = _small_blobs(rng)
+    R = synth.haar_rotations(1, rng)
+    sh = np.array([1.7, -2.3])
+    k1, k2 = firm.disk_points(N)
+    img = blobs.projection_image(N, R[0], c, s, a, shift=sh)
+    f = blobs.centred_dft2(img, k1, k2)
+    ref = blobs.slices(N, R, c, s, a, shifts=sh[None, :])[0]
+    assert np.linalg.norm(f - ref) / np.linalg.norm(ref) < 1e-3
+    f0 = blobs.centred_dft2(blobs.projection_image(N, R[0], c, s, a), k1, k2)
+    assert np.linalg.norm(f - ref) < 0.1 * np.linalg.norm(f0 - ref)   # the shift matters
+
+
+def test_centred_dft2_is_shifted_fft2():
+    """The centred DFT at integer frequencies is numpy's FFT of the image with its centre moved
+    to index 0, read at k mod N; the boundary k_d = +N/2 takes the value of -N/2."""
+    N = 16
+    img = np.random.default_rng(12).standard_normal((N, N))
+    k1, k2 = firm.disk_points(N)
+    f = blobs.centred_dft2(img, k1, k2)
+    F = np.fft.fft2(np.fft.ifftshift(img))
+    assert np.max(np.abs(f - F[k1 % N, k2 % N])) < 1e-11 * np.max(np.abs(F))
+    edge = (np.abs(k1) == N // 2) | (np.abs(k2) == N // 2)
+    assert edge.sum() == 4
+
+
 def test_c_blob_slices_match_numpy():
     """The plain-C closed form equals the numpy closed form, with CTF and shifts."""
     rng = _rng(5)
