@@ -27,14 +27,15 @@ PASS_NAMES = ["rows_i3_pad_fwd", "cols_i2_fwd", "mid_i1_fwd_mul_inv", "cols_i2_i
 
 
 def pass_bytes(N):
-    """Algorithmic HBM bytes of the five passes of one product (FP32 spectrum, half spectrum along
-    axis 3: N + 1 complex columns)."""
+    """Algorithmic HBM bytes of the five passes of one plain product (FP32 spectrum, half spectrum
+    along axis 3: N + 1 complex columns; lambda x is added through the middle pass's multiplier,
+    so the last pass reads only T1)."""
     H = N + 1
     x = 4 * N ** 3
     t1 = 8 * N * N * H
     t2 = 8 * N * 2 * N * H
     kh = 4 * 2 * N * 2 * N * H
-    return [x + t1, t1 + t2, t2 + kh + t2, t2 + t1, t1 + x + x]
+    return [x + t1, t1 + t2, t2 + kh + t2, t2 + t1, t1 + x]
 
 
 def source_sha():

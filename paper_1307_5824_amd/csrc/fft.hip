@@ -274,7 +274,7 @@ k_cols(const typename VecOf<S>::V* __restrict__ src, void* __restrict__ dstv, in
 // inverse transform, keep the first n_in.
 template <int L, class S, bool HALF>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
-k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, int ncols, int64_t s_outer,
+k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, S kadd, int ncols, int64_t s_outer,
       int64_t s_elem, int64_t s_group, int n_in, const typename VecOf<S>::V* __restrict__ tw, const int* active) {
     // HALF: the pencils are zero-padded (n_in = L / 2) and only their first half is kept, which
     // the compiler folds into the first and last stages
@@ -310,7 +310,7 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, int n
     fft_reg<L, C, false>(v, lds, twp, (S)-1);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const S k = k0[(j + t * T) * C];
+        const S k = k0[(j + t * T) * C] + kadd;
         v[t] = mkv<V>(v[t].x * k, v[t].y * k);
     }
     fft_reg<L, C, false>(v, lds, twp, (S)1);
@@ -393,16 +393,16 @@ hipError_t launch_cols(hipStream_t st, const typename VecOf<S>::V* src, void* ds
 template <int L, class S = float>
 hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec, int nouter, int ncols,
                       int64_t s_outer, int64_t s_elem, int n_in, const typename VecOf<S>::V* tw,
-                      const int* active = nullptr, int64_t s_group = -1) {
+                      const int* active = nullptr, int64_t s_group = -1, S kadd = 0) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = nouter * ceil_div(ncols, Cfg::C);
     if (s_group < 0) s_group = Cfg::C;
     if (2 * n_in == L)
-        hipLaunchKernelGGL((k_mid<L, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, ncols, s_outer,
-                           s_elem, s_group, n_in, tw, active);
+        hipLaunchKernelGGL((k_mid<L, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, kadd, ncols,
+                           s_outer, s_elem, s_group, n_in, tw, active);
     else
-        hipLaunchKernelGGL((k_mid<L, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, ncols, s_outer,
-                           s_elem, s_group, n_in, tw, active);
+        hipLaunchKernelGGL((k_mid<L, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, kadd, ncols,
+                           s_outer, s_elem, s_group, n_in, tw, active);
     return hipGetLastError();
 }
 
@@ -435,17 +435,20 @@ hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, fl
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T1, p->T2, N, N + 1, (int64_t)N * QP, 1, QP, C, 1,
                                                           se_, N, L, -1.f, p->tw, EpiArgs(), active, -1, sg_)));
     if (ev) RET_IF(hipEventRecord(ev[2], st));
-    // C: along i1 for every (q2, q3): forward, times K^, inverse, keep i1 < N
-    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_)));
+    // C: along i1 for every (q2, q3): forward, times K^, inverse, keep i1 < N.  The plain form
+    // multiplies by K^ + lam / L^3 instead: with the unnormalised inverse that adds exactly
+    // lam x to the cropped output, so that pass E need not read x
+    const float kadd = cg ? 0.f : lam / ((float)L * L * L);
+    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd)));
     if (ev) RET_IF(hipEventRecord(ev[3], st));
     // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
                                                           QP, L, N, 1.f, p->tw, EpiArgs(), active, sg_, -1)));
     if (ev) RET_IF(hipEventRecord(ev[4], st));
-    // E: inverse along q3 (half spectrum -> real), crop, + lam x
+    // E: inverse along q3 (half spectrum -> real), crop (CG form: + lam p and <p, q>)
     if (cg)
         return launch_c2r<L, true>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, lam, pvec, p->tw, partials, active);
-    RET_IF((launch_c2r<L, false>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, lam, src, p->tw)));
+    RET_IF((launch_c2r<L, false>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, 0.f, (const float*)nullptr, p->tw)));
     if (ev) RET_IF(hipEventRecord(ev[5], st));
     return hipSuccess;
 }
