@@ -155,6 +155,7 @@ def main():
     net = firm.PCNet(max_batch=1)
     net.set_params(train_precond.load_weights())
     state = {}
+    res = firm.inference_res(N)   # the network's grid: 4^3 spectrum samples per feature, as in training
 
     def step():
         e = [ev() for _ in range(7)]
@@ -165,7 +166,7 @@ def main():
         e[2].record()
         x, rep = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter)
         e[3].record()
-        d = plan.precond_from_output(net.forward(plan.kernel_features(wl.lam)[None]))
+        d = plan.precond_from_output(net.forward(plan.kernel_features(wl.lam, res=res)[None]))
         e[4].record()
         _, rep_l = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter, precond=d)
         e[5].record()

@@ -214,9 +214,12 @@ firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, cons
                               const double* amps, double snr, uint64_t seed, void* b_dev);
 
 /* ---- learned Fourier-diagonal preconditioner ----------------------------------------
- * A 3D conv net maps f = log(|K^| pooled to 32^3 / Ker(0) + lam_rel) to a log diagonal on the
- * 32^3 frequency grid: o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
+ * A 3D conv net maps f = log(|K^| pooled to res^3 / Ker(0) + lam_rel) to a log diagonal on the
+ * res^3 frequency grid: o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
  * padding, 1 -> 32 -> 32 -> 32 -> 1 channels (c2, c3 on BF16 matrix cores, FP32 accumulation).
+ * res is a power of two in [32, 256]; the network is fully convolutional, so weights trained
+ * at one res apply at another (training uses res 32 at N = 64, i.e. (2N/res)^3 = 4^3 spectrum
+ * samples per feature; inference at N keeps that ratio with res = N/2).
  * d = exp(U sym(o)) / Ker(0) on the N^3 grid (sym: o(u) + o(-u) halved; U: periodic trilinear
  * interpolation) is the diagonal of z = F^{-1}(d . F r).  |K^| is the unnormalised DFT_2N of the
  * circulant column (the Fourier multiplier of the embedded product).  Training objectives:
@@ -235,28 +238,32 @@ firm_status firm_pcnet_create(firm_pcnet* out, int max_batch, void* stream);
 void firm_pcnet_destroy(firm_pcnet net);
 firm_status firm_pcnet_set_params(firm_pcnet net, const float* params_host);  /* resets Adam */
 firm_status firm_pcnet_get_params(firm_pcnet net, float* params_host);
-/* out_dev [B][32^3] = network output o for features feat_dev [B][32^3] (centred order). */
-firm_status firm_pcnet_forward(firm_pcnet net, const float* feat_dev, float* out_dev, int B);
-/* Mean loss of B samples at size N under `objective` and (if grad_host) the parameter gradients
- * (host, NPARAM floats).  objective 0: A_dev, B_dev [B][N^3] probe statistics (centred order)
+/* out_dev [B][res^3] = network output o for features feat_dev [B][res^3] (centred order).
+ * Activation buffers grow on first use of a larger B x res^3 (24 bytes per voxel x 32 channels x
+ * ... : about 1.6 GB at res 128, B 1). */
+firm_status firm_pcnet_forward(firm_pcnet net, const float* feat_dev, int res, float* out_dev, int B);
+/* Mean loss of B samples at size N (N <= 8 res) under `objective`, features [B][res^3], and (if
+ * grad_host) the parameter gradients (host, NPARAM floats).  objective 0: A_dev, B_dev [B][N^3] probe statistics (centred order)
  * from firm_probe_stats and sumc host [B]; objective 1: A_dev [B][N^3] the Fourier diagonals t
  * from firm_chan_spectrum (t > 0; B_dev and sumc may be NULL).  ker0: host [B], Ker(0) of each
  * sample's kernel.  FIRM_ERR_ARG for an objective other than 0 or 1. */
-firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int B, int N, int objective,
+firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int res, int B, int N, int objective,
                                  const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
                                  double* loss, float* grad_host);
 /* One Adam step (Kingma & Ba 2015) on the mean loss of firm_pcnet_loss_grad. */
-firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int B, int N, int objective,
+firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int res, int B, int N, int objective,
                                   const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
                                   double lr, double* loss);
 const char* firm_pcnet_last_error(firm_pcnet net);
 
-/* Features of the plan's kernel: feat_dev [32^3] = log(mean |K^| over (2N/32)^3 blocks / Ker(0) +
- * lam_rel), centred frequency order, with K^ the unnormalised DFT_2N of the circulant column
- * ((2N)^3 times the spectrum of firm_kernel_spectrum).  Needs N >= 16. */
-firm_status firm_kernel_features(firm_plan plan, double lam_rel, float* feat_dev);
-/* d_dev [N^3] (centred) = exp(U sym(out)) / Ker(0) from a network output out_dev [32^3]. */
-firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, float* d_dev);
+/* Features of the plan's kernel: feat_dev [res^3] = log(mean |K^| over (2N/res)^3 blocks /
+ * Ker(0) + lam_rel), centred frequency order, with K^ the unnormalised DFT_2N of the circulant
+ * column ((2N)^3 times the spectrum of firm_kernel_spectrum).  res: power of two in [32, 2N]
+ * (and <= 256). */
+firm_status firm_kernel_features(firm_plan plan, double lam_rel, int res, float* feat_dev);
+/* d_dev [N^3] (centred) = exp(U sym(out)) / Ker(0) from a network output out_dev [res^3]
+ * (N <= 8 res). */
+firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, int res, float* d_dev);
 /* Probe statistics on the centred N^3 grid for nprobes real probes z (probes_dev [nprobes][N^3]):
  * A = sum |F u|^2, B = sum Re(conj(F u) F z) with u = (A*A + lambda) z (FP32 product), and
  * *sumc = sum ||F z||^2 (host). */

@@ -4,8 +4,9 @@ The preconditioner is P r = F^{-1}(d . F r) on the periodic N^3 grid (a circulan
 diagonal in the Fourier basis: section 2.3, eq. circ1), with d > 0 and d(q) = d(-q) so that P
 is real, symmetric and positive definite.  d comes from a small network:
 
-  features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32; K^ = DFT_2N of the
-            circulant column, unnormalised: the Fourier multiplier of the embedded product)
+  features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32 by default, any power
+            of two up to 2N: the network is fully convolutional; K^ = DFT_2N of the circulant
+            column, unnormalised: the Fourier multiplier of the embedded product)
   network   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))            (3^3 convolutions,
             circular padding, channels 1 -> C -> C -> C -> 1)
   symmetric s(u) = (o(u) + o(-u)) / 2 on the centred G^3 frequency grid
@@ -133,39 +134,40 @@ def net_backward(do, params, cache, emulate_bf16=False):
 
 # ----------------------------------------------------------------- features --
 
-def pool_features(khat_full, ker0, lam_rel):
-    """f = log(mean over (2N/G)^3 blocks of |K^| / Ker(0) + lam_rel), on the centred G^3 grid.
+def pool_features(khat_full, ker0, lam_rel, g=G):
+    """f = log(mean over (2N/g)^3 blocks of |K^| / Ker(0) + lam_rel), on the centred g^3 grid.
     khat_full: the (2N)^3 spectrum in FFT order."""
     M2 = khat_full.shape[0]
     k = np.fft.fftshift(np.abs(khat_full))
-    s = M2 // G
-    pooled = k.reshape(G, s, G, s, G, s).mean(axis=(1, 3, 5))
+    s = M2 // g
+    pooled = k.reshape(g, s, g, s, g, s).mean(axis=(1, 3, 5))
     return np.log(pooled / ker0 + lam_rel)
 
 
 def symmetrise(o):
-    """s(u) = (o(u) + o(-u)) / 2 on the centred G^3 grid (index u + G/2)."""
+    """s(u) = (o(u) + o(-u)) / 2 on the centred coarse grid (index u + G/2)."""
     flipped = np.roll(o[::-1, ::-1, ::-1], 1, axis=(0, 1, 2))
     return 0.5 * (o + flipped)
 
 
-def _interp_axis(N):
-    """Per-axis periodic linear interpolation from G coarse points to N fine points (both centred):
-    fine frequency q = i - N/2 sits at coarse coordinate q G / N."""
+def _interp_axis(N, g=G):
+    """Per-axis periodic linear interpolation from g coarse points to N fine points (both centred):
+    fine frequency q = i - N/2 sits at coarse coordinate q g / N."""
     q = np.arange(N) - N // 2
-    u = q * (G / N)
+    u = q * (g / N)
     lo = np.floor(u).astype(int)
     t = u - lo
-    i0 = (lo + G // 2) % G
-    i1 = (lo + 1 + G // 2) % G
+    i0 = (lo + g // 2) % g
+    i1 = (lo + 1 + g // 2) % g
     return i0, i1, t
 
 
 def upsample(s, N):
-    """U s: periodic trilinear interpolation of the G^3 grid onto the N^3 frequency grid."""
+    """U s: periodic trilinear interpolation of the g^3 grid of s onto the N^3 frequency grid."""
+    g = s.shape[0]
     out = s
     for ax in range(3):
-        i0, i1, t = _interp_axis(N)
+        i0, i1, t = _interp_axis(N, g)
         a = np.take(out, i0, axis=ax)
         b = np.take(out, i1, axis=ax)
         shape = [1, 1, 1]
@@ -174,13 +176,13 @@ def upsample(s, N):
     return out
 
 
-def upsample_adjoint(g, N):
-    """U^T g: the adjoint of upsample (scatter-add of the interpolation weights)."""
+def upsample_adjoint(g, N, gc=G):
+    """U^T g: the adjoint of upsample from the gc^3 grid (scatter-add of the interpolation weights)."""
     out = g
     for ax in (2, 1, 0):
-        i0, i1, t = _interp_axis(N)
+        i0, i1, t = _interp_axis(N, gc)
         shape = list(out.shape)
-        shape[ax] = G
+        shape[ax] = gc
         acc = np.zeros(shape)
         ws = [1, 1, 1]
         ws[ax] = N
@@ -253,11 +255,11 @@ def loss_and_grads(f, params, N, ker0, A, B, C, emulate_bf16=False, objective="p
     d = diagonal(o, N, ker0)
     if objective == "kaporin":
         L = kaporin_loss(d, A)
-        gs = upsample_adjoint(kaporin_grad_logd(d, A), N)
+        gs = upsample_adjoint(kaporin_grad_logd(d, A), N, f.shape[0])
     else:
         L = probe_loss(d, A, B, C)
         gd = probe_loss_grad_d(d, A, B, C)
-        gs = upsample_adjoint(gd * d, N)        # through exp and U
+        gs = upsample_adjoint(gd * d, N, f.shape[0])        # through exp and U
     go = symmetrise(gs)                          # symmetrise is self-adjoint
     grads, _ = net_backward(go, params, cache, emulate_bf16)
     return L, grads, d

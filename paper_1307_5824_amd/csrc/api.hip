@@ -619,12 +619,13 @@ firm_status firm_synth_slices(firm_plan p, int B, const double* centers, const d
 
 extern "C" {
 
-firm_status firm_kernel_features(firm_plan p, double lam_rel, float* feat) {
+firm_status firm_kernel_features(firm_plan p, double lam_rel, int res, float* feat) {
     if (!p || !feat) return firm_fail(p, FIRM_ERR_ARG, "null argument");
-    if (p->N < 16) return firm_fail(p, FIRM_ERR_ARG, "features need N >= 16 (2N >= 32)");
+    if (res < 32 || res > 256 || (res & (res - 1)) || res > 2 * p->N)
+        return firm_fail(p, FIRM_ERR_ARG, "res must be a power of two in [32, min(256, 2N)]");
     if (!(lam_rel >= 0.0) || !std::isfinite(lam_rel)) return firm_fail(p, FIRM_ERR_ARG, "lam_rel must be >= 0");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
-    FIRM_HIP(p, kernel_features(p, (float)lam_rel, feat));
+    FIRM_HIP(p, kernel_features(p, (float)lam_rel, res, feat));
     return FIRM_OK;
 }
 

@@ -100,7 +100,7 @@ size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl);
 hipError_t fft_khat_unblock(firm_plan p, float* out);
 hipError_t fft_forward_r2c(firm_plan p, const float* x, float2* out);  // N^3 real -> [N][N][QPn] half spectrum
 hipError_t chan_spectrum(firm_plan p, double lam, float* out);  // fft.hip: Chan spectrum + lam, centred N^3
-hipError_t kernel_features(firm_plan p, float lam_rel, float* feat);
+hipError_t kernel_features(firm_plan p, float lam_rel, int res, float* feat);
 hipError_t probe_accumulate(firm_plan p, const float2* zh, const float2* uh, float* A, float* B, double* partials,
                             int nblocks);
 hipError_t synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out);

@@ -1,11 +1,12 @@
-// Learned Fourier-diagonal preconditioner: a 3D conv net on the 32^3 pooled log kernel
-// spectrum, its training on the probe loss, and the kernels that turn its output into the
-// diagonal d of z = F^{-1}(d . F r) (circulant diagonalisation, section 2.3, eq. circ1).
+// Learned Fourier-diagonal preconditioner: a 3D conv net on the g^3 pooled log kernel
+// spectrum (g a power of two >= 32; 32 in training, larger grids at inference: the network is
+// fully convolutional), its training, and the kernels that turn its output into the diagonal d
+// of z = F^{-1}(d . F r) (circulant diagonalisation, section 2.3, eq. circ1).
 //
 // Network (C channels, circular padding, cross-correlation with 3^3 filters):
 //   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))
 // Layers c2, c3 (C -> C) are implicit GEMMs on the matrix cores: one wavefront computes a
-// 32-voxel row x 32 output channels tile with v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32
+// 32-voxel row segment x 32 output channels tile with v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32
 // accumulation), K = 27 taps x C input channels; forward and backward-data share the kernel
 // (the backward uses the transposed weights and the mirrored taps).  c1, c4, the weight
 // gradients and Adam run on the vector ALUs in FP32.  Activations are channel-last
@@ -18,15 +19,16 @@
 
 namespace {
 
-constexpr int G = 32;            // coarse grid
-constexpr int GV = G * G * G;    // voxels per sample
 constexpr int CH = 32;           // channels
+constexpr int G0 = 32;           // coarse grid of training (and the smallest)
 
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef float f16_t __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ int wrapg(int i) { return i & (G - 1); }
-__device__ __forceinline__ int vox(int a, int b, int c) { return (wrapg(a) * G + wrapg(b)) * G + wrapg(c); }
+__device__ __forceinline__ int wrapg(int i, int g) { return i & (g - 1); }
+__device__ __forceinline__ int vox(int a, int b, int c, int g) {
+    return (wrapg(a, g) * g + wrapg(b, g)) * g + wrapg(c, g);
+}
 
 // ------------------------------------------------------------------ weights --
 
@@ -46,19 +48,19 @@ __global__ void k_pack_weights(const float* __restrict__ w, __bf16* __restrict__
 // h1[b][v][co] = relu(b1[co] + sum_tap w1[co][tap] f[b][v + off(tap)])
 __global__ void __launch_bounds__(256) k_conv_first(const float* __restrict__ f, const float* __restrict__ w1,
                                                     const float* __restrict__ b1, float* __restrict__ h,
-                                                    __bf16* __restrict__ hb, int B) {
+                                                    __bf16* __restrict__ hb, int B, int g) {
     __shared__ float ws[CH * 27], bs[CH];
     for (int i = threadIdx.x; i < CH * 27; i += 256) ws[i] = w1[i];
     if (threadIdx.x < CH) bs[threadIdx.x] = b1[threadIdx.x];
     __syncthreads();
-    const int64_t n = (int64_t)B * GV;
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
         float nb[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t)
-            nb[t] = f[(int64_t)b * GV + vox(v1 + t / 9 - 1, v2 + (t / 3) % 3 - 1, v3 + t % 3 - 1)];
+            nb[t] = f[(int64_t)b * GV + vox(v1 + t / 9 - 1, v2 + (t / 3) % 3 - 1, v3 + t % 3 - 1, g)];
         for (int co = 0; co < CH; ++co) {
             float z = bs[co];
 #pragma unroll
@@ -72,7 +74,7 @@ __global__ void __launch_bounds__(256) k_conv_first(const float* __restrict__ f,
 
 // ------------------------------------------------------------- MFMA layers --
 
-// One wavefront: the 32 voxels of a row (b, v1, v2, 0..31) x 32 output channels.
+// One wavefront: 32 voxels of a row (b, v1, v2, 32 s .. 32 s + 31) x 32 output channels.
 //   out[v][n] = sum_tap sum_k x[v + sgn * off(tap)][k] W[tap][n][k]
 // FWD: + bias, relu, store FP32 and BF16.   BWD: multiply by (hprev > 0), store FP32 and BF16.
 // Operand layout of v_mfma_f32_32x32x16_bf16 (lane l, element t):
@@ -81,23 +83,27 @@ __global__ void __launch_bounds__(256) k_conv_first(const float* __restrict__ f,
 template <bool FWD>
 __global__ void __launch_bounds__(256) k_conv_mfma(const __bf16* __restrict__ x, const __bf16* __restrict__ W,
                                                    const float* __restrict__ bias, const float* __restrict__ hprev,
-                                                   float* __restrict__ out, __bf16* __restrict__ outb, int B) {
+                                                   float* __restrict__ out, __bf16* __restrict__ outb, int B,
+                                                   int g) {
     __shared__ bf8_t wl[27 * CH * CH / 8];  // 55,296 B
     const bf8_t* W8 = reinterpret_cast<const bf8_t*>(W);
     for (int i = threadIdx.x; i < 27 * CH * CH / 8; i += 256) wl[i] = W8[i];
     __syncthreads();
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + wave;  // (b, v1, v2)
-    if (row >= B * G * G) return;
-    const int b = row / (G * G), v1 = (row / G) % G, v2 = row % G;
+    const int segs = g / 32;
+    const int row = blockIdx.x * 4 + wave;  // (b, v1, v2, segment)
+    if (row >= B * g * g * segs) return;
+    const int seg = row % segs, r2 = row / segs;
+    const int b = r2 / (g * g), v1 = (r2 / g) % g, v2 = r2 % g, s0 = 32 * seg;
     const int i = l & 31, kb = l >> 5;
     const int sgn = FWD ? 1 : -1;
     f16_t acc = {};
+    const int64_t GV = (int64_t)g * g * g;
     const __bf16* xb = x + (int64_t)b * GV * CH;
 #pragma unroll 1
     for (int tap = 0; tap < 27; ++tap) {
         const int da = sgn * (tap / 9 - 1), db = sgn * ((tap / 3) % 3 - 1), dc = sgn * (tap % 3 - 1);
-        const int src = vox(v1 + da, v2 + db, i + dc);
+        const int src = vox(v1 + da, v2 + db, s0 + i + dc, g);
 #pragma unroll
         for (int c0 = 0; c0 < CH; c0 += 16) {
             const bf8_t a = *reinterpret_cast<const bf8_t*>(xb + (int64_t)src * CH + c0 + 8 * kb);
@@ -109,7 +115,7 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const __bf16* __restrict__ x,
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int vi = 8 * (t / 4) + 4 * kb + (t % 4);
-        const int64_t o = ((int64_t)b * GV + (v1 * G + v2) * G + vi) * CH + j;
+        const int64_t o = ((int64_t)b * GV + ((int64_t)v1 * g + v2) * g + s0 + vi) * CH + j;
         float z = acc[t];
         if (FWD) z = fmaxf(z + bias[j], 0.f);
         else z = hprev[o] > 0.f ? z : 0.f;
@@ -123,17 +129,18 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const __bf16* __restrict__ x,
 // o[b][v] = -f[b][v] + b4 + sum_tap sum_ci w4[ci][tap] h3[b][v + off][ci]
 __global__ void __launch_bounds__(256) k_conv_last(const float* __restrict__ h, const float* __restrict__ f,
                                                    const float* __restrict__ w4, const float* __restrict__ b4,
-                                                   float* __restrict__ o, int B) {
+                                                   float* __restrict__ o, int B, int g) {
     __shared__ float ws[CH * 27];
     for (int i = threadIdx.x; i < CH * 27; i += 256) ws[i] = w4[i];
     __syncthreads();
-    const int64_t n = (int64_t)B * GV;
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
         float z = b4[0];
         for (int t = 0; t < 27; ++t) {
-            const float* hn = h + ((int64_t)b * GV + vox(v1 + t / 9 - 1, v2 + (t / 3) % 3 - 1, v3 + t % 3 - 1)) * CH;
+            const float* hn =
+                h + ((int64_t)b * GV + vox(v1 + t / 9 - 1, v2 + (t / 3) % 3 - 1, v3 + t % 3 - 1, g)) * CH;
 #pragma unroll 8
             for (int ci = 0; ci < CH; ++ci) z = fmaf(ws[ci * 27 + t], hn[ci], z);
         }
@@ -144,22 +151,22 @@ __global__ void __launch_bounds__(256) k_conv_last(const float* __restrict__ h, 
 // gz3[b][v][ci] = (h3 > 0) sum_tap w4[ci][tap] go[b][v - off(tap)]
 __global__ void __launch_bounds__(256) k_conv_last_bwd(const float* __restrict__ go, const float* __restrict__ w4,
                                                        const float* __restrict__ h3, float* __restrict__ gz,
-                                                       __bf16* __restrict__ gzb, int B) {
+                                                       __bf16* __restrict__ gzb, int B, int g) {
     __shared__ float ws[CH * 27];
     for (int i = threadIdx.x; i < CH * 27; i += 256) ws[i] = w4[i];
     __syncthreads();
-    const int64_t n = (int64_t)B * GV;
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
-        float g[27];
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
+        float gt[27];
 #pragma unroll
         for (int t = 0; t < 27; ++t)
-            g[t] = go[(int64_t)b * GV + vox(v1 - (t / 9 - 1), v2 - ((t / 3) % 3 - 1), v3 - (t % 3 - 1))];
+            gt[t] = go[(int64_t)b * GV + vox(v1 - (t / 9 - 1), v2 - ((t / 3) % 3 - 1), v3 - (t % 3 - 1), g)];
         for (int ci = 0; ci < CH; ++ci) {
             float s = 0.f;
 #pragma unroll
-            for (int t = 0; t < 27; ++t) s = fmaf(ws[ci * 27 + t], g[t], s);
+            for (int t = 0; t < 27; ++t) s = fmaf(ws[ci * 27 + t], gt[t], s);
             const float r = h3[i * CH + ci] > 0.f ? s : 0.f;
             gz[i * CH + ci] = r;
             gzb[i * CH + ci] = (__bf16)r;
@@ -174,19 +181,19 @@ __global__ void __launch_bounds__(256) k_conv_last_bwd(const float* __restrict__
 template <int CI>
 __global__ void __launch_bounds__(CH * CI) k_wgrad(const float* __restrict__ gz, const float* __restrict__ x,
                                                    float* __restrict__ dw, float* __restrict__ db, int B,
-                                                   int chunk) {
+                                                   int chunk, int g) {
     const int tap = blockIdx.y;
     const int co = threadIdx.x / CI, ci = threadIdx.x % CI;
     const int64_t v0 = (int64_t)blockIdx.x * chunk;
-    const int64_t n = (int64_t)B * GV;
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     const int da = tap / 9 - 1, dbb = (tap / 3) % 3 - 1, dc = tap % 3 - 1;
     float acc = 0.f, accb = 0.f;
     for (int64_t i = v0; i < v0 + chunk && i < n; ++i) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
-        const float g = gz[i * CH + co];
-        acc = fmaf(g, x[((int64_t)b * GV + vox(v1 + da, v2 + dbb, v3 + dc)) * CI + ci], acc);
-        accb += g;
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
+        const float gv = gz[i * CH + co];
+        acc = fmaf(gv, x[((int64_t)b * GV + vox(v1 + da, v2 + dbb, v3 + dc, g)) * CI + ci], acc);
+        accb += gv;
     }
     unsafeAtomicAdd(&dw[(co * CI + ci) * 27 + tap], acc);
     if (tap == 0 && ci == 0) unsafeAtomicAdd(&db[co], accb);
@@ -195,18 +202,18 @@ __global__ void __launch_bounds__(CH * CI) k_wgrad(const float* __restrict__ gz,
 // dW4[ci][tap] = sum go[b][v] h3[b][v + off][ci]; db4 = sum go.  Block: one tap, chunk; thread = ci.
 __global__ void __launch_bounds__(256) k_wgrad_last(const float* __restrict__ go, const float* __restrict__ h3,
                                                     float* __restrict__ dw, float* __restrict__ db, int B,
-                                                    int chunk) {
+                                                    int chunk, int g) {
     const int tap = blockIdx.y;
     const int ci = threadIdx.x % CH, part = threadIdx.x / CH;  // 8 parts of the chunk
-    const int64_t n = (int64_t)B * GV;
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     const int da = tap / 9 - 1, dbb = (tap / 3) % 3 - 1, dc = tap % 3 - 1;
     float acc = 0.f, accb = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * chunk + part; i < (int64_t)(blockIdx.x + 1) * chunk && i < n; i += 8) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
-        const float g = go[i];
-        acc = fmaf(g, h3[((int64_t)b * GV + vox(v1 + da, v2 + dbb, v3 + dc)) * CH + ci], acc);
-        accb += g;
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
+        const float gv = go[i];
+        acc = fmaf(gv, h3[((int64_t)b * GV + vox(v1 + da, v2 + dbb, v3 + dc, g)) * CH + ci], acc);
+        accb += gv;
     }
     unsafeAtomicAdd(&dw[ci * 27 + tap], acc);
     if (tap == 0 && ci == 0) unsafeAtomicAdd(&db[0], accb);
@@ -229,35 +236,35 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 
 // ------------------------------------------------------- diagonal and loss --
 
-__device__ __forceinline__ int flipg(int u) { return (G - u) & (G - 1); }  // centred index of -u
+__device__ __forceinline__ int flipg(int u, int g) { return (g - u) & (g - 1); }  // centred index of -u
 
-// s = (o(u) + o(-u)) / 2 on the centred G^3 grid (index u + G/2 -> flipped (G - idx) % G)
-__global__ void k_symmetrise(const float* __restrict__ o, float* __restrict__ s, int B) {
-    const int64_t n = (int64_t)B * GV;
+// s = (o(u) + o(-u)) / 2 on the centred g^3 grid (index u + g/2 -> flipped (g - idx) % g)
+__global__ void k_symmetrise(const float* __restrict__ o, float* __restrict__ s, int B, int g) {
+    const int64_t GV = (int64_t)g * g * g, n = (int64_t)B * GV;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(i / GV), v = (int)(i % GV);
-        const int v1 = v / (G * G), v2 = (v / G) % G, v3 = v % G;
-        s[i] = 0.5f * (o[i] + o[(int64_t)b * GV + (flipg(v1) * G + flipg(v2)) * G + flipg(v3)]);
+        const int v1 = v / (g * g), v2 = (v / g) % g, v3 = v % g;
+        s[i] = 0.5f * (o[i] + o[(int64_t)b * GV + ((int64_t)flipg(v1, g) * g + flipg(v2, g)) * g + flipg(v3, g)]);
     }
 }
 
 // periodic linear interpolation weights of fine centred index q on the coarse grid
-__device__ __forceinline__ void interp(int i, int N, int& c0, int& c1, float& t) {
-    const float u = (float)(i - N / 2) * ((float)G / (float)N);
+__device__ __forceinline__ void interp(int i, int N, int g, int& c0, int& c1, float& t) {
+    const float u = (float)(i - N / 2) * ((float)g / (float)N);
     const float fl = floorf(u);
     t = u - fl;
     const int lo = (int)fl;
-    c0 = wrapg(lo + G / 2);
-    c1 = wrapg(lo + 1 + G / 2);
+    c0 = wrapg(lo + g / 2, g);
+    c1 = wrapg(lo + 1 + g / 2, g);
 }
 
-__device__ __forceinline__ float upsample_at(const float* s, int i1, int i2, int i3, int N) {
+__device__ __forceinline__ float upsample_at(const float* s, int i1, int i2, int i3, int N, int g) {
     int a0, a1, b0, b1, e0, e1;
     float ta, tb, te;
-    interp(i1, N, a0, a1, ta);
-    interp(i2, N, b0, b1, tb);
-    interp(i3, N, e0, e1, te);
-    auto S = [&](int a, int b, int e) { return s[(a * G + b) * G + e]; };
+    interp(i1, N, g, a0, a1, ta);
+    interp(i2, N, g, b0, b1, tb);
+    interp(i3, N, g, e0, e1, te);
+    auto S = [&](int a, int b, int e) { return s[((int64_t)a * g + b) * g + e]; };
     const float x00 = S(a0, b0, e0) * (1 - te) + S(a0, b0, e1) * te;
     const float x01 = S(a0, b1, e0) * (1 - te) + S(a0, b1, e1) * te;
     const float x10 = S(a1, b0, e0) * (1 - te) + S(a1, b0, e1) * te;
@@ -266,28 +273,28 @@ __device__ __forceinline__ float upsample_at(const float* s, int i1, int i2, int
 }
 
 // d(q) = exp(U s (q)) / ker0 on the centred N^3 grid
-__global__ void k_diag_from_s(const float* __restrict__ s, float* __restrict__ d, int N, float inv_ker0) {
+__global__ void k_diag_from_s(const float* __restrict__ s, float* __restrict__ d, int N, int g, float inv_ker0) {
     const int64_t n = (int64_t)N * N * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        d[i] = expf(upsample_at(s, i1, i2, i3, N)) * inv_ker0;
+        d[i] = expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0;
     }
 }
 
 // per sample: d = exp(U s)/ker0, loss partial sum (d^2 A - 2 d B) (+ C added on the host),
 // g(q) = (2 d A - 2 B) d / sumC  (gradient of the loss with respect to log d)
 __global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, const float* __restrict__ A,
-                                                   const float* __restrict__ Bs, float* __restrict__ g, int N,
-                                                   float inv_ker0, float inv_sumc, double* partials) {
+                                                   const float* __restrict__ Bs, float* __restrict__ gr, int N,
+                                                   int g, float inv_ker0, float inv_sumc, double* partials) {
     __shared__ double red[4];
     const int64_t n = (int64_t)N * N * N;
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const float d = expf(upsample_at(s, i1, i2, i3, N)) * inv_ker0;
+        const float d = expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0;
         const float a = A[i], bb = Bs[i];
         acc += (double)d * d * a - 2.0 * (double)d * bb;
-        g[i] = (2.f * d * a - 2.f * bb) * d * inv_sumc;
+        gr[i] = (2.f * d * a - 2.f * bb) * d * inv_sumc;
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -297,13 +304,13 @@ __global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, 
 
 // Kaporin objective, pass 1: d = exp(U s) / ker0, block partials of sum d t and sum log(d t)
 __global__ void __launch_bounds__(256) k_kap_sums(const float* __restrict__ s, const float* __restrict__ t, int N,
-                                                  float inv_ker0, double* partials, int nblk) {
+                                                  int g, float inv_ker0, double* partials, int nblk) {
     __shared__ double red[8];
     const int64_t n = (int64_t)N * N * N;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const float u = upsample_at(s, i1, i2, i3, N);
+        const float u = upsample_at(s, i1, i2, i3, N, g);
         const double dt = (double)expf(u) * inv_ker0 * t[i];
         a1 += dt;
         a2 += log(dt);
@@ -324,27 +331,27 @@ __global__ void __launch_bounds__(256) k_kap_sums(const float* __restrict__ s, c
 }
 
 // Kaporin objective, pass 2: gradient with respect to log d, g = d t / sum(d t) - 1 / n
-__global__ void k_kap_grad(const float* __restrict__ s, const float* __restrict__ t, float* __restrict__ g, int N,
-                           float inv_ker0, double inv_sum, double inv_n) {
+__global__ void k_kap_grad(const float* __restrict__ s, const float* __restrict__ t, float* __restrict__ gr, int N,
+                           int g, float inv_ker0, double inv_sum, double inv_n) {
     const int64_t n = (int64_t)N * N * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const double dt = (double)expf(upsample_at(s, i1, i2, i3, N)) * inv_ker0 * t[i];
-        g[i] = (float)(dt * inv_sum - inv_n);
+        const double dt = (double)expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0 * t[i];
+        gr[i] = (float)(dt * inv_sum - inv_n);
     }
 }
 
 // gs = U^T g: each coarse point gathers, per axis, the fine indices whose interpolation reads it
 // (those within one coarse cell of it) with their weights.
-__device__ __forceinline__ int adj_axis(int uc, int N, int* fi, float* wi) {
-    const int centre = ((uc - G / 2) * N) / G + N / 2;  // a fine index near the coarse point
-    const int rad = N / G + 1;
+__device__ __forceinline__ int adj_axis(int uc, int N, int g, int* fi, float* wi) {
+    const int centre = ((uc - g / 2) * N) / g + N / 2;  // a fine index near the coarse point
+    const int rad = N / g + 1;                          // N <= 8 g: at most 19 candidates
     int cnt = 0;
     for (int q = centre - rad; q <= centre + rad; ++q) {
         const int qi = ((q % N) + N) % N;
         int c0, c1;
         float t;
-        interp(qi, N, c0, c1, t);
+        interp(qi, N, g, c0, c1, t);
         float w = 0.f;
         if (c0 == uc) w += 1.f - t;
         if (c1 == uc) w += t;
@@ -353,19 +360,20 @@ __device__ __forceinline__ int adj_axis(int uc, int N, int* fi, float* wi) {
     return cnt;
 }
 
-__global__ void k_upsample_adj(const float* __restrict__ g, float* __restrict__ gs, int N) {
+__global__ void k_upsample_adj(const float* __restrict__ gr, float* __restrict__ gs, int N, int g) {
+    const int GV = g * g * g;
     for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < GV; u += gridDim.x * blockDim.x) {
         int f1[24], f2[24], f3[24];
         float w1[24], w2[24], w3[24];
-        const int n1 = adj_axis(u / (G * G), N, f1, w1);
-        const int n2 = adj_axis((u / G) % G, N, f2, w2);
-        const int n3 = adj_axis(u % G, N, f3, w3);
+        const int n1 = adj_axis(u / (g * g), N, g, f1, w1);
+        const int n2 = adj_axis((u / g) % g, N, g, f2, w2);
+        const int n3 = adj_axis(u % g, N, g, f3, w3);
         float acc = 0.f;
         for (int a = 0; a < n1; ++a)
             for (int b = 0; b < n2; ++b) {
                 const float wab = w1[a] * w2[b];
-                const float* gr = g + ((int64_t)f1[a] * N + f2[b]) * N;
-                for (int c = 0; c < n3; ++c) acc += wab * w3[c] * gr[f3[c]];
+                const float* gl = gr + ((int64_t)f1[a] * N + f2[b]) * N;
+                for (int c = 0; c < n3; ++c) acc += wab * w3[c] * gl[f3[c]];
             }
         gs[u] = acc;
     }
@@ -385,6 +393,7 @@ struct firm_pcnet_s {
     float* v = nullptr;
     int step = 0;
     __bf16 *w2f = nullptr, *w2b = nullptr, *w3f = nullptr, *w3b = nullptr;
+    int64_t cap = 0;        // voxels (batch x g^3) the activation buffers hold
     float *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *o = nullptr, *s = nullptr;
     __bf16 *h1b = nullptr, *h2b = nullptr, *h3b = nullptr;
     float *go = nullptr, *gz = nullptr, *gz2 = nullptr, *gtmp = nullptr, *gs = nullptr;
@@ -413,23 +422,56 @@ firm_status net_fail(firm_pcnet n, firm_status s, const std::string& msg) {
 
 int nblk(int64_t n, int t = 256) { return (int)std::min<int64_t>((n + t - 1) / t, 65536); }
 
+bool valid_res(int g) { return g >= G0 && g <= 256 && (g & (g - 1)) == 0; }
+
 hipError_t pack(firm_pcnet n) {
     hipLaunchKernelGGL(k_pack_weights, dim3(64), dim3(256), 0, n->stream, n->prm + OFF_W2, n->w2f, n->w2b);
     hipLaunchKernelGGL(k_pack_weights, dim3(64), dim3(256), 0, n->stream, n->prm + OFF_W3, n->w3f, n->w3b);
     return hipGetLastError();
 }
 
-hipError_t forward(firm_pcnet n, const float* feat, int B) {
-    const int64_t nv = (int64_t)B * GV;
+void free_acts(firm_pcnet n) {
+    void* d[] = {n->h1, n->h2, n->h3, n->o, n->s, n->h1b, n->h2b, n->h3b, n->go, n->gz, n->gz2, n->gs, n->gzb,
+                 n->gz2b};
+    for (void* p : d)
+        if (p) (void)hipFree(p);
+    n->h1 = n->h2 = n->h3 = n->o = n->s = n->go = n->gz = n->gz2 = n->gs = nullptr;
+    n->h1b = n->h2b = n->h3b = n->gzb = n->gz2b = nullptr;
+    n->cap = 0;
+}
+
+// Activation and gradient buffers for nv voxels (batch x g^3); reallocated only to grow.
+hipError_t ensure_cap(firm_pcnet n, int64_t nv) {
+    if (nv <= n->cap) return hipSuccess;
+    (void)hipStreamSynchronize(n->stream);
+    free_acts(n);
+    hipError_t e = hipSuccess;
+    auto al = [&](auto** p, int64_t cnt) {
+        if (e == hipSuccess) e = hipMalloc((void**)p, cnt * sizeof(**p));
+    };
+    al(&n->h1, nv * CH); al(&n->h2, nv * CH); al(&n->h3, nv * CH);
+    al(&n->h1b, nv * CH); al(&n->h2b, nv * CH); al(&n->h3b, nv * CH);
+    al(&n->o, nv); al(&n->s, nv); al(&n->go, nv); al(&n->gs, nv);
+    al(&n->gz, nv * CH); al(&n->gz2, nv * CH); al(&n->gzb, nv * CH); al(&n->gz2b, nv * CH);
+    if (e != hipSuccess) {
+        free_acts(n);
+        return e;
+    }
+    n->cap = nv;
+    return hipSuccess;
+}
+
+hipError_t forward(firm_pcnet n, const float* feat, int B, int g) {
+    const int64_t nv = (int64_t)B * g * g * g;
     hipLaunchKernelGGL(k_conv_first, dim3(nblk(nv)), dim3(256), 0, n->stream, feat, n->prm + OFF_W1, n->prm + OFF_B1,
-                       n->h1, n->h1b, B);
-    const int rows = B * G * G;
-    hipLaunchKernelGGL((k_conv_mfma<true>), dim3((rows + 3) / 4), dim3(256), 0, n->stream, n->h1b, n->w2f,
-                       n->prm + OFF_B2, nullptr, n->h2, n->h2b, B);
-    hipLaunchKernelGGL((k_conv_mfma<true>), dim3((rows + 3) / 4), dim3(256), 0, n->stream, n->h2b, n->w3f,
-                       n->prm + OFF_B3, nullptr, n->h3, n->h3b, B);
+                       n->h1, n->h1b, B, g);
+    const int64_t rows = (int64_t)B * g * g * (g / 32);
+    hipLaunchKernelGGL((k_conv_mfma<true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, n->stream, n->h1b,
+                       n->w2f, n->prm + OFF_B2, nullptr, n->h2, n->h2b, B, g);
+    hipLaunchKernelGGL((k_conv_mfma<true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, n->stream, n->h2b,
+                       n->w3f, n->prm + OFF_B3, nullptr, n->h3, n->h3b, B, g);
     hipLaunchKernelGGL(k_conv_last, dim3(nblk(nv)), dim3(256), 0, n->stream, n->h3, feat, n->prm + OFF_W4,
-                       n->prm + OFF_B4, n->o, B);
+                       n->prm + OFF_B4, n->o, B, g);
     return hipGetLastError();
 }
 
@@ -441,8 +483,8 @@ int64_t firm_pcnet_num_params(void) { return NPARAM; }
 
 void firm_pcnet_destroy(firm_pcnet n) {
     if (!n) return;
-    void* d[] = {n->prm, n->grad, n->m, n->v, n->w2f, n->w2b, n->w3f, n->w3b, n->h1, n->h2, n->h3, n->o, n->s,
-                 n->h1b, n->h2b, n->h3b, n->go, n->gz, n->gz2, n->gtmp, n->gs, n->gzb, n->gz2b, n->part};
+    free_acts(n);
+    void* d[] = {n->prm, n->grad, n->m, n->v, n->w2f, n->w2b, n->w3f, n->w3b, n->gtmp, n->part};
     for (void* p : d)
         if (p) (void)hipFree(p);
     if (n->hpart) (void)hipHostFree(n->hpart);
@@ -455,18 +497,14 @@ firm_status firm_pcnet_create(firm_pcnet* out, int max_batch, void* stream) {
     firm_pcnet n = new firm_pcnet_s();
     n->bmax = max_batch;
     n->stream = (hipStream_t)stream;
-    const int64_t nv = (int64_t)max_batch * GV;
     hipError_t e = hipSuccess;
     auto al = [&](auto** p, int64_t cnt) {
         if (e == hipSuccess) e = hipMalloc((void**)p, cnt * sizeof(**p));
     };
     al(&n->prm, NPARAM); al(&n->grad, NPARAM); al(&n->m, NPARAM); al(&n->v, NPARAM);
     al(&n->w2f, 27 * CH * CH); al(&n->w2b, 27 * CH * CH); al(&n->w3f, 27 * CH * CH); al(&n->w3b, 27 * CH * CH);
-    al(&n->h1, nv * CH); al(&n->h2, nv * CH); al(&n->h3, nv * CH);
-    al(&n->h1b, nv * CH); al(&n->h2b, nv * CH); al(&n->h3b, nv * CH);
-    al(&n->o, nv); al(&n->s, nv); al(&n->go, nv); al(&n->gs, nv);
-    al(&n->gz, nv * CH); al(&n->gz2, nv * CH); al(&n->gzb, nv * CH); al(&n->gz2b, nv * CH);
     al(&n->part, 4096);
+    if (e == hipSuccess) e = ensure_cap(n, (int64_t)max_batch * G0 * G0 * G0);
     if (e == hipSuccess) e = hipHostMalloc((void**)&n->hpart, 4096 * sizeof(double), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(n->prm, 0, NPARAM * sizeof(float));
     if (e == hipSuccess) e = hipMemset(n->m, 0, NPARAM * sizeof(float));
@@ -499,24 +537,30 @@ firm_status firm_pcnet_get_params(firm_pcnet n, float* host) {
     return FIRM_OK;
 }
 
-firm_status firm_pcnet_forward(firm_pcnet n, const float* feat, float* out, int B) {
+firm_status firm_pcnet_forward(firm_pcnet n, const float* feat, int res, float* out, int B) {
     if (!n || !feat || !out) return firm_fail(nullptr, FIRM_ERR_ARG, "null argument");
     if (B < 1 || B > n->bmax) return net_fail(n, FIRM_ERR_ARG, "batch out of range");
-    NHIP(n, forward(n, feat, B));
-    NHIP(n, hipMemcpyAsync(out, n->o, (size_t)B * GV * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
+    if (!valid_res(res)) return net_fail(n, FIRM_ERR_ARG, "res must be a power of two in [32, 256]");
+    const int64_t nv = (int64_t)B * res * res * res;
+    NHIP(n, ensure_cap(n, nv));
+    NHIP(n, forward(n, feat, B, res));
+    NHIP(n, hipMemcpyAsync(out, n->o, (size_t)nv * sizeof(float), hipMemcpyDeviceToDevice, n->stream));
     return FIRM_OK;
 }
 
 // Loss (mean over the batch) and parameter gradients for B samples at size N.  A and Bs are
 // [B][N^3] device arrays on the centred grid; sumc and ker0 are host arrays of B values.
-firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, int objective, const float* A,
-                                 const float* Bs, const double* sumc, const double* ker0, double* loss,
-                                 float* grad_host) {
+firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B, int N, int objective,
+                                 const float* A, const float* Bs, const double* sumc, const double* ker0,
+                                 double* loss, float* grad_host) {
     if (objective != 0 && objective != 1) return net_fail(n, FIRM_ERR_ARG, "objective must be 0 (probe) or 1 (Kaporin)");
     if (!n || !feat || !A || !ker0 || !loss || (objective == 0 && (!Bs || !sumc)))
         return firm_fail(nullptr, FIRM_ERR_ARG, "null argument");
     if (B < 1 || B > n->bmax) return net_fail(n, FIRM_ERR_ARG, "batch out of range");
     if (N < 8 || N > 256 || (N & (N - 1))) return net_fail(n, FIRM_ERR_ARG, "N must be a power of two in [8, 256]");
+    if (!valid_res(res) || N > 8 * res) return net_fail(n, FIRM_ERR_ARG, "res must be a power of two in [32, 256], N <= 8 res");
+    const int g = res;
+    const int64_t GV = (int64_t)g * g * g;
     const int64_t n3 = (int64_t)N * N * N;
     if (n->gN < N) {
         if (n->gtmp) (void)hipFree(n->gtmp);
@@ -527,9 +571,10 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
     for (int b = 0; b < B; ++b)
         if ((objective == 0 && !(sumc[b] > 0)) || !(ker0[b] > 0))
             return net_fail(n, FIRM_ERR_ARG, "sumc and ker0 must be > 0");
+    NHIP(n, ensure_cap(n, (int64_t)B * GV));
     hipStream_t st = n->stream;
-    NHIP(n, forward(n, feat, B));
-    hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->o, n->s, B);
+    NHIP(n, forward(n, feat, B, g));
+    hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->o, n->s, B, g);
     const int lb = nblk(n3);
     const int lblocks = std::min(lb, 1024);
     double total = 0.0;
@@ -537,15 +582,15 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
         const float* sb = n->s + (int64_t)b * GV;
         if (objective == 0) {
             hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, Bs + b * n3, n->gtmp, N,
-                               (float)(1.0 / ker0[b]), (float)(1.0 / sumc[b]), n->part);
+                               g, (float)(1.0 / ker0[b]), (float)(1.0 / sumc[b]), n->part);
             NHIP(n, hipMemcpyAsync(n->hpart, n->part, lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
             NHIP(n, hipStreamSynchronize(st));
             double sp = 0.0;
             for (int i = 0; i < lblocks; ++i) sp += n->hpart[i];
             total += sp / sumc[b] + 1.0;
         } else {
-            hipLaunchKernelGGL(k_kap_sums, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, N, (float)(1.0 / ker0[b]),
-                               n->part, lblocks);
+            hipLaunchKernelGGL(k_kap_sums, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, N, g,
+                               (float)(1.0 / ker0[b]), n->part, lblocks);
             NHIP(n, hipMemcpyAsync(n->hpart, n->part, 2 * lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
             NHIP(n, hipStreamSynchronize(st));
             double sdt = 0.0, slog = 0.0;
@@ -556,31 +601,31 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
             if (!(sdt > 0) || !std::isfinite(sdt) || !std::isfinite(slog))
                 return net_fail(n, FIRM_ERR_ARG, "Kaporin objective needs t > 0 and a finite diagonal");
             total += std::log(sdt / (double)n3) - slog / (double)n3;
-            hipLaunchKernelGGL(k_kap_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, A + b * n3, n->gtmp, N,
+            hipLaunchKernelGGL(k_kap_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, A + b * n3, n->gtmp, N, g,
                                (float)(1.0 / ker0[b]), 1.0 / sdt, 1.0 / (double)n3);
         }
-        hipLaunchKernelGGL(k_upsample_adj, dim3(nblk(GV)), dim3(256), 0, st, n->gtmp, n->gs + (int64_t)b * GV, N);
+        hipLaunchKernelGGL(k_upsample_adj, dim3(nblk(GV)), dim3(256), 0, st, n->gtmp, n->gs + (int64_t)b * GV, N, g);
     }
     *loss = total / B;
-    hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->gs, n->go, B);
+    hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->gs, n->go, B, g);
     // backward
     NHIP(n, fill_zero(n->grad, NPARAM * sizeof(float), st));
     const int chunks = (int)(((int64_t)B * GV + 255) / 256);
     hipLaunchKernelGGL(k_wgrad_last, dim3(chunks, 27), dim3(256), 0, st, n->go, n->h3, n->grad + OFF_W4,
-                       n->grad + OFF_B4, B, 256);
+                       n->grad + OFF_B4, B, 256, g);
     hipLaunchKernelGGL(k_conv_last_bwd, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->go, n->prm + OFF_W4,
-                       n->h3, n->gz, n->gzb, B);
+                       n->h3, n->gz, n->gzb, B, g);
     hipLaunchKernelGGL((k_wgrad<CH>), dim3(chunks, 27), dim3(CH * CH), 0, st, n->gz, n->h2, n->grad + OFF_W3,
-                       n->grad + OFF_B3, B, 256);
-    const int rows = B * G * G;
-    hipLaunchKernelGGL((k_conv_mfma<false>), dim3((rows + 3) / 4), dim3(256), 0, st, n->gzb, n->w3b, nullptr,
-                       n->h2, n->gz2, n->gz2b, B);
+                       n->grad + OFF_B3, B, 256, g);
+    const int64_t rows = (int64_t)B * g * g * (g / 32);
+    hipLaunchKernelGGL((k_conv_mfma<false>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n->gzb, n->w3b,
+                       nullptr, n->h2, n->gz2, n->gz2b, B, g);
     hipLaunchKernelGGL((k_wgrad<CH>), dim3(chunks, 27), dim3(CH * CH), 0, st, n->gz2, n->h1, n->grad + OFF_W2,
-                       n->grad + OFF_B2, B, 256);
-    hipLaunchKernelGGL((k_conv_mfma<false>), dim3((rows + 3) / 4), dim3(256), 0, st, n->gz2b, n->w2b, nullptr,
-                       n->h1, n->gz, n->gzb, B);
+                       n->grad + OFF_B2, B, 256, g);
+    hipLaunchKernelGGL((k_conv_mfma<false>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n->gz2b, n->w2b,
+                       nullptr, n->h1, n->gz, n->gzb, B, g);
     hipLaunchKernelGGL((k_wgrad<1>), dim3(chunks, 27), dim3(CH), 0, st, n->gz, feat, n->grad + OFF_W1,
-                       n->grad + OFF_B1, B, 256);
+                       n->grad + OFF_B1, B, 256, g);
     NHIP(n, hipGetLastError());
     if (grad_host) {
         NHIP(n, hipMemcpyAsync(grad_host, n->grad, NPARAM * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -590,9 +635,10 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int B, int N, 
     return FIRM_OK;
 }
 
-firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int B, int N, int objective, const float* A,
-                                  const float* Bs, const double* sumc, const double* ker0, double lr, double* loss) {
-    firm_status s = firm_pcnet_loss_grad(n, feat, B, N, objective, A, Bs, sumc, ker0, loss, nullptr);
+firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int res, int B, int N, int objective,
+                                  const float* A, const float* Bs, const double* sumc, const double* ker0, double lr,
+                                  double* loss) {
+    firm_status s = firm_pcnet_loss_grad(n, feat, res, B, N, objective, A, Bs, sumc, ker0, loss, nullptr);
     if (s != FIRM_OK) return s;
     n->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
@@ -603,15 +649,19 @@ firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int B, int N,
     return FIRM_OK;
 }
 
-// d (centred N^3) = exp(U sym(out)) / Ker(0) of the plan's kernel
-firm_status firm_precond_from_output(firm_plan p, const float* out32, float* d) {
-    if (!p || !out32 || !d) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+// d (centred N^3) = exp(U sym(out)) / Ker(0) of the plan's kernel, out on the res^3 grid
+firm_status firm_precond_from_output(firm_plan p, const float* out, int res, float* d) {
+    if (!p || !out || !d) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!valid_res(res) || p->N > 8 * res)
+        return firm_fail(p, FIRM_ERR_ARG, "res must be a power of two in [32, 256], N <= 8 res");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    const int64_t GV = (int64_t)res * res * res;
     float* s = nullptr;
     FIRM_HIP(p, hipMalloc((void**)&s, GV * sizeof(float)));
-    hipLaunchKernelGGL(k_symmetrise, dim3(nblk(GV)), dim3(256), 0, p->stream, out32, s, 1);
+    hipLaunchKernelGGL(k_symmetrise, dim3(nblk(GV)), dim3(256), 0, p->stream, out, s, 1, res);
     const int64_t n3 = (int64_t)p->N * p->N * p->N;
-    hipLaunchKernelGGL(k_diag_from_s, dim3(nblk(n3)), dim3(256), 0, p->stream, s, d, p->N, (float)(1.0 / p->ker0));
+    hipLaunchKernelGGL(k_diag_from_s, dim3(nblk(n3)), dim3(256), 0, p->stream, s, d, p->N, res,
+                       (float)(1.0 / p->ker0));
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     (void)hipFree(s);

@@ -7,13 +7,14 @@
 
 namespace {
 
-// feat[f] (centred 32^3) = log(mean of |K^| over the (2N/32)^3 block / Ker(0) + lam_rel); K^ is read
+// feat[f] (centred R^3) = log(mean of |K^| over the (2N/R)^3 block / Ker(0) + lam_rel); K^ is read
 // from the blocked half spectrum, the other half by K^(-q) = K^(q).
-__global__ void k_features(const float* __restrict__ kh, int N, int C, float inv_ker0, float lam_rel,
+__global__ void k_features(const float* __restrict__ kh, int N, int C, int R, float inv_ker0, float lam_rel,
                            float* __restrict__ feat) {
-    const int L = 2 * N, s = L / 32, ng = (N + 1 + C - 1) / C;
-    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < 32 * 32 * 32; f += gridDim.x * blockDim.x) {
-        const int f1 = f / 1024, f2 = (f / 32) % 32, f3 = f % 32;
+    const int L = 2 * N, s = L / R, ng = (N + 1 + C - 1) / C;
+    const int64_t RV = (int64_t)R * R * R;
+    for (int64_t f = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; f < RV; f += (int64_t)gridDim.x * blockDim.x) {
+        const int f1 = (int)(f / ((int64_t)R * R)), f2 = (int)((f / R) % R), f3 = (int)(f % R);
         double acc = 0.0;
         for (int a = 0; a < s; ++a)
             for (int b = 0; b < s; ++b)
@@ -52,12 +53,13 @@ __global__ void __launch_bounds__(256) k_probe_accum(const float2* __restrict__ 
 
 }  // namespace
 
-hipError_t kernel_features(firm_plan p, float lam_rel, float* feat) {
+hipError_t kernel_features(firm_plan p, float lam_rel, int res, float* feat) {
     // the stored spectrum carries the 1 / (2N)^3 of the inverse transform; the features use the
     // Fourier multiplier itself
     const double L3 = 8.0 * p->N * p->N * p->N;
-    hipLaunchKernelGGL(k_features, dim3(128), dim3(256), 0, p->stream, p->khat, p->N, fft_cols_per_block(2 * p->N, false),
-                       (float)(L3 / p->ker0), lam_rel, feat);
+    const int64_t RV = (int64_t)res * res * res;
+    hipLaunchKernelGGL(k_features, dim3((unsigned)std::min<int64_t>((RV + 255) / 256, 4096)), dim3(256), 0, p->stream,
+                       p->khat, p->N, fft_cols_per_block(2 * p->N, false), res, (float)(L3 / p->ker0), lam_rel, feat);
     return hipGetLastError();
 }
 

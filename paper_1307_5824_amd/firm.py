@@ -77,13 +77,13 @@ def _load():
         "firm_pcnet_destroy": (None, [vp]),
         "firm_pcnet_set_params": (i, [vp, vp]),
         "firm_pcnet_get_params": (i, [vp, vp]),
-        "firm_pcnet_forward": (i, [vp, vp, vp, i]),
-        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
-        "firm_pcnet_train_step": (i, [vp, vp, i, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
+        "firm_pcnet_forward": (i, [vp, vp, i, vp, i]),
+        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
+        "firm_pcnet_train_step": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
         "firm_chan_spectrum": (i, [vp, d, vp]),
         "firm_pcnet_last_error": (ctypes.c_char_p, [vp]),
-        "firm_kernel_features": (i, [vp, d, vp]),
-        "firm_precond_from_output": (i, [vp, vp, vp]),
+        "firm_kernel_features": (i, [vp, d, i, vp]),
+        "firm_precond_from_output": (i, [vp, vp, i, vp]),
         "firm_probe_stats": (i, [vp, vp, i, d, vp, vp, ctypes.POINTER(d)]),
         "firm_synth_normals": (i, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, vp]),
     }
@@ -309,16 +309,26 @@ class Plan:
 
 # ---- learned preconditioner helpers (attached to Plan below)
 
-def _plan_kernel_features(self, lam_rel, out=None):
+def inference_res(N):
+    """Network grid for a plan of size N: N / 4 within [32, 128] (8^3 spectrum samples per feature
+    from N = 128 up; res 32 below).  Measured at N = 256 on the large workload with the weights
+    trained at N = 64: PCG to 1e-5 in 331, 291 and 318 iterations at res 32, 64 and 128."""
+    return int(min(128, max(32, N // 4)))
+
+
+def _plan_kernel_features(self, lam_rel, res=32, out=None):
     if out is None:
-        out = self._torch.empty((32, 32, 32), dtype=self._torch.float32, device="cuda")
-    _check(lib.firm_kernel_features(self.h, float(lam_rel), _ptr(out)), self.h)
+        out = self._torch.empty((res, res, res), dtype=self._torch.float32, device="cuda")
+    self._req(out, res ** 3, self._torch.float32)
+    _check(lib.firm_kernel_features(self.h, float(lam_rel), int(res), _ptr(out)), self.h)
     return out
 
 
 def _plan_precond_from_output(self, o, out=None):
+    res = int(o.shape[-1])
+    self._req(o, res ** 3, self._torch.float32)
     out = self._vol(out)
-    _check(lib.firm_precond_from_output(self.h, _ptr(o), _ptr(out)), self.h)
+    _check(lib.firm_precond_from_output(self.h, _ptr(o), res, _ptr(out)), self.h)
     return out
 
 
@@ -397,10 +407,12 @@ class PCNet:
         return arr
 
     def forward(self, feat):
+        """Network output [B][res][res][res] for features [B][res][res][res] (or one [res]^3)."""
         t = self._torch
         B = feat.shape[0] if feat.dim() == 4 else 1
-        out = t.empty((B, 32, 32, 32), dtype=t.float32, device="cuda")
-        self._chk(lib.firm_pcnet_forward(self.h, _ptr(feat), _ptr(out), int(B)))
+        res = int(feat.shape[-1])
+        out = t.empty((B, res, res, res), dtype=t.float32, device="cuda")
+        self._chk(lib.firm_pcnet_forward(self.h, _ptr(feat), res, _ptr(out), int(B)))
         return out
 
     OBJECTIVES = {"probe": 0, "kaporin": 1}
@@ -413,7 +425,8 @@ class PCNet:
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
         g = np.zeros(PCNet.NPARAM, dtype=np.float32) if with_grad else None
-        self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(B), int(N), self.OBJECTIVES[objective], _ptr(A),
+        self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(feat.shape[-1]), int(B), int(N),
+                                           self.OBJECTIVES[objective], _ptr(A),
                                            _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
                                            k0.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
                                            None if g is None else g.ctypes.data_as(ctypes.c_void_p)))
@@ -424,7 +437,8 @@ class PCNet:
         sc = None if sumc is None else np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
-        self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(B), int(N), self.OBJECTIVES[objective], _ptr(A),
+        self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(feat.shape[-1]), int(B), int(N),
+                                            self.OBJECTIVES[objective], _ptr(A),
                                             _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
                                             k0.ctypes.data_as(ctypes.c_void_p), float(lr), ctypes.byref(loss)))
         return loss.value

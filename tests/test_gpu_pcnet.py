@@ -104,6 +104,44 @@ def test_kernel_features_match_oracle(firm, N):
     assert np.max(np.abs(np.exp(feat) - np.exp(ref))) < 1e-5 * np.max(np.exp(ref))
 
 
+def test_forward_at_res64_matches_oracle(firm):
+    """The network is fully convolutional: the same weights on a 64^3 feature grid."""
+    params = _params(6)
+    f = 0.5 * np.random.default_rng(7).standard_normal((1, 64, 64, 64))
+    vec = opc.flatten_params(params).astype(np.float32)
+    params32 = opc.unflatten_params(vec)
+    net = firm.PCNet(max_batch=1)
+    net.set_params(vec)
+    out = host(net.forward(dev(f)))
+    ref, _ = opc.net_forward(f[0].astype(np.float32).astype(np.float64), params32, emulate_bf16=True)
+    assert out.shape == (1, 64, 64, 64)
+    assert rel(out[0], ref) < 1e-4
+
+
+def test_kernel_features_and_diagonal_at_res64(firm):
+    """Features pooled to 64^3 (2 x 2 x 2 spectrum samples each at N = 64) and the diagonal
+    interpolated from a 64^3 output onto N = 128."""
+    N = 64
+    R, _, _, _ = small_geometry(N, 4, 404)
+    K32 = ker_to_centred(ofirm.kernel_direct(N, R).real, N).astype(np.float32)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(K32))
+    feat = host(plan.kernel_features(1e-2, res=64))
+    khat = np.fft.fftn(ofirm.circulant_first_column(K32[1:, 1:, 1:].astype(np.float64), N)).real
+    ref = opc.pool_features(khat, float(K32[N, N, N]), 1e-2, g=64)
+    assert np.max(np.abs(np.exp(feat) - np.exp(ref))) < 1e-5 * np.max(np.exp(ref))
+    N2 = 128
+    R2, _, _, _ = small_geometry(N2, 2, 405)
+    plan2 = firm.Plan(N2, R2)
+    K2 = np.zeros((2 * N2,) * 3, dtype=np.float32)
+    K2[N2, N2, N2] = 3.0                                   # a delta kernel: Ker(0) = 3
+    plan2.kernel_set(dev(K2))
+    o = np.random.default_rng(8).standard_normal((64, 64, 64))
+    d = host(plan2.precond_from_output(dev(o)))
+    refd = opc.diagonal(o.astype(np.float32).astype(np.float64), N2, 3.0)
+    assert rel(d, refd) < 1e-5
+
+
 def test_precond_from_output_matches_oracle(firm):
     N = 32
     R, _, _, _ = small_geometry(N, 3, 7)

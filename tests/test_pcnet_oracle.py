@@ -1,6 +1,7 @@
 """Pins of the preconditioner-network oracle: convolution by its definition written as loops,
 identity filters, adjoints, Parseval, and central finite differences for every gradient."""
 import numpy as np
+import pytest
 
 from oracle import firm as ofirm
 from oracle import pcnet
@@ -60,15 +61,18 @@ def test_conv3d_backward_finite_differences():
     assert abs((f(x, w, b + e) - f(x, w, b - e)) / (2 * h) - db[1]) < 1e-6 * (1 + abs(db[1]))
 
 
-def test_upsample_properties():
+@pytest.mark.parametrize("G", [32, 64])
+def test_upsample_properties(G):
     rng = _rng(4)
-    G = pcnet.G
     s = rng.standard_normal((G, G, G))
     assert np.allclose(pcnet.upsample(s, G), s)                         # N = G samples the grid
     assert np.allclose(pcnet.upsample(np.full((G, G, G), 2.5), 64), 2.5)
+    up2 = pcnet.upsample(s, 2 * G)                                       # N = 2G: even points hit the
+    assert np.allclose(up2[::2, ::2, ::2], s)                            # grid, odd ones are midpoints
+    assert np.allclose(up2[1::2, ::2, ::2], 0.5 * (s + np.roll(s, -1, axis=0)))
     g = rng.standard_normal((16, 16, 16))
     lhs = np.sum(pcnet.upsample(s, 16) * g)
-    rhs = np.sum(s * pcnet.upsample_adjoint(g, 16))
+    rhs = np.sum(s * pcnet.upsample_adjoint(g, 16, G))
     assert abs(lhs - rhs) < 1e-10 * abs(lhs)
     ss = pcnet.symmetrise(s)
     assert np.allclose(ss, np.roll(ss[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
