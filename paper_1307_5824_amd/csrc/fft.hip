@@ -306,11 +306,15 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, S kad
         if (HALF && t >= 4) v[t] = mkv<V>(0, 0);  // e >= L / 2
         else v[t] = (valid && e < nin) ? d0[e * s_elem] : mkv<V>(0, 0);
     }
+    // the spectrum values are loaded before the forward transform, which hides their latency
+    S kv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) kv[t] = k0[(j + t * T) * C];
     if (TWL) __syncthreads();  // the twiddle table is in place
     fft_reg<L, C, false>(v, lds, twp, (S)-1);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        const S k = k0[(j + t * T) * C] + kadd;
+        const S k = kv[t] + kadd;
         v[t] = mkv<V>(v[t].x * k, v[t].y * k);
     }
     fft_reg<L, C, false>(v, lds, twp, (S)1);
