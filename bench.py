@@ -234,6 +234,30 @@ def main():
     del imgs, b_img
     print(f"images: synth {synth_img_ms:.1f} ms, images_to_slices {img2sl_ms:.1f} ms", file=sys.stderr, flush=True)
 
+    # the 16-bit spectrum (option khat_bf16; reduced precision, so not `value`): products/s, the
+    # product's error against the FP32 spectrum's, and the refined solve to the same tolerance
+    p16 = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
+                    precision=args.precision, lambda_relative=1, khat_bf16=1)
+    p16.kernel_set(plan.kernel_get())
+    y16 = p16.apply_AtA(x_probe, wl.lam)
+    y32 = plan.apply_AtA(x_probe, wl.lam)
+    err16 = (torch.linalg.norm((y16 - y32).double()) / torch.linalg.norm(y32.double())).item()
+    e = [ev() for _ in range(4)]
+    e[0].record()
+    for _ in range(args.apply_reps):
+        p16.apply_AtA(x_probe, wl.lam, y16)
+    e[1].record()
+    _, rep16 = p16.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter)
+    e[2].record()
+    torch.cuda.synchronize()
+    k16 = {"applies_per_s": round(args.apply_reps / (e[0].elapsed_time(e[1]) / 1e3), 2),
+           "product_rel_err_vs_fp32_spectrum": float(f"{err16:.3g}"),
+           "cg_time_to_tol_s": round(e[1].elapsed_time(e[2]) / 1e3, 4), "cg_iters": rep16["iters"],
+           "cg_true_rel_res": rep16["true_rel_res"]}
+    p16.close()
+    del y16, y32
+    print(f"16-bit spectrum: {k16}", file=sys.stderr, flush=True)
+
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
     pass_ms = plan.apply_AtA_timed(x_probe, wl.lam, 50)
     pb = pass_bytes(N)
@@ -282,6 +306,7 @@ def main():
         "forward_project_ms": round(fwd_ms, 2),
         "data_rel_residual": round(data_res, 5),
         "images_to_slices_ms": round(img2sl_ms, 2),
+        "khat_bf16": k16,
         "synth_images_ms": round(synth_img_ms, 2),
         "roofline": roofline,
     }

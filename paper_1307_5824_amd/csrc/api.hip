@@ -145,7 +145,7 @@ void firm_plan_destroy(firm_plan p) {
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
                    p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec,
-                   p->img_ws};
+                   p->img_ws, p->khat16, p->shtab};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->host_scal) (void)hipHostFree(p->host_scal);
@@ -196,7 +196,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     if (opt) o = *opt;
     if (o.kb_width == 0) o.kb_width = 7;
     if (o.kb_width < 4 || o.kb_width > 8) return firm_fail(nullptr, FIRM_ERR_ARG, "kb_width must be in [4, 8]");
-    if (o.reserved != 0) return firm_fail(nullptr, FIRM_ERR_ARG, "reserved option must be 0");
+    if (o.khat_bf16 != 0 && o.khat_bf16 != 1) return firm_fail(nullptr, FIRM_ERR_ARG, "khat_bf16 must be 0 or 1");
     if (o.check_every < 0) return firm_fail(nullptr, FIRM_ERR_ARG, "check_every must be >= 0");
     if (o.precision < 0 || o.precision > 2) return firm_fail(nullptr, FIRM_ERR_ARG, "precision must be 0, 1 or 2");
     if (o.lambda_relative != 0 && o.lambda_relative != 1)
@@ -217,6 +217,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     p->precision = o.precision;
     p->lambda_relative = o.lambda_relative;
     p->inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+    p->khat_bf16 = o.khat_bf16;
 
     // geometry: columns 1 and 2 of R^{-1} = R^T are rows 1 and 2 of R; normal = c1 x c2
     std::vector<double> c12((size_t)M * 6);
@@ -272,6 +273,10 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->tw, (size_t)FIRM_TWN));
     chk(dalloc(&p->kerc, (size_t)(N2 * N2 * N2)));
     chk(dalloc(&p->khat, blocked_spectrum_elems(2 * N, 2 * N, N + 1, false)));
+    if (p->khat_bf16) {
+        chk(dalloc(&p->khat16, blocked_spectrum_elems(2 * N, 2 * N, N + 1, false)));
+        chk(dalloc(&p->shtab, (size_t)448));
+    }
     chk(dalloc(&p->T1, (size_t)((int64_t)N * N * p->QP)));
     chk(dalloc(&p->T2, (size_t)fft_t2_elems(N, false)));
     chk(dalloc(&p->r, (size_t)n3));

@@ -269,13 +269,110 @@ k_cols(const typename VecOf<S>::V* __restrict__ src, void* __restrict__ dstv, in
     }
 }
 
+// ---- 16-bit spectrum (option khat_bf16) ----------------------------------------------
+// Shell of a frequency of the blocked half spectrum: the rounded radius of the signed
+// frequency (q1, q2 in [0, L), q3 in [0, L/2]).  Encoder and product evaluate the same
+// integer expression, so both see the same shell.
+__device__ __forceinline__ int khat_shell(int q1, int q2, int q3, int L) {
+    const int a = q1 < L / 2 ? q1 : q1 - L, b = q2 < L / 2 ? q2 : q2 - L;
+    return (int)floorf(sqrtf((float)(a * a + b * b + q3 * q3)) + 0.5f);
+}
+
+constexpr int KSH_MAX = 448;  // shells at N <= 256: round(sqrt(3) N) + 1 <= 445
+
+// blocked element i -> (q1, q2, q3); false for the padding columns q3 > N
+__device__ __forceinline__ bool khat_blocked_q(int64_t i, int L, int C, int ng, int& q1, int& q2, int& q3) {
+    const int c = (int)(i % C);
+    q1 = (int)((i / C) % L);
+    const int g = (int)((i / ((int64_t)C * L)) % ng);
+    q2 = (int)(i / ((int64_t)C * L * ng));
+    q3 = g * C + c;
+    return q3 <= L / 2;
+}
+
+// pass 1: per-shell sum and count (block-private in LDS, then added to the global totals)
+__global__ void __launch_bounds__(256) k_khat_shell_sum(const float* __restrict__ kh, int L, int C, int ng,
+                                                        double* __restrict__ gsum, unsigned* __restrict__ gcnt) {
+    __shared__ double ssum[KSH_MAX];
+    __shared__ unsigned scnt[KSH_MAX];
+    for (int i = threadIdx.x; i < KSH_MAX; i += 256) { ssum[i] = 0.0; scnt[i] = 0u; }
+    __syncthreads();
+    const int64_t n = (int64_t)L * ng * L * C;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int q1, q2, q3;
+        if (!khat_blocked_q(i, L, C, ng, q1, q2, q3)) continue;
+        const int sh = khat_shell(q1, q2, q3, L);
+        atomicAdd(&ssum[sh], (double)kh[i]);
+        atomicAdd(&scnt[sh], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KSH_MAX; i += 256)
+        if (scnt[i]) {
+            atomicAdd(&gsum[i], ssum[i]);
+            atomicAdd(&gcnt[i], scnt[i]);
+        }
+}
+
+// pass 2: per-shell largest deviation from the shell mean (non-negative floats compare as
+// their bit patterns)
+__global__ void __launch_bounds__(256) k_khat_shell_dev(const float* __restrict__ kh, int L, int C, int ng,
+                                                        const double* __restrict__ gsum,
+                                                        const unsigned* __restrict__ gcnt,
+                                                        unsigned* __restrict__ gdev) {
+    __shared__ float smu[KSH_MAX];
+    __shared__ unsigned sdev[KSH_MAX];
+    for (int i = threadIdx.x; i < KSH_MAX; i += 256) {
+        smu[i] = gcnt[i] ? (float)(gsum[i] / gcnt[i]) : 0.f;
+        sdev[i] = 0u;
+    }
+    __syncthreads();
+    const int64_t n = (int64_t)L * ng * L * C;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int q1, q2, q3;
+        if (!khat_blocked_q(i, L, C, ng, q1, q2, q3)) continue;
+        const int sh = khat_shell(q1, q2, q3, L);
+        atomicMax(&sdev[sh], __float_as_uint(fabsf(kh[i] - smu[sh])));
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KSH_MAX; i += 256)
+        if (sdev[i]) atomicMax(&gdev[i], sdev[i]);
+}
+
+// pass 3: the per-shell (offset, scale) pairs
+__global__ void k_khat_shell_tab(const double* __restrict__ gsum, const unsigned* __restrict__ gcnt,
+                                 const unsigned* __restrict__ gdev, float2* __restrict__ tab) {
+    for (int i = threadIdx.x; i < KSH_MAX; i += blockDim.x) {
+        const float dev = __uint_as_float(gdev[i]);
+        tab[i] = make_float2(gcnt[i] ? (float)(gsum[i] / gcnt[i]) : 0.f, dev > 0.f ? dev : 1.f);
+    }
+}
+
+// pass 4: BF16 codes of (K^ - offset) / scale, rounded to nearest even; padding columns 0
+__global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__ kh, int L, int C, int ng,
+                                                       const float2* __restrict__ tab, uint16_t* __restrict__ k16) {
+    const int64_t n = (int64_t)L * ng * L * C;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int q1, q2, q3;
+        uint16_t code = 0;
+        if (khat_blocked_q(i, L, C, ng, q1, q2, q3)) {
+            const float2 ms = tab[khat_shell(q1, q2, q3, L)];
+            const uint32_t u = __float_as_uint((kh[i] - ms.x) / ms.y);
+            code = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+        }
+        k16[i] = code;
+    }
+}
+
 // Middle pass of the product: along axis 1, zero-pad the first n_in entries, forward
 // transform, multiply by the real spectrum (blocked layout [outer][group][element][C]),
 // inverse transform, keep the first n_in.
-template <int L, class S, bool HALF>
+// K16: the spectrum is the 16-bit form of the option khat_bf16 (BF16 codes b, value
+// mu(shell) + sc(shell) b with the per-shell pairs in shtab).
+template <int L, class S, bool HALF, bool K16>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
-k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, S kadd, int ncols, int64_t s_outer,
-      int64_t s_elem, int64_t s_group, int n_in, const typename VecOf<S>::V* __restrict__ tw, const int* active) {
+k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, const float2* __restrict__ shtab,
+      S kadd, int ncols, int64_t s_outer, int64_t s_elem, int64_t s_group, int n_in,
+      const typename VecOf<S>::V* __restrict__ tw, const int* active) {
     // HALF: the pencils are zero-padded (n_in = L / 2) and only their first half is kept, which
     // the compiler folds into the first and last stages
     using V = typename VecOf<S>::V;
@@ -298,7 +395,7 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, S kad
     const int col = g * C + c;
     const bool valid = col < ncols;
     V* d0 = data + o * s_outer + (int64_t)g * s_group + c;
-    const S* k0 = spec + ((int64_t)o * ng + g) * L * C + c;
+    const int64_t kofs = ((int64_t)o * ng + g) * L * C + c;
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -308,8 +405,21 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const S* __restrict__ spec, S kad
     }
     // the spectrum values are loaded before the forward transform, which hides their latency
     S kv[8];
+    if constexpr (!K16) {
+        const S* k0 = reinterpret_cast<const S*>(specv) + kofs;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) kv[t] = k0[(j + t * T) * C];
+        for (int t = 0; t < 8; ++t) kv[t] = k0[(j + t * T) * C];
+    } else {
+        const uint16_t* k0 = reinterpret_cast<const uint16_t*>(specv) + kofs;
+        uint16_t raw[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) raw[t] = k0[(j + t * T) * C];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float2 ms = shtab[valid ? khat_shell(j + t * T, o, col, L) : 0];
+            kv[t] = (S)(ms.x + ms.y * __uint_as_float((uint32_t)raw[t] << 16));
+        }
+    }
     if (TWL) __syncthreads();  // the twiddle table is in place
     fft_reg<L, C, false>(v, lds, twp, (S)-1);
 #pragma unroll
@@ -394,19 +504,32 @@ hipError_t launch_cols(hipStream_t st, const typename VecOf<S>::V* src, void* ds
     return hipGetLastError();
 }
 
+// spec16 / shtab: the 16-bit spectrum of the option khat_bf16 (FP32 only), used instead of spec
 template <int L, class S = float>
 hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec, int nouter, int ncols,
                       int64_t s_outer, int64_t s_elem, int n_in, const typename VecOf<S>::V* tw,
-                      const int* active = nullptr, int64_t s_group = -1, S kadd = 0) {
+                      const int* active = nullptr, int64_t s_group = -1, S kadd = 0,
+                      const uint16_t* spec16 = nullptr, const float2* shtab = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     const int blocks = nouter * ceil_div(ncols, Cfg::C);
     if (s_group < 0) s_group = Cfg::C;
+    if constexpr (sizeof(S) == 4) {
+        if (spec16) {
+            if (2 * n_in == L)
+                hipLaunchKernelGGL((k_mid<L, S, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
+                                   (const void*)spec16, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+            else
+                hipLaunchKernelGGL((k_mid<L, S, false, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
+                                   (const void*)spec16, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+            return hipGetLastError();
+        }
+    }
     if (2 * n_in == L)
-        hipLaunchKernelGGL((k_mid<L, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, kadd, ncols,
-                           s_outer, s_elem, s_group, n_in, tw, active);
+        hipLaunchKernelGGL((k_mid<L, S, true, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
+                           (const void*)spec, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
     else
-        hipLaunchKernelGGL((k_mid<L, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, spec, kadd, ncols,
-                           s_outer, s_elem, s_group, n_in, tw, active);
+        hipLaunchKernelGGL((k_mid<L, S, false, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
+                           (const void*)spec, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
     return hipGetLastError();
 }
 
@@ -443,7 +566,8 @@ hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, fl
     // multiplies by K^ + lam / L^3 instead: with the unnormalised inverse that adds exactly
     // lam x to the cropped output, so that pass E need not read x
     const float kadd = cg ? 0.f : lam / ((float)L * L * L);
-    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd)));
+    RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd,
+                          p->khat_bf16 ? p->khat16 : nullptr, p->shtab)));
     if (ev) RET_IF(hipEventRecord(ev[3], st));
     // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
@@ -656,8 +780,30 @@ hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam) 
     return hipErrorInvalidValue;
 }
 
+namespace {
+template <int L>
+hipError_t khat_f32_all(firm_plan p, float2* w1) {
+    RET_IF(khat_f32<L>(p, w1));
+    if (!p->khat_bf16) return hipSuccess;
+    // 16-bit copy with per-shell offset and scale; the statistics live in w1 (free again)
+    constexpr int C = FftCfg<L, float2>::C;
+    const int N = L / 2, ng = (N + 1 + C - 1) / C;
+    double* gsum = reinterpret_cast<double*>(w1);
+    unsigned* gcnt = reinterpret_cast<unsigned*>(gsum + KSH_MAX);
+    unsigned* gdev = gcnt + KSH_MAX;
+    RET_IF(fill_zero(gsum, KSH_MAX * (sizeof(double) + 2 * sizeof(unsigned)), p->stream));
+    const int64_t n = (int64_t)L * ng * L * C;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_khat_shell_sum, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng, gsum, gcnt);
+    hipLaunchKernelGGL(k_khat_shell_dev, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng, gsum, gcnt, gdev);
+    hipLaunchKernelGGL(k_khat_shell_tab, dim3(1), dim3(256), 0, p->stream, gsum, gcnt, gdev, p->shtab);
+    hipLaunchKernelGGL(k_khat_encode16, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng, p->shtab, p->khat16);
+    return hipGetLastError();
+}
+}  // namespace
+
 hipError_t fft_khat_from_kerc(firm_plan p, float2* w1) {
-    DISPATCH_L(2 * p->N, khat_f32, p, w1);
+    DISPATCH_L(2 * p->N, khat_f32_all, p, w1);
     return hipErrorInvalidValue;
 }
 

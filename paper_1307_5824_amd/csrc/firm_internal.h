@@ -43,6 +43,9 @@ struct firm_plan_s {
     bool have_kernel = false;
     float* kerc = nullptr;     // (2N)^3 Ker in circulant order c[p1][p2][p3]
     float* khat = nullptr;     // real spectrum, q3 in [0, N], blocked as [q2][q3 group][q1][C]
+    int khat_bf16 = 0;         // option: the FP32 product reads the 16-bit copy below
+    uint16_t* khat16 = nullptr;  // BF16 codes of (K^ - offset) / scale per shell, blocked like khat
+    float2* shtab = nullptr;     // per-shell (offset, scale), KSH_MAX entries
 
     // apply workspaces
     float2* T1 = nullptr;      // [N][N][QP]
