@@ -194,7 +194,10 @@ def main():
     ph = np.mean(np.array(phases), axis=0)
     applies_per_s = args.apply_reps / (ph[5] / 1e3)
 
-    # the analytic ablation: PCG with the inverse of T. Chan's circulant spectrum
+    # the analytic ablation: PCG with the inverse of T. Chan's circulant spectrum (one untimed call
+    # first, as the steps' warmup does for the learned path)
+    plan.chan_spectrum(wl.lam)
+    torch.cuda.synchronize()
     e = [ev() for _ in range(3)]
     e[0].record()
     d_chan = 1.0 / plan.chan_spectrum(wl.lam)
@@ -236,26 +239,29 @@ def main():
 
     # the 16-bit spectrum (option khat_bf16; reduced precision, so not `value`): products/s, the
     # product's error against the FP32 spectrum's, and the refined solve to the same tolerance
-    p16 = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
-                    precision=args.precision, lambda_relative=1, khat_bf16=1)
-    p16.kernel_set(plan.kernel_get())
-    y16 = p16.apply_AtA(x_probe, wl.lam)
+    k16 = {}
     y32 = plan.apply_AtA(x_probe, wl.lam)
-    err16 = (torch.linalg.norm((y16 - y32).double()) / torch.linalg.norm(y32.double())).item()
-    e = [ev() for _ in range(4)]
-    e[0].record()
-    for _ in range(args.apply_reps):
-        p16.apply_AtA(x_probe, wl.lam, y16)
-    e[1].record()
-    _, rep16 = p16.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter)
-    e[2].record()
-    torch.cuda.synchronize()
-    k16 = {"applies_per_s": round(args.apply_reps / (e[0].elapsed_time(e[1]) / 1e3), 2),
-           "product_rel_err_vs_fp32_spectrum": float(f"{err16:.3g}"),
-           "cg_time_to_tol_s": round(e[1].elapsed_time(e[2]) / 1e3, 4), "cg_iters": rep16["iters"],
-           "cg_true_rel_res": rep16["true_rel_res"]}
-    p16.close()
-    del y16, y32
+    for mode, name in ((1, "shell_offset_scale"), (2, "plain")):
+        p16 = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
+                        precision=args.precision, lambda_relative=1, khat_bf16=mode)
+        p16.kernel_set(plan.kernel_get())
+        y16 = p16.apply_AtA(x_probe, wl.lam)
+        err16 = (torch.linalg.norm((y16 - y32).double()) / torch.linalg.norm(y32.double())).item()
+        e = [ev() for _ in range(3)]
+        e[0].record()
+        for _ in range(args.apply_reps):
+            p16.apply_AtA(x_probe, wl.lam, y16)
+        e[1].record()
+        _, rep16 = p16.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter)
+        e[2].record()
+        torch.cuda.synchronize()
+        k16[name] = {"applies_per_s": round(args.apply_reps / (e[0].elapsed_time(e[1]) / 1e3), 2),
+                     "product_rel_err_vs_fp32_spectrum": float(f"{err16:.3g}"),
+                     "cg_time_to_tol_s": round(e[1].elapsed_time(e[2]) / 1e3, 4), "cg_iters": rep16["iters"],
+                     "cg_true_rel_res": rep16["true_rel_res"]}
+        p16.close()
+        del y16
+    del y32
     print(f"16-bit spectrum: {k16}", file=sys.stderr, flush=True)
 
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
@@ -294,6 +300,7 @@ def main():
             "learned_pcg": round((ph[3] + ph[4]) / 1e3, 4),
             "learned_inference": round(ph[3] / 1e3, 4),
             "chan_pcg": round(sum(chan_ms) / 1e3, 4),
+            "chan_spectrum": round(chan_ms[0] / 1e3, 4),
             "speedup_learned_vs_cg": round(ph[2] / (ph[3] + ph[4]), 3),
             "iters": {"cg": int(np.mean([r[0]["iters"] for r in reps])),
                       "learned_pcg": int(np.mean([r[1]["iters"] for r in reps])), "chan_pcg": rep_c["iters"]},

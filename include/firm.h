@@ -71,11 +71,11 @@ typedef struct {
                              FP32 (P)CG corrections); 2 = FP64 CG (no preconditioner) */
     int lambda_relative;  /* 0: lambda as given; 1: the lambda of every call is multiplied by
                              Ker(0) = sum_m sum_k h_m^2, the diagonal of A*A */
-    int khat_bf16;        /* 1: the FP32 product (and FP32 (P)CG) reads K^ stored in 16 bits: BF16
-                             codes of (K^ - o_s) / s_s with a per-shell offset o_s (shell mean)
-                             and scale s_s (largest deviation), shell = rounded |q|; half the
-                             spectrum bytes, product error <= 1e-3.  The FP64 product keeps the
-                             FP32 kernel.  0 = FP32 K^ */
+    int khat_bf16;        /* 16-bit kernel spectrum for the FP32 product (and FP32 (P)CG), half
+                             the spectrum bytes, product error <= 1e-3; the FP64 product keeps
+                             the FP32 kernel.  0 = FP32 K^; 1 = BF16 codes of (K^ - o_s) / s_s
+                             with a per-shell offset o_s (shell mean) and scale s_s (largest
+                             deviation), shell = rounded |q|; 2 = BF16 codes of K^ */
     double inner_tol;     /* precision 1: relative tolerance of each FP32 correction; 0 = 1e-3 */
     void* stream;         /* hipStream_t for all work; NULL = null stream */
 } firm_options;

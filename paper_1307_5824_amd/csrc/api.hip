@@ -196,7 +196,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     if (opt) o = *opt;
     if (o.kb_width == 0) o.kb_width = 7;
     if (o.kb_width < 4 || o.kb_width > 8) return firm_fail(nullptr, FIRM_ERR_ARG, "kb_width must be in [4, 8]");
-    if (o.khat_bf16 != 0 && o.khat_bf16 != 1) return firm_fail(nullptr, FIRM_ERR_ARG, "khat_bf16 must be 0 or 1");
+    if (o.khat_bf16 < 0 || o.khat_bf16 > 2) return firm_fail(nullptr, FIRM_ERR_ARG, "khat_bf16 must be 0, 1 or 2");
     if (o.check_every < 0) return firm_fail(nullptr, FIRM_ERR_ARG, "check_every must be >= 0");
     if (o.precision < 0 || o.precision > 2) return firm_fail(nullptr, FIRM_ERR_ARG, "precision must be 0, 1 or 2");
     if (o.lambda_relative != 0 && o.lambda_relative != 1)

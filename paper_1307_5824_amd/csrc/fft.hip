@@ -347,7 +347,8 @@ __global__ void k_khat_shell_tab(const double* __restrict__ gsum, const unsigned
     }
 }
 
-// pass 4: BF16 codes of (K^ - offset) / scale, rounded to nearest even; padding columns 0
+// pass 4: BF16 codes of (K^ - offset) / scale (or of K^ itself, tab null), rounded to nearest
+// even; padding columns 0
 __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__ kh, int L, int C, int ng,
                                                        const float2* __restrict__ tab, uint16_t* __restrict__ k16) {
     const int64_t n = (int64_t)L * ng * L * C;
@@ -355,7 +356,7 @@ __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__
         int q1, q2, q3;
         uint16_t code = 0;
         if (khat_blocked_q(i, L, C, ng, q1, q2, q3)) {
-            const float2 ms = tab[khat_shell(q1, q2, q3, L)];
+            const float2 ms = tab ? tab[khat_shell(q1, q2, q3, L)] : make_float2(0.f, 1.f);
             const uint32_t u = __float_as_uint((kh[i] - ms.x) / ms.y);
             code = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
         }
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__
 // transform, multiply by the real spectrum (blocked layout [outer][group][element][C]),
 // inverse transform, keep the first n_in.
 // K16: the spectrum is the 16-bit form of the option khat_bf16 (BF16 codes b, value
-// mu(shell) + sc(shell) b with the per-shell pairs in shtab).
+// mu(shell) + sc(shell) b with the per-shell pairs in shtab, or b itself when shtab is null).
 template <int L, class S, bool HALF, bool K16>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, const float2* __restrict__ shtab,
@@ -414,10 +415,15 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
         uint16_t raw[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) raw[t] = k0[(j + t * T) * C];
+        if (shtab) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float2 ms = shtab[valid ? khat_shell(j + t * T, o, col, L) : 0];
-            kv[t] = (S)(ms.x + ms.y * __uint_as_float((uint32_t)raw[t] << 16));
+            for (int t = 0; t < 8; ++t) {
+                const float2 ms = shtab[valid ? khat_shell(j + t * T, o, col, L) : 0];
+                kv[t] = (S)(ms.x + ms.y * __uint_as_float((uint32_t)raw[t] << 16));
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) kv[t] = (S)__uint_as_float((uint32_t)raw[t] << 16);
         }
     }
     if (TWL) __syncthreads();  // the twiddle table is in place
@@ -567,7 +573,7 @@ hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, fl
     // lam x to the cropped output, so that pass E need not read x
     const float kadd = cg ? 0.f : lam / ((float)L * L * L);
     RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd,
-                          p->khat_bf16 ? p->khat16 : nullptr, p->shtab)));
+                          p->khat_bf16 ? p->khat16 : nullptr, p->khat_bf16 == 1 ? p->shtab : nullptr)));
     if (ev) RET_IF(hipEventRecord(ev[3], st));
     // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
@@ -785,15 +791,20 @@ template <int L>
 hipError_t khat_f32_all(firm_plan p, float2* w1) {
     RET_IF(khat_f32<L>(p, w1));
     if (!p->khat_bf16) return hipSuccess;
-    // 16-bit copy with per-shell offset and scale; the statistics live in w1 (free again)
     constexpr int C = FftCfg<L, float2>::C;
     const int N = L / 2, ng = (N + 1 + C - 1) / C;
+    const int64_t n = (int64_t)L * ng * L * C;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+    if (p->khat_bf16 == 2) {  // plain BF16 codes
+        hipLaunchKernelGGL(k_khat_encode16, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng,
+                           (const float2*)nullptr, p->khat16);
+        return hipGetLastError();
+    }
+    // 16-bit copy with per-shell offset and scale; the statistics live in w1 (free again)
     double* gsum = reinterpret_cast<double*>(w1);
     unsigned* gcnt = reinterpret_cast<unsigned*>(gsum + KSH_MAX);
     unsigned* gdev = gcnt + KSH_MAX;
     RET_IF(fill_zero(gsum, KSH_MAX * (sizeof(double) + 2 * sizeof(unsigned)), p->stream));
-    const int64_t n = (int64_t)L * ng * L * C;
-    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_khat_shell_sum, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng, gsum, gcnt);
     hipLaunchKernelGGL(k_khat_shell_dev, dim3(blocks), dim3(256), 0, p->stream, p->khat, L, C, ng, gsum, gcnt, gdev);
     hipLaunchKernelGGL(k_khat_shell_tab, dim3(1), dim3(256), 0, p->stream, gsum, gcnt, gdev, p->shtab);

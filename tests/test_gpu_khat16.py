@@ -44,15 +44,15 @@ def _physical(N, M, seed):
     return R, grp, table, Ker
 
 
-@pytest.mark.parametrize("N,M", [(16, 120), (32, 60)])
-def test_bf16_spectrum_product_within_1e3(firm, N, M):
-    print(f"khat16 apply N={N} M={M}", flush=True)
+@pytest.mark.parametrize("N,M,mode", [(16, 120, 1), (32, 60, 1), (32, 60, 2)])
+def test_bf16_spectrum_product_within_1e3(firm, N, M, mode):
+    print(f"khat16 apply N={N} M={M} mode={mode}", flush=True)
     R, grp, table, Ker = _physical(N, M, 500 + N)
     lam = 1e-2 * Ker[N - 1, N - 1, N - 1]
     x = np.random.default_rng(N).standard_normal((N, N, N))
     ref = ofirm.toeplitz_apply_fft(Ker, x).real + lam * x
     K = dev(ker_to_centred(Ker, N))
-    p16 = firm.Plan(N, R, ctf_group=grp, ctf_table=table, khat_bf16=1)
+    p16 = firm.Plan(N, R, ctf_group=grp, ctf_table=table, khat_bf16=mode)
     p32 = firm.Plan(N, R, ctf_group=grp, ctf_table=table)
     p16.kernel_set(K)
     p32.kernel_set(K)
