@@ -65,7 +65,8 @@ __device__ __forceinline__ int out_index(int e, int L, int n_out, bool& zero) {
 
 __device__ __forceinline__ bool cg_inactive(const int* active) { return active && *active == 0; }
 
-// Non-temporal (streaming) loads and stores of 4- and 8-byte values; wider ones are plain.  Every
+// Non-temporal (streaming) loads of 2-, 4- and 8-byte values and stores of 4- and 8-byte values;
+// wider ones are plain.  Every
 // pass of the product reads its input and writes its output once, so none of it is worth
 // caching: at N = 256 the five passes take 397 instead of 433 us per product with these.
 template <class T>
@@ -75,6 +76,9 @@ __device__ __forceinline__ T ld_nt(const T* p) {
         return *reinterpret_cast<const T*>(&b);
     } else if constexpr (sizeof(T) == 4) {
         const int b = __builtin_nontemporal_load(reinterpret_cast<const int*>(p));
+        return *reinterpret_cast<const T*>(&b);
+    } else if constexpr (sizeof(T) == 2) {
+        const short b = __builtin_nontemporal_load(reinterpret_cast<const short*>(p));
         return *reinterpret_cast<const T*>(&b);
     } else {
         return *p;
@@ -439,7 +443,7 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
         const uint16_t* k0 = reinterpret_cast<const uint16_t*>(specv) + kofs;
         uint16_t raw[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) raw[t] = k0[(j + t * T) * C];
+        for (int t = 0; t < 8; ++t) raw[t] = ld_nt(k0 + (j + t * T) * C);
         if (shtab) {
 #pragma unroll
             for (int t = 0; t < 8; ++t) {
