@@ -102,9 +102,9 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     constexpr int NK = PT - W + 1;                     // possible first rows of a window
     __shared__ int pt_key[SP_PB], pt_slot[SP_PB], bstart[NK + 1];
     __shared__ int img_m[SP_THREADS];
-    __shared__ int img_k1[SP_THREADS], img_k2[SP_THREADS];
+    __shared__ int img_k1[SP_THREADS];
     __shared__ int queue[SP_QCAP];
-    __shared__ int nimg, qn, any;
+    __shared__ int nimg, qn, qfail, any;
 
     const int tid = threadIdx.x;
     const int4 wk = a.work[blockIdx.x];
@@ -120,8 +120,187 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     const double Rt = T * 0.8660254037844386 + 1e-3;
     const double rk = Rt / a.s;
     const int S = (int)floor(2.0 * rk) + 3;
-    const int SS = S * S;
     const int N2 = N * N;
+
+    // points of the queue [0, nq) staged and accumulated in batches of SP_PB
+    auto process = [&](int nq) {
+        if (tid == 0 && nq > 0) any = 1;
+        const int wv = tid >> 6, lane = tid & 63;
+        const int r0 = wv * H;                                   // this wave's rows [r0, r0 + H)
+        for (int pb = 0; pb < nq; pb += SP_PB) {
+            const int nb = min(SP_PB, nq - pb);
+            // stage the batch: each of its threads computes one point's tile-relative window
+            // start and weights; wave 0 ranks the points by their first row (counting sort
+            // with ballots); each point is then written to its rank, so that the points
+            // meeting a wavefront's slab form one contiguous range
+            float ph[3][W];
+            int lo[3] = {0, 0, 0};
+            float scale = 1.f;
+            float2 pval = make_float2(0.f, 0.f);
+            if (tid < nb) {
+                const int e = queue[pb + tid];
+                const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
+                const int m = img_m[sl];
+                const double* c = a.c12 + 6 * (int64_t)m;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
+                    // stencil stays inside the padded tile for every width
+                    const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
+                    const double left = tau - 0.5 * W;
+                    const int b0 = (int)floor(left) + 1;
+                    const float f = (float)((double)b0 - left);  // in (0, 1]
+                    kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
+                    // in [0, PT - W] for every point of the tile (clamped position); the bound
+                    // also keeps the LDS accesses inside the tile should rounding ever differ
+                    lo[d] = min(max(b0 - (tt[d] * T - PADLO), 0), PT - W);
+                }
+                const int g = a.group ? a.group[m] : 0;
+                const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
+                if constexpr (!CPLX) {
+                    scale = 2.f * h * h;
+                } else {
+                    // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
+                    const int idx = a.rowstart[k1 + N / 2] + k2;
+                    const float2 bp = a.b[(int64_t)m * a.P + idx];
+                    const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
+                    const float sr = bp.x + bm.x, si = bp.y - bm.y;
+                    float cs = 1.f, sn = 0.f;
+                    if (a.shifts) {
+                        const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
+                                                              k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+                        cs = (float)cos(th);
+                        sn = (float)sin(th);
+                    }
+                    pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
+                }
+                pt_key[tid] = lo[0];
+            }
+            __syncthreads();
+            if (tid < 64) {
+                constexpr int NCH = (SP_PB + 63) / 64;
+                const int ln = tid;
+                const uint64_t lt = (1ull << ln) - 1ull;
+                int key[NCH];
+#pragma unroll
+                for (int ch = 0; ch < NCH; ++ch) key[ch] = ch * 64 + ln < nb ? pt_key[ch * 64 + ln] : -1;
+                int run = 0;
+                for (int v = 0; v < NK; ++v) {
+                    if (ln == 0) bstart[v] = run;
+#pragma unroll
+                    for (int ch = 0; ch < NCH; ++ch) {
+                        const uint64_t msk = __ballot(key[ch] == v);
+                        if (key[ch] == v) pt_slot[ch * 64 + ln] = run + __popcll(msk & lt);
+                        run += __popcll(msk);
+                    }
+                }
+                if (ln == 0) bstart[NK] = run;
+            }
+            __syncthreads();
+            if (tid < nb) {
+                const int d = pt_slot[tid];
+                float* q = pt_w + d * PSTR;
+#pragma unroll
+                for (int r = 0; r < SP_WAVES * H; ++r) {  // row r of the padded tile
+                    const int j1 = r - lo[0];
+                    float w = 0.f;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) w = (j1 == j) ? ph[0][j] : w;
+                    q[r] = scale * w;
+                }
+#pragma unroll
+                for (int j = 0; j < W; ++j) {
+                    q[SP_WAVES * H + j] = ph[1][j];
+                    q[SP_WAVES * H + W + j] = ph[2][j];
+                }
+                pt_lo[d] = lo[0] | (lo[1] << 8) | (lo[2] << 16);
+                if constexpr (CPLX) pt_v[d] = pval;
+            }
+            __syncthreads();
+            // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1], taken two at a time;
+            // when the two footprints are disjoint both points' rows are read before either is
+            // written back (two independent read-modify-write chains in flight)
+            const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
+            const int pbeg = vlo <= vhi ? bstart[vlo] : 0, pend = vlo <= vhi ? bstart[vhi + 1] : 0;
+            constexpr int A2 = SP_WAVES * H, A3 = SP_WAVES * H + W;
+            const int jl = lane < W * W ? lane : 0;
+            const int j2 = jl / W, j3 = jl - (jl / W) * W;  // footprint cell of this lane
+            const bool act = lane < W * W;
+            struct Pt {
+                int cb, l1, l2;
+                float rw[H];
+                float w23;
+                float2 v;
+            };
+            auto load = [&](int pi, Pt& q) {
+                const float* w = pt_w + pi * PSTR;
+                const int lw = pt_lo[pi];
+                q.l1 = (lw >> 8) & 255;
+                q.l2 = lw >> 16;
+                q.cb = r0 * PP + (q.l1 + j2) * RP + q.l2 + j3;
+#pragma unroll
+                for (int k = 0; k < H; ++k) q.rw[k] = w[r0 + k];
+                q.w23 = w[A2 + j2] * w[A3 + j3];
+                q.v = CPLX ? pt_v[pi] : make_float2(0.f, 0.f);
+            };
+            // rows of the slab: read, then add weight * value (weight 0 outside the window)
+            auto rd = [&](const Pt& q, float (&vr)[H], float (&vi)[H]) {
+#pragma unroll
+                for (int k = 0; k < H; ++k) {
+                    vr[k] = tile[q.cb + k * PP];
+                    if (CPLX) vi[k] = tile[NR * PP + q.cb + k * PP];
+                }
+            };
+            auto wr = [&](const Pt& q, const float (&vr)[H], const float (&vi)[H]) {
+                if constexpr (!CPLX) {
+#pragma unroll
+                    for (int k = 0; k < H; ++k) tile[q.cb + k * PP] = fmaf(q.rw[k], q.w23, vr[k]);
+                } else {
+                    const float sr = q.w23 * q.v.x, si = q.w23 * q.v.y;
+#pragma unroll
+                    for (int k = 0; k < H; ++k) {
+                        tile[q.cb + k * PP] = fmaf(q.rw[k], sr, vr[k]);
+                        tile[NR * PP + q.cb + k * PP] = fmaf(q.rw[k], si, vi[k]);
+                    }
+                }
+            };
+            for (int pi = pbeg; pi < pend; pi += 2) {
+                const bool two = pi + 1 < pend;
+                Pt a, b;
+                load(pi, a);
+                load(two ? pi + 1 : pi, b);
+                const bool apart = two && (abs(a.l1 - b.l1) >= W || abs(a.l2 - b.l2) >= W);
+                float ar[H], ai[H], br[H], bi[H];
+                if (act) {
+                    if (apart) {
+                        rd(a, ar, ai);
+                        rd(b, br, bi);
+                        wr(a, ar, ai);
+                        wr(b, br, bi);
+                    } else {
+                        rd(a, ar, ai);
+                        wr(a, ar, ai);
+                        if (two) {
+                            rd(b, br, bi);
+                            wr(b, br, bi);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
+    // rounding of the row intervals; the edge tiles also own the clamped cells beyond the grid
+    constexpr double MARGIN = 1e-3, FAR = 1e30;
+    double blo[3], bhi[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
+        bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
+    }
+    if (tid == 0) { qn = 0; qfail = SP_QCAP; }
 
     for (int mb = wk.y; mb < wk.z; mb += SP_THREADS) {
         __syncthreads();
@@ -134,206 +313,86 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
             if (dist <= Rt + 1e-3) {
                 const double* c = a.c12 + 6 * (int64_t)m;
                 const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
-                const double u2 = (tc[0] * c[3] + tc[1] * c[4] + tc[2] * c[5]) / a.s;
                 const int sl = atomicAdd(&nimg, 1);
                 img_m[sl] = m;
-                img_k1[sl] = (int)ceil(u1 - rk) - 1;
-                img_k2[sl] = (int)ceil(u2 - rk) - 1;
+                img_k1[sl] = (int)ceil(u1 - rk) - 1;  // first candidate row
             }
         }
         __syncthreads();
-        const int total = nimg * SS;
-        for (int base = 0; base < total; base += SP_QCAP) {
-            if (tid == 0) qn = 0;
-            __syncthreads();
-            const int lim = min(total, base + SP_QCAP);
-            for (int i = base + tid; i < lim; i += SP_THREADS) {
-                const int sl = i / SS, cc = i - sl * SS;
-                const int k1 = img_k1[sl] + cc / S, k2 = img_k2[sl] + cc % S;
-                if (!(k1 > 0 || (k1 == 0 && k2 > 0))) continue;
-                if (4 * (k1 * k1 + k2 * k2) > N2) continue;
-                const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                bool in = true;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
-                    int cell = (int)floor(tau);
-                    cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
-                    in = in && (cell / T == tt[d]);
-                }
-                if (in) {
-                    const int qi = atomicAdd(&qn, 1);
-                    queue[qi] = (sl << 18) | ((k1 + 256) << 9) | (k2 + 256);
-                }
-            }
-            __syncthreads();
-            if (tid == 0 && qn > 0) any = 1;
-            const int wv = tid >> 6, lane = tid & 63;
-            const int r0 = wv * H;                                   // this wave's rows [r0, r0 + H)
-            for (int pb = 0; pb < qn; pb += SP_PB) {
-                const int nb = min(SP_PB, qn - pb);
-                // stage the batch: each of its threads computes one point's tile-relative window
-                // start and weights; wave 0 ranks the points by their first row (counting sort
-                // with ballots); each point is then written to its rank, so that the points
-                // meeting a wavefront's slab form one contiguous range
-                float ph[3][W];
-                int lo[3] = {0, 0, 0};
-                float scale = 1.f;
-                float2 pval = make_float2(0.f, 0.f);
-                if (tid < nb) {
-                    const int e = queue[pb + tid];
-                    const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
-                    const int m = img_m[sl];
-                    const double* c = a.c12 + 6 * (int64_t)m;
+        // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
+        // plus the disk and half-disk bounds), the exact cell test per point (a bit mask), then
+        // the points are queued.  A reservation that does not fit waits for the queue to be
+        // processed; the reservations that fitted form the prefix up to the first that did not.
+        const int units = nimg * S;
+        for (int ub = 0; ub < units; ub += SP_THREADS) {
+            const int u = ub + tid;
+            int sl = 0, k1 = 0, klo = 0;
+            uint32_t mask = 0u;
+            if (u < units) {
+                sl = u / S;
+                k1 = img_k1[sl] + (u - sl * S);
+                if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                    const int kd = (int)sqrt((double)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                    double lo = -kd, hi = kd;
+                    bool ok = true;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
-                        // stencil stays inside the padded tile for every width
-                        const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
-                        const double left = tau - 0.5 * W;
-                        const int b0 = (int)floor(left) + 1;
-                        const float f = (float)((double)b0 - left);  // in (0, 1]
-                        kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
-                        // in [0, PT - W] for every point of the tile (clamped position); the bound
-                        // also keeps the LDS accesses inside the tile should rounding ever differ
-                        lo[d] = min(max(b0 - (tt[d] * T - PADLO), 0), PT - W);
-                    }
-                    const int g = a.group ? a.group[m] : 0;
-                    const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
-                    if constexpr (!CPLX) {
-                        scale = 2.f * h * h;
-                    } else {
-                        // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
-                        const int idx = a.rowstart[k1 + N / 2] + k2;
-                        const float2 bp = a.b[(int64_t)m * a.P + idx];
-                        const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
-                        const float sr = bp.x + bm.x, si = bp.y - bm.y;
-                        float cs = 1.f, sn = 0.f;
-                        if (a.shifts) {
-                            const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
-                                                                  k2 * a.shifts[2 * (int64_t)m + 1]) / N;
-                            cs = (float)cos(th);
-                            sn = (float)sin(th);
-                        }
-                        pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
-                    }
-                    pt_key[tid] = lo[0];
-                }
-                __syncthreads();
-                if (tid < 64) {
-                    constexpr int NCH = (SP_PB + 63) / 64;
-                    const int ln = tid;
-                    const uint64_t lt = (1ull << ln) - 1ull;
-                    int key[NCH];
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) key[ch] = ch * 64 + ln < nb ? pt_key[ch * 64 + ln] : -1;
-                    int run = 0;
-                    for (int v = 0; v < NK; ++v) {
-                        if (ln == 0) bstart[v] = run;
-#pragma unroll
-                        for (int ch = 0; ch < NCH; ++ch) {
-                            const uint64_t msk = __ballot(key[ch] == v);
-                            if (key[ch] == v) pt_slot[ch * 64 + ln] = run + __popcll(msk & lt);
-                            run += __popcll(msk);
-                        }
-                    }
-                    if (ln == 0) bstart[NK] = run;
-                }
-                __syncthreads();
-                if (tid < nb) {
-                    const int d = pt_slot[tid];
-                    float* q = pt_w + d * PSTR;
-#pragma unroll
-                    for (int r = 0; r < SP_WAVES * H; ++r) {  // row r of the padded tile
-                        const int j1 = r - lo[0];
-                        float w = 0.f;
-#pragma unroll
-                        for (int j = 0; j < W; ++j) w = (j1 == j) ? ph[0][j] : w;
-                        q[r] = scale * w;
-                    }
-#pragma unroll
-                    for (int j = 0; j < W; ++j) {
-                        q[SP_WAVES * H + j] = ph[1][j];
-                        q[SP_WAVES * H + W + j] = ph[2][j];
-                    }
-                    pt_lo[d] = lo[0] | (lo[1] << 8) | (lo[2] << 16);
-                    if constexpr (CPLX) pt_v[d] = pval;
-                }
-                __syncthreads();
-                // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1], taken two at a time;
-                // when the two footprints are disjoint both points' rows are read before either is
-                // written back (two independent read-modify-write chains in flight)
-                const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
-                const int pbeg = vlo <= vhi ? bstart[vlo] : 0, pend = vlo <= vhi ? bstart[vhi + 1] : 0;
-                constexpr int A2 = SP_WAVES * H, A3 = SP_WAVES * H + W;
-                const int jl = lane < W * W ? lane : 0;
-                const int j2 = jl / W, j3 = jl - (jl / W) * W;  // footprint cell of this lane
-                const bool act = lane < W * W;
-                struct Pt {
-                    int cb, l1, l2;
-                    float rw[H];
-                    float w23;
-                    float2 v;
-                };
-                auto load = [&](int pi, Pt& q) {
-                    const float* w = pt_w + pi * PSTR;
-                    const int lw = pt_lo[pi];
-                    q.l1 = (lw >> 8) & 255;
-                    q.l2 = lw >> 16;
-                    q.cb = r0 * PP + (q.l1 + j2) * RP + q.l2 + j3;
-#pragma unroll
-                    for (int k = 0; k < H; ++k) q.rw[k] = w[r0 + k];
-                    q.w23 = w[A2 + j2] * w[A3 + j3];
-                    q.v = CPLX ? pt_v[pi] : make_float2(0.f, 0.f);
-                };
-                // rows of the slab: read, then add weight * value (weight 0 outside the window)
-                auto rd = [&](const Pt& q, float (&vr)[H], float (&vi)[H]) {
-#pragma unroll
-                    for (int k = 0; k < H; ++k) {
-                        vr[k] = tile[q.cb + k * PP];
-                        if (CPLX) vi[k] = tile[NR * PP + q.cb + k * PP];
-                    }
-                };
-                auto wr = [&](const Pt& q, const float (&vr)[H], const float (&vi)[H]) {
-                    if constexpr (!CPLX) {
-#pragma unroll
-                        for (int k = 0; k < H; ++k) tile[q.cb + k * PP] = fmaf(q.rw[k], q.w23, vr[k]);
-                    } else {
-                        const float sr = q.w23 * q.v.x, si = q.w23 * q.v.y;
-#pragma unroll
-                        for (int k = 0; k < H; ++k) {
-                            tile[q.cb + k * PP] = fmaf(q.rw[k], sr, vr[k]);
-                            tile[NR * PP + q.cb + k * PP] = fmaf(q.rw[k], si, vi[k]);
-                        }
-                    }
-                };
-                for (int pi = pbeg; pi < pend; pi += 2) {
-                    const bool two = pi + 1 < pend;
-                    Pt a, b;
-                    load(pi, a);
-                    load(two ? pi + 1 : pi, b);
-                    const bool apart = two && (abs(a.l1 - b.l1) >= W || abs(a.l2 - b.l2) >= W);
-                    float ar[H], ai[H], br[H], bi[H];
-                    if (act) {
-                        if (apart) {
-                            rd(a, ar, ai);
-                            rd(b, br, bi);
-                            wr(a, ar, ai);
-                            wr(b, br, bi);
+                        const double al = a.s * k1 * c[d] + halfL, be = a.s * c[3 + d];
+                        if (fabs(be) < 1e-9) {
+                            ok = ok && al >= blo[d] && al <= bhi[d];
                         } else {
-                            rd(a, ar, ai);
-                            wr(a, ar, ai);
-                            if (two) {
-                                rd(b, br, bi);
-                                wr(b, br, bi);
-                            }
+                            const double t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
+                            lo = fmax(lo, fmin(t1, t2));
+                            hi = fmin(hi, fmax(t1, t2));
                         }
                     }
+                    klo = (int)ceil(lo);
+                    if (k1 == 0) klo = max(klo, 1);
+                    // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                    const int cnt = ok && hi >= klo ? min((int)floor(hi) - klo + 1, 32) : 0;
+                    for (int j = 0; j < cnt; ++j) {
+                        const int k2 = klo + j;
+                        bool in = 4 * (k1 * k1 + k2 * k2) <= N2;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
+                            int cell = (int)floor(tau);
+                            cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+                            in = in && (cell / T == tt[d]);
+                        }
+                        if (in) mask |= 1u << j;
+                    }
                 }
+            }
+            const int c = __popc(mask);
+            bool pend = c > 0;
+            while (true) {
+                if (pend) {
+                    const int pos = atomicAdd(&qn, c);
+                    if (pos + c <= SP_QCAP) {
+                        uint32_t mk = mask;
+                        for (int w = pos; mk; ++w) {
+                            const int j = __ffs(mk) - 1;
+                            mk &= mk - 1u;
+                            queue[w] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
+                        }
+                        pend = false;
+                    } else {
+                        atomicMin(&qfail, pos);
+                    }
+                }
+                if (!__syncthreads_or(pend)) break;
+                process(min(qfail, qn));  // the queue is full
+                __syncthreads();
+                if (tid == 0) { qn = 0; qfail = SP_QCAP; }
                 __syncthreads();
             }
-            __syncthreads();
         }
+        // the view slots are refilled next round: process what is queued
+        process(qn);
+        __syncthreads();
+        if (tid == 0) { qn = 0; qfail = SP_QCAP; }
     }
     __syncthreads();
     if (!any) return;
