@@ -236,6 +236,40 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
     }
 }
 
+
+// Pencil of the middle pass over nouter rows of ncols columns, C pencils per block.  When C
+// does not divide ncols, the ncols % C columns of every row's last, partial group are packed C
+// to a block (pencils of consecutive rows), in the first blocks of the grid (started first:
+// their accesses do not coalesce); every later block takes one full group (o, g).  Without
+// this, each row's last block would run both transforms for a few pencils.  (The one-transform
+// column passes keep one block per group: there the uncoalesced tail accesses cost more than
+// the idle pencils.)  Out: the row o, the column group g, the column cc within it, and whether
+// the pencil exists (o is clamped to a valid row when it does not).
+template <int C>
+__device__ __forceinline__ void tail_packed_pencil(int nouter, int ncols, int c, int& o, int& g, int& cc, bool& valid) {
+    const int rtail = ncols % C, ngm = ncols / C;
+    const int ntail = (nouter * rtail + C - 1) / C;
+    if ((int)blockIdx.x >= ntail) {
+        const int b = blockIdx.x - ntail;
+        o = b / ngm;
+        g = b - o * ngm;
+        cc = c;
+        valid = true;
+    } else {
+        const int pi = blockIdx.x * C + c;
+        o = pi / rtail;
+        cc = pi - o * rtail;
+        g = ngm;
+        valid = o < nouter;
+        if (!valid) o = nouter - 1;
+    }
+}
+
+// blocks of the middle pass: full groups plus the packed tail columns
+template <int C>
+inline int tail_packed_blocks(int nouter, int ncols) {
+    return nouter * (ncols / C) + (nouter * (ncols % C) + C - 1) / C;
+}
 // Complex pencils along one axis.  Block -> (outer o, column group); CONTIG means the
 // transformed axis is contiguous (lanes along elements), otherwise lanes run along columns.
 template <int L, bool CONTIG, int MAP, int EPI, class S, int PADK>
@@ -259,9 +293,9 @@ k_cols(const typename VecOf<S>::V* __restrict__ src, void* __restrict__ dstv, in
     if (PADK == 1) n_in = L / 2;
     if (PADK == 2) n_out = L / 2;
     const int ng = (ncols + C - 1) / C;
+    const int c = P::c(), j = P::j();
     const int o = blockIdx.x / ng;
     const int g = blockIdx.x - o * ng;
-    const int c = P::c(), j = P::j();
     const int col = g * C + c;
     const bool valid = col < ncols;
     const V* s0 = src + o * s_outer + (int64_t)g * s_group + (int64_t)c * s_col;
@@ -401,7 +435,7 @@ __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__
 template <int L, class S, bool HALF, bool K16>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, const float2* __restrict__ shtab,
-      S kadd, int ncols, int64_t s_outer, int64_t s_elem, int64_t s_group, int n_in,
+      S kadd, int nouter, int ncols, int64_t s_outer, int64_t s_elem, int64_t s_group, int n_in,
       const typename VecOf<S>::V* __restrict__ tw, const int* active) {
     // HALF: the pencils are zero-padded (n_in = L / 2) and only their first half is kept, which
     // the compiler folds into the first and last stages
@@ -418,14 +452,14 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
         for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
     const V* twp = TWL ? twl : tw;
     const int nin = HALF ? L / 2 : n_in;
-    const int ng = (ncols + C - 1) / C;
-    const int o = blockIdx.x / ng;
-    const int g = blockIdx.x - o * ng;
+    const int ng = (ncols + C - 1) / C;  // column groups of the data and spectrum layouts
     const int c = P::c(), j = P::j();
-    const int col = g * C + c;
-    const bool valid = col < ncols;
-    V* d0 = data + o * s_outer + (int64_t)g * s_group + c;
-    const int64_t kofs = ((int64_t)o * ng + g) * L * C + c;
+    int o, g, cc;
+    bool valid;
+    tail_packed_pencil<C>(nouter, ncols, c, o, g, cc, valid);
+    const int col = g * C + cc;
+    V* d0 = data + o * s_outer + (int64_t)g * s_group + cc;
+    const int64_t kofs = ((int64_t)o * ng + g) * L * C + cc;
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -546,25 +580,28 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
                       const int* active = nullptr, int64_t s_group = -1, S kadd = 0,
                       const uint16_t* spec16 = nullptr, const float2* shtab = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
-    const int blocks = nouter * ceil_div(ncols, Cfg::C);
-    if (s_group < 0) s_group = Cfg::C;
-    if constexpr (sizeof(S) == 4) {
-        if (spec16) {
+    constexpr int C = Cfg::C;
+    if (s_group < 0) s_group = C;
+    const void* sp = spec16 ? (const void*)spec16 : (const void*)spec;
+    const int blocks = tail_packed_blocks<C>(nouter, ncols);
+    bool k16 = false;
+    if constexpr (sizeof(S) == 4) k16 = spec16 != nullptr;
+    if (k16) {
+        if constexpr (sizeof(S) == 4) {
             if (2 * n_in == L)
-                hipLaunchKernelGGL((k_mid<L, S, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
-                                   (const void*)spec16, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+                hipLaunchKernelGGL((k_mid<L, S, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab,
+                                   kadd, nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
             else
-                hipLaunchKernelGGL((k_mid<L, S, false, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
-                                   (const void*)spec16, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
-            return hipGetLastError();
+                hipLaunchKernelGGL((k_mid<L, S, false, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab,
+                                   kadd, nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
         }
+    } else if (2 * n_in == L) {
+        hipLaunchKernelGGL((k_mid<L, S, true, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd,
+                           nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+    } else {
+        hipLaunchKernelGGL((k_mid<L, S, false, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd,
+                           nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
     }
-    if (2 * n_in == L)
-        hipLaunchKernelGGL((k_mid<L, S, true, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
-                           (const void*)spec, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
-    else
-        hipLaunchKernelGGL((k_mid<L, S, false, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data,
-                           (const void*)spec, shtab, kadd, ncols, s_outer, s_elem, s_group, n_in, tw, active);
     return hipGetLastError();
 }
 
