@@ -66,17 +66,46 @@ __device__ __forceinline__ void kb_weights(const float* __restrict__ poly, float
     }
 }
 
-// Smallest LDS row pitch >= PT at which the W x W footprint cells j2 * pitch + j3 of one
-// instruction fall in distinct banks (64 banks of 4 bytes).
-constexpr int row_pitch(int PT, int W) {
-    for (int rp = PT; rp < PT + 32; ++rp) {
-        bool ok = true;
-        for (int a = 0; a < W * W && ok; ++a)
-            for (int b = a + 1; b < W * W && ok; ++b)
-                if (((a / W) * rp + a % W) % 64 == ((b / W) * rp + b % W) % 64) ok = false;
-        if (ok) return rp;
+// LDS bank layout of the footprint accesses.  A wave's LDS access is served as two halves of
+// 32 lanes over 32 banks of 4 bytes, so the W x W footprint cells j2 * pitch + j3 are split by
+// rows between the two halves such that each half's cells fall in distinct banks.
+// rows_disjoint: the cells of the rows in `mask` fall in distinct banks.
+constexpr bool rows_disjoint(int mask, int rp, int W) {
+    bool used[32] = {};
+    for (int r = 0; r < W; ++r) {
+        if (!((mask >> r) & 1)) continue;
+        for (int j = 0; j < W; ++j) {
+            const int b = (r * rp + j) % 32;
+            if (used[b]) return false;
+            used[b] = true;
+        }
     }
+    return true;
+}
+
+// rows of the first half (a bit mask) for row pitch rp, or -1 if no split is conflict-free
+constexpr int half_split(int rp, int W) {
+    for (int mask = 0; mask < (1 << W); ++mask) {
+        int na = 0;
+        for (int r = 0; r < W; ++r) na += (mask >> r) & 1;
+        if (na * W > 32 || (W - na) * W > 32) continue;
+        if (rows_disjoint(mask, rp, W) && rows_disjoint(((1 << W) - 1) & ~mask, rp, W)) return mask;
+    }
+    return -1;
+}
+
+// smallest LDS row pitch >= PT that admits a conflict-free split
+constexpr int row_pitch(int PT, int W) {
+    for (int rp = PT; rp < PT + 32; ++rp)
+        if (half_split(rp, W) >= 0) return rp;
     return PT;
+}
+
+// Fine-grid position of the disk point (k1, k2) of a view along axis d: the one expression
+// that both the point enumeration (which tile owns the point) and the staging (where its
+// window starts) evaluate, so that the two agree to the last bit.
+__device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, double c3d, double halfL) {
+    return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
 }
 
 template <int T, int W, bool CPLX, int NTH>
@@ -87,36 +116,41 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     constexpr int NCELL = PT * PT * PT;
     constexpr int H = (PT + SP_WAVES - 1) / SP_WAVES;  // rows per wavefront slab
     constexpr int RP = row_pitch(PT, W);               // LDS pitch of a tile row (bank-conflict free)
+    constexpr int SPLIT = half_split(RP, W);           // footprint rows of the first half-wave
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
     constexpr int NR = SP_WAVES * H;                   // planes, padded to whole slabs
     constexpr int NV = CPLX ? 2 : 1;                   // real and imaginary parts in separate tiles
-    // staged point: for each wavefront its H slab-row weights (0 outside the window), then the
-    // window weights of axes 1 and 2; stride in floats
-    constexpr int PSTR = ((SP_WAVES * H + 2 * W) + 3) / 4 * 4;
+    // staged point: the weights of the NR tile rows (0 outside the window), then the window
+    // weights of axes 1 and 2; stride in floats
+    constexpr int PSTR = ((NR + 2 * W) + 3) / 4 * 4;
     static_assert(W <= 8, "window width");
     constexpr int SP_PB = 96;                          // points staged per batch (two tiles per CU)
+    constexpr int NK = PT - W + 1;                     // possible first rows of a window
+    static_assert(NK <= 64, "first-row buckets");
+    static_assert(NR % 4 == 0 && PSTR % 4 == 0, "row weights zeroed as float4");
+    constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
     __shared__ __align__(16) float tile[NV * NR * PP];
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
-    __shared__ int pt_lo[SP_PB];
+    __shared__ int pt_lo[SP_PB];                       // window starts of axes 1, 2 in bytes 1, 2
     __shared__ float2 pt_v[CPLX ? SP_PB : 1];
-    constexpr int NK = PT - W + 1;                     // possible first rows of a window
-    __shared__ int pt_key[SP_PB], pt_slot[SP_PB], bstart[NK + 1];
+    __shared__ int st_kr[SP_PB];                       // batch position -> first row | rank << 8
+    __shared__ int bcnt[NK], bstart[NK];
     __shared__ int img_m[SP_THREADS];
-    __shared__ int img_k1[SP_THREADS];
     __shared__ int queue[SP_QCAP];
     __shared__ int nimg, qn, qfail, any;
 
     const int tid = threadIdx.x;
     const int4 wk = a.work[blockIdx.x];
     const int nt = a.nt;
-    const int tt[3] = {wk.x / (nt * nt), (wk.x / nt) % nt, wk.x % nt};
+    const int tt0 = wk.x / (nt * nt), tt1 = (wk.x / nt) % nt, tt2 = wk.x % nt;
     const int L = a.L, N = a.N;
     const double halfL = 0.5 * L;
 
     for (int i = tid; i < NV * NR * PP; i += SP_THREADS) tile[i] = 0.f;
-    if (tid == 0) any = 0;
+    for (int i = tid; i < NK; i += SP_THREADS) bcnt[i] = 0;
+    if (tid == 0) { any = 0; nimg = 0; qn = 0; qfail = SP_QCAP; }
 
-    const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
+    const double tc0 = tt0 * T + 0.5 * T - halfL, tc1 = tt1 * T + 0.5 * T - halfL, tc2 = tt2 * T + 0.5 * T - halfL;
     const double Rt = T * 0.8660254037844386 + 1e-3;
     const double rk = Rt / a.s;
     const int S = (int)floor(2.0 * rk) + 3;
@@ -125,107 +159,139 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     // points of the queue [0, nq) staged and accumulated in batches of SP_PB
     auto process = [&](int nq) {
         if (tid == 0 && nq > 0) any = 1;
+        // tile coordinates as values: a select between the captured references would be a
+        // select between addresses, which puts them in scratch memory
+        const int tv0 = tt0, tv1 = tt1, tv2 = tt2;
         const int wv = tid >> 6, lane = tid & 63;
         const int r0 = wv * H;                                   // this wave's rows [r0, r0 + H)
         for (int pb = 0; pb < nq; pb += SP_PB) {
             const int nb = min(SP_PB, nq - pb);
-            // stage the batch: each of its threads computes one point's tile-relative window
-            // start and weights; wave 0 ranks the points by their first row (counting sort
-            // with ballots); each point is then written to its rank, so that the points
-            // meeting a wavefront's slab form one contiguous range
-            float ph[3][W];
-            int lo[3] = {0, 0, 0};
+            // stage the batch in three steps.  (1) One item per (point, axis), spread over all
+            // threads: the window start and weights along that axis; the axis-0 item also
+            // computes the point's value and ranks the point among those with the same first
+            // row (bucket counts in LDS).  (2) One wave turns the counts into bucket starts.
+            // (3) Every item writes its weights to the point's slot, bucket start + rank, so
+            // that the points meeting a wavefront's slab form one contiguous range.
+            float ph[NIT][W];
+            int lod[NIT], pp[NIT], dd[NIT];
             float scale = 1.f;
             float2 pval = make_float2(0.f, 0.f);
-            if (tid < nb) {
-                const int e = queue[pb + tid];
-                const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
-                const int m = img_m[sl];
-                const double* c = a.c12 + 6 * (int64_t)m;
 #pragma unroll
-                for (int d = 0; d < 3; ++d) {
+            for (int it = 0; it < NIT; ++it) {
+                const int i = tid + it * SP_THREADS;
+                dd[it] = -1;
+                pp[it] = 0;
+                lod[it] = 0;
+                if (i < 3 * nb) {
+                    const int d = i / nb, p = i - d * nb;
+                    dd[it] = d;
+                    pp[it] = p;
+                    const int e = queue[pb + p];
+                    const int sl = e >> 18, k1 = ((e >> 9) & 511) - 256, k2 = (e & 511) - 256;
+                    const int m = img_m[sl];
+                    const double* c = a.c12 + 6 * (int64_t)m;
+                    const int ttd = d == 0 ? tv0 : (d == 1 ? tv1 : tv2);
                     // |t_d| <= L/2 in exact arithmetic; clamp the rounding excess so the
                     // stencil stays inside the padded tile for every width
-                    const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)L);
+                    const double tau = fmin(fmax(tau_of(a.s, k1, k2, c[d], c[3 + d], halfL), 0.0), (double)L);
                     const double left = tau - 0.5 * W;
                     const int b0 = (int)floor(left) + 1;
                     const float f = (float)((double)b0 - left);  // in (0, 1]
-                    kb_weights<W>(a.poly, 2.f * f - 1.f, ph[d]);
+                    kb_weights<W>(a.poly, 2.f * f - 1.f, ph[it]);
                     // in [0, PT - W] for every point of the tile (clamped position); the bound
                     // also keeps the LDS accesses inside the tile should rounding ever differ
-                    lo[d] = min(max(b0 - (tt[d] * T - PADLO), 0), PT - W);
+                    lod[it] = min(max(b0 - (ttd * T - PADLO), 0), PT - W);
+                    if (d == 0) {
+                        const int g = a.group ? a.group[m] : 0;
+                        const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
+                        if constexpr (!CPLX) {
+                            scale = 2.f * h * h;
+                        } else {
+                            // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
+                            const int idx = a.rowstart[k1 + N / 2] + k2;
+                            const float2 bp = a.b[(int64_t)m * a.P + idx];
+                            const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
+                            const float sr = bp.x + bm.x, si = bp.y - bm.y;
+                            float cs = 1.f, sn = 0.f;
+                            if (a.shifts) {
+                                const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
+                                                                      k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+                                cs = (float)cos(th);
+                                sn = (float)sin(th);
+                            }
+                            pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
+                        }
+                        st_kr[p] = lod[it] | (atomicAdd(&bcnt[lod[it]], 1) << 8);
+                    }
                 }
-                const int g = a.group ? a.group[m] : 0;
-                const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
-                if constexpr (!CPLX) {
-                    scale = 2.f * h * h;
+            }
+            __syncthreads();
+            if (tid < 64) {  // exclusive scan of the bucket counts; the counts restart at zero
+                const int v = tid < NK ? bcnt[tid] : 0;
+                int incl = v;
+#pragma unroll
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int t = __shfl_up(incl, o, 64);
+                    if (tid >= o) incl += t;
+                }
+                if (tid < NK) {
+                    bstart[tid] = incl - v;
+                    bcnt[tid] = 0;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int d = dd[it];
+                if (d < 0) continue;
+                const int kr = st_kr[pp[it]];
+                const int slot = bstart[kr & 255] + (kr >> 8);
+                float* q = pt_w + slot * PSTR;
+                if (d == 0) {
+                    // rows of the padded tile: zero, then the window's W rows
+#pragma unroll
+                    for (int r = 0; r < NR; r += 4) *reinterpret_cast<float4*>(q + r) = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+                    for (int j = 0; j < W; ++j) q[lod[it] + j] = scale * ph[it][j];
+                    if constexpr (CPLX) pt_v[slot] = pval;
                 } else {
-                    // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
-                    const int idx = a.rowstart[k1 + N / 2] + k2;
-                    const float2 bp = a.b[(int64_t)m * a.P + idx];
-                    const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
-                    const float sr = bp.x + bm.x, si = bp.y - bm.y;
-                    float cs = 1.f, sn = 0.f;
-                    if (a.shifts) {
-                        const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
-                                                              k2 * a.shifts[2 * (int64_t)m + 1]) / N;
-                        cs = (float)cos(th);
-                        sn = (float)sin(th);
-                    }
-                    pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
+                    const int off = d == 1 ? NR : NR + W;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) q[off + j] = ph[it][j];
+                    reinterpret_cast<unsigned char*>(pt_lo)[4 * slot + d] = (unsigned char)lod[it];
                 }
-                pt_key[tid] = lo[0];
-            }
-            __syncthreads();
-            if (tid < 64) {
-                constexpr int NCH = (SP_PB + 63) / 64;
-                const int ln = tid;
-                const uint64_t lt = (1ull << ln) - 1ull;
-                int key[NCH];
-#pragma unroll
-                for (int ch = 0; ch < NCH; ++ch) key[ch] = ch * 64 + ln < nb ? pt_key[ch * 64 + ln] : -1;
-                int run = 0;
-                for (int v = 0; v < NK; ++v) {
-                    if (ln == 0) bstart[v] = run;
-#pragma unroll
-                    for (int ch = 0; ch < NCH; ++ch) {
-                        const uint64_t msk = __ballot(key[ch] == v);
-                        if (key[ch] == v) pt_slot[ch * 64 + ln] = run + __popcll(msk & lt);
-                        run += __popcll(msk);
-                    }
-                }
-                if (ln == 0) bstart[NK] = run;
-            }
-            __syncthreads();
-            if (tid < nb) {
-                const int d = pt_slot[tid];
-                float* q = pt_w + d * PSTR;
-#pragma unroll
-                for (int r = 0; r < SP_WAVES * H; ++r) {  // row r of the padded tile
-                    const int j1 = r - lo[0];
-                    float w = 0.f;
-#pragma unroll
-                    for (int j = 0; j < W; ++j) w = (j1 == j) ? ph[0][j] : w;
-                    q[r] = scale * w;
-                }
-#pragma unroll
-                for (int j = 0; j < W; ++j) {
-                    q[SP_WAVES * H + j] = ph[1][j];
-                    q[SP_WAVES * H + W + j] = ph[2][j];
-                }
-                pt_lo[d] = lo[0] | (lo[1] << 8) | (lo[2] << 16);
-                if constexpr (CPLX) pt_v[d] = pval;
             }
             __syncthreads();
             // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1], taken two at a time;
             // when the two footprints are disjoint both points' rows are read before either is
             // written back (two independent read-modify-write chains in flight)
             const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
-            const int pbeg = vlo <= vhi ? bstart[vlo] : 0, pend = vlo <= vhi ? bstart[vhi + 1] : 0;
-            constexpr int A2 = SP_WAVES * H, A3 = SP_WAVES * H + W;
-            const int jl = lane < W * W ? lane : 0;
-            const int j2 = jl / W, j3 = jl - (jl / W) * W;  // footprint cell of this lane
-            const bool act = lane < W * W;
+            const int pbeg = vlo <= vhi ? bstart[vlo] : 0;
+            const int pend = vlo <= vhi ? (vhi + 1 < NK ? bstart[vhi + 1] : nb) : 0;
+            constexpr int A2 = NR, A3 = NR + W;
+            // footprint cell (j2, j3) of this lane: the rows of SPLIT fill the first half-wave,
+            // the other rows the second, W lanes per row
+            int j2 = 0, j3 = 0;
+            bool act = false;
+            if constexpr (SPLIT >= 0) {
+                const int half = lane >> 5, idx = lane & 31, rank = idx / W;
+                int seen = 0;
+#pragma unroll
+                for (int r = 0; r < W; ++r) {
+                    if ((((SPLIT >> r) & 1) != 0) != (half == 0)) continue;
+                    if (seen == rank) {
+                        j2 = r;
+                        j3 = idx - rank * W;
+                        act = true;
+                    }
+                    ++seen;
+                }
+            } else {
+                act = lane < W * W;
+                const int jl = act ? lane : 0;
+                j2 = jl / W;
+                j3 = jl - j2 * W;
+            }
             struct Pt {
                 int cb, l1, l2;
                 float rw[H];
@@ -236,7 +302,7 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
                 const float* w = pt_w + pi * PSTR;
                 const int lw = pt_lo[pi];
                 q.l1 = (lw >> 8) & 255;
-                q.l2 = lw >> 16;
+                q.l2 = (lw >> 16) & 255;
                 q.cb = r0 * PP + (q.l1 + j2) * RP + q.l2 + j3;
 #pragma unroll
                 for (int k = 0; k < H; ++k) q.rw[k] = w[r0 + k];
@@ -292,111 +358,147 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     };
 
     // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
-    // rounding of the row intervals; the edge tiles also own the clamped cells beyond the grid
-    constexpr double MARGIN = 1e-3, FAR = 1e30;
-    double blo[3], bhi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
-        bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
-    }
-    if (tid == 0) { qn = 0; qfail = SP_QCAP; }
+    // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
+    // grid.  Each interval is then trimmed to the exact one with the FP64 cell test.
+    constexpr float MARGIN = 1e-2f, FAR = 1e30f;
+    const float blo0 = tt0 == 0 ? -FAR : tt0 * T - MARGIN, bhi0 = (tt0 + 1) * T >= L ? FAR : (tt0 + 1) * T + MARGIN;
+    const float blo1 = tt1 == 0 ? -FAR : tt1 * T - MARGIN, bhi1 = (tt1 + 1) * T >= L ? FAR : (tt1 + 1) * T + MARGIN;
+    const float blo2 = tt2 == 0 ? -FAR : tt2 * T - MARGIN, bhi2 = (tt2 + 1) * T >= L ? FAR : (tt2 + 1) * T + MARGIN;
 
-    for (int mb = wk.y; mb < wk.z; mb += SP_THREADS) {
-        __syncthreads();
-        if (tid == 0) nimg = 0;
-        __syncthreads();
-        const int m = mb + tid;
-        if (m < wk.z) {
-            const float* n = a.nrm + 4 * (int64_t)m;
-            const double dist = fabs(tc[0] * n[0] + tc[1] * n[1] + tc[2] * n[2]);
-            if (dist <= Rt + 1e-3) {
-                const double* c = a.c12 + 6 * (int64_t)m;
-                const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
-                const int sl = atomicAdd(&nimg, 1);
-                img_m[sl] = m;
-                img_k1[sl] = (int)ceil(u1 - rk) - 1;  // first candidate row
+    // the point (k1, k2) of the view with columns c lies in the tile (the test that decides
+    // which tile spreads a point): inside the disk and its clamped cell in the tile per axis
+    auto in_tile = [&](const double* c, int k1, int k2) {
+        if (4 * (k1 * k1 + k2 * k2) > N2) return false;
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int cell = (int)floor(tau_of(a.s, k1, k2, c[d], c[3 + d], halfL));
+            cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+            in = in && (cell / T == (d == 0 ? tt0 : (d == 1 ? tt1 : tt2)));
+        }
+        return in;
+    };
+
+    // the view slots and the queue persist across the image chunks, so that batches are full:
+    // queued points name their view by slot, and the slots are reused only after the queue has
+    // been processed.  A chunk is VPT views per thread (the fixed cost of a chunk, barriers and
+    // the latency of the view data, is paid once for all of them).
+    constexpr int VPT = 4;
+    int base = 0;  // first slot whose rows are not yet enumerated
+    for (int mb = wk.y; mb < wk.z; mb += VPT * SP_THREADS) {
+        unsigned pendv = 0u;  // this thread's views of the chunk that meet the tile, not yet in a slot
+        {
+            float4 nv[VPT];
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) {
+                const int m = mb + v * SP_THREADS + tid;
+                nv[v] = m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int v = 0; v < VPT; ++v) {
+                // the plane meets the tile's cube: distance of the centre at most the cube's half
+                // extent along the normal
+                const int m = mb + v * SP_THREADS + tid;
+                if (m < wk.z && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
+                                    0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3)
+                    pendv |= 1u << v;
             }
         }
-        __syncthreads();
-        // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
-        // plus the disk and half-disk bounds), the exact cell test per point (a bit mask), then
-        // the points are queued.  A reservation that does not fit waits for the queue to be
-        // processed; the reservations that fitted form the prefix up to the first that did not.
-        const int units = nimg * S;
-        for (int ub = 0; ub < units; ub += SP_THREADS) {
-            const int u = ub + tid;
-            int sl = 0, k1 = 0, klo = 0;
-            uint32_t mask = 0u;
-            if (u < units) {
-                sl = u / S;
-                k1 = img_k1[sl] + (u - sl * S);
-                if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+        while (true) {
+            // slots for the surviving views while free ones last
+            for (int v = 0; v < VPT; ++v) {
+                if (!((pendv >> v) & 1u)) continue;
+                const int sl = atomicAdd(&nimg, 1);
+                if (sl < SP_THREADS) {
+                    img_m[sl] = mb + v * SP_THREADS + tid;
+                    pendv &= ~(1u << v);
+                }
+            }
+            __syncthreads();
+            const int top = min(nimg, SP_THREADS);
+            // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
+            // plus the disk and half-disk bounds), trimmed to the exact test at both ends (the cell
+            // along a row is monotone in k2, so the points that pass form an interval), then the
+            // points are queued.  A reservation that does not fit waits for the queue's whole
+            // batches to be processed; the reservations that fitted form the prefix up to the
+            // first that did not.
+            const int units = (top - base) * S;
+            for (int ub = 0; ub < units; ub += SP_THREADS) {
+                const int u = ub + tid;
+                int sl = 0, k1 = 0, klo = 0, cnt = 0;
+                if (u < units) {
+                    const int v = u / S;
+                    sl = base + v;
                     const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const int kd = (int)sqrt((double)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
-                    double lo = -kd, hi = kd;
-                    bool ok = true;
-#pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const double al = a.s * k1 * c[d] + halfL, be = a.s * c[3 + d];
-                        if (fabs(be) < 1e-9) {
-                            ok = ok && al >= blo[d] && al <= bhi[d];
-                        } else {
-                            const double t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
-                            lo = fmax(lo, fmin(t1, t2));
-                            hi = fmin(hi, fmax(t1, t2));
-                        }
-                    }
-                    klo = (int)ceil(lo);
-                    if (k1 == 0) klo = max(klo, 1);
-                    // a row crosses a tile in at most T sqrt(3) / s + 1 points
-                    const int cnt = ok && hi >= klo ? min((int)floor(hi) - klo + 1, 32) : 0;
-                    for (int j = 0; j < cnt; ++j) {
-                        const int k2 = klo + j;
-                        bool in = 4 * (k1 * k1 + k2 * k2) <= N2;
+                    const double u1 = (tc0 * c[0] + tc1 * c[1] + tc2 * c[2]) / a.s;
+                    k1 = (int)ceil(u1 - rk) - 1 + (u - v * S);
+                    if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+                        const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                        float lo = (float)-kd, hi = (float)kd;
+                        bool ok = true;
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
-                            const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
-                            int cell = (int)floor(tau);
-                            cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
-                            in = in && (cell / T == tt[d]);
+                            const float bl = d == 0 ? blo0 : (d == 1 ? blo1 : blo2);
+                            const float bh = d == 0 ? bhi0 : (d == 1 ? bhi1 : bhi2);
+                            const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
+                            if (fabsf(be) < 1e-6f) {
+                                ok = ok && al >= bl && al <= bh;
+                            } else {
+                                const float t1 = (bl - al) / be, t2 = (bh - al) / be;
+                                lo = fmaxf(lo, fminf(t1, t2));
+                                hi = fminf(hi, fmaxf(t1, t2));
+                            }
                         }
-                        if (in) mask |= 1u << j;
+                        klo = (int)ceilf(lo);
+                        if (k1 == 0) klo = max(klo, 1);
+                        int khi = (int)floorf(hi);
+                        if (ok) {
+                            while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
+                            while (khi >= klo && !in_tile(c, k1, khi)) --khi;
+                            // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                            cnt = min(khi - klo + 1, 32);
+                        }
                     }
                 }
-            }
-            const int c = __popc(mask);
-            bool pend = c > 0;
-            while (true) {
-                if (pend) {
-                    const int pos = atomicAdd(&qn, c);
-                    if (pos + c <= SP_QCAP) {
-                        uint32_t mk = mask;
-                        for (int w = pos; mk; ++w) {
-                            const int j = __ffs(mk) - 1;
-                            mk &= mk - 1u;
-                            queue[w] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
+                bool pend = cnt > 0;
+                while (true) {
+                    if (pend) {
+                        const int pos = atomicAdd(&qn, cnt);
+                        if (pos + cnt <= SP_QCAP) {
+                            for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
+                            pend = false;
+                        } else {
+                            atomicMin(&qfail, pos);
                         }
-                        pend = false;
-                    } else {
-                        atomicMin(&qfail, pos);
                     }
+                    if (!__syncthreads_or(pend)) break;
+                    // the queue is full: process its whole batches and keep the rest at its front
+                    const int nv = min(qfail, qn);
+                    const int nfull = nv / SP_PB * SP_PB;
+                    process(nfull);
+                    const int rest = nv - nfull;
+                    const int keep = tid < rest ? queue[nfull + tid] : 0;
+                    __syncthreads();
+                    if (tid < rest) queue[tid] = keep;
+                    if (tid == 0) { qn = rest; qfail = SP_QCAP; }
+                    __syncthreads();
                 }
-                if (!__syncthreads_or(pend)) break;
-                process(min(qfail, qn));  // the queue is full
-                __syncthreads();
-                if (tid == 0) { qn = 0; qfail = SP_QCAP; }
-                __syncthreads();
             }
+            base = top;
+            if (!__syncthreads_or(pendv != 0u)) break;
+            // the slots ran out: process everything queued, then reuse them
+            process(qn);
+            __syncthreads();
+            if (tid == 0) { qn = 0; qfail = SP_QCAP; nimg = 0; }
+            __syncthreads();
+            base = 0;
         }
-        // the view slots are refilled next round: process what is queued
-        process(qn);
-        __syncthreads();
-        if (tid == 0) { qn = 0; qfail = SP_QCAP; }
     }
     __syncthreads();
+    process(qn);
+    __syncthreads();
     if (!any) return;
-    const int o0 = tt[0] * T - PADLO, o1 = tt[1] * T - PADLO, o2 = tt[2] * T - PADLO;
+    const int o0 = tt0 * T - PADLO, o1 = tt1 * T - PADLO, o2 = tt2 * T - PADLO;
     for (int i = tid; i < NCELL; i += SP_THREADS) {
         const int l0 = i / (PT * PT), l1 = (i / PT) % PT, l2 = i % PT;
         const int li = l0 * PP + l1 * RP + l2;
