@@ -66,38 +66,47 @@ __device__ __forceinline__ void kb_weights(const float* __restrict__ poly, float
     }
 }
 
-// LDS bank layout of the footprint accesses.  A wave's LDS access is served as two halves of
-// 32 lanes over 32 banks of 4 bytes, so the W x W footprint cells j2 * pitch + j3 are split by
-// rows between the two halves such that each half's cells fall in distinct banks.
-// rows_disjoint: the cells of the rows in `mask` fall in distinct banks.
-constexpr bool rows_disjoint(int mask, int rp, int W) {
-    bool used[32] = {};
-    for (int r = 0; r < W; ++r) {
-        if (!((mask >> r) & 1)) continue;
-        for (int j = 0; j < W; ++j) {
-            const int b = (r * rp + j) % 32;
-            if (used[b]) return false;
-            used[b] = true;
+// LDS bank layout of the footprint accesses.  LDS has 32 banks of 4 bytes and serves a wave's
+// access in groups of lanes: two groups of 32 for 4-byte elements, four groups of 16 for
+// 8-byte elements (G groups of 64 / G lanes, whose elements must fall in 64 / G distinct
+// element slots modulo 128 bytes).  The W x W footprint cells j2 * pitch + j3 (in elements) are
+// split by rows among the G groups so that each group's cells are conflict-free.
+// place_rows: assign rows r.. to groups (grp[]), by backtracking.
+constexpr bool place_rows(int r, int W, int rp, int G, int* grp) {
+    if (r == W) return true;
+    const int cap = 64 / G;
+    for (int g = 0; g < G; ++g) {
+        int n = 0;
+        for (int q = 0; q < r; ++q) n += grp[q] == g;
+        if ((n + 1) * W > cap) continue;
+        bool ok = true;
+        for (int q = 0; q < r && ok; ++q) {
+            if (grp[q] != g) continue;
+            for (int i = 0; i < W && ok; ++i)
+                for (int j = 0; j < W && ok; ++j)
+                    if ((q * rp + i) % cap == (r * rp + j) % cap) ok = false;
         }
+        if (!ok) continue;
+        grp[r] = g;
+        if (place_rows(r + 1, W, rp, G, grp)) return true;
     }
-    return true;
+    return false;
 }
 
-// rows of the first half (a bit mask) for row pitch rp, or -1 if no split is conflict-free
-constexpr int half_split(int rp, int W) {
-    for (int mask = 0; mask < (1 << W); ++mask) {
-        int na = 0;
-        for (int r = 0; r < W; ++r) na += (mask >> r) & 1;
-        if (na * W > 32 || (W - na) * W > 32) continue;
-        if (rows_disjoint(mask, rp, W) && rows_disjoint(((1 << W) - 1) & ~mask, rp, W)) return mask;
-    }
-    return -1;
+// group of every footprint row (two bits per row) for row pitch rp, or -1 if none is
+// conflict-free
+constexpr int row_groups(int rp, int W, int G) {
+    int grp[8] = {};
+    if (!place_rows(0, W, rp, G, grp)) return -1;
+    int code = 0;
+    for (int r = 0; r < W; ++r) code |= grp[r] << (2 * r);
+    return code;
 }
 
 // smallest LDS row pitch >= PT that admits a conflict-free split
-constexpr int row_pitch(int PT, int W) {
+constexpr int row_pitch(int PT, int W, int G) {
     for (int rp = PT; rp < PT + 32; ++rp)
-        if (half_split(rp, W) >= 0) return rp;
+        if (row_groups(rp, W, G) >= 0) return rp;
     return PT;
 }
 
@@ -115,8 +124,10 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;
     constexpr int H = (PT + SP_WAVES - 1) / SP_WAVES;  // rows per wavefront slab
-    constexpr int RP = row_pitch(PT, W);               // LDS pitch of a tile row (bank-conflict free)
-    constexpr int SPLIT = half_split(RP, W);           // footprint rows of the first half-wave
+    // the real tile holds floats; the complex tile holds (re, im) pairs, one 8-byte access per cell
+    constexpr int G = CPLX ? 4 : 2;                    // lane groups of one LDS access
+    constexpr int RP = row_pitch(PT, W, G);            // LDS pitch of a tile row, in cells (conflict-free)
+    constexpr int GROUPS = row_groups(RP, W, G);       // lane group of every footprint row
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
     constexpr int NR = SP_WAVES * H;                   // planes, padded to whole slabs
     constexpr int NV = CPLX ? 2 : 1;                   // real and imaginary parts in separate tiles
@@ -129,7 +140,7 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     static_assert(NK <= 64, "first-row buckets");
     static_assert(NR % 4 == 0 && PSTR % 4 == 0, "row weights zeroed as float4");
     constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
-    __shared__ __align__(16) float tile[NV * NR * PP];
+    __shared__ __align__(16) float tile[NV * NR * PP];  // complex: (re, im) per cell
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
     __shared__ int pt_lo[SP_PB];                       // window starts of axes 1, 2 in bytes 1, 2
     __shared__ float2 pt_v[CPLX ? SP_PB : 1];
@@ -269,16 +280,16 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
             const int pbeg = vlo <= vhi ? bstart[vlo] : 0;
             const int pend = vlo <= vhi ? (vhi + 1 < NK ? bstart[vhi + 1] : nb) : 0;
             constexpr int A2 = NR, A3 = NR + W;
-            // footprint cell (j2, j3) of this lane: the rows of SPLIT fill the first half-wave,
-            // the other rows the second, W lanes per row
+            // footprint cell (j2, j3) of this lane: lane group g holds the rows assigned to it,
+            // W lanes per row
             int j2 = 0, j3 = 0;
             bool act = false;
-            if constexpr (SPLIT >= 0) {
-                const int half = lane >> 5, idx = lane & 31, rank = idx / W;
+            if constexpr (GROUPS >= 0) {
+                const int g = lane / (64 / G), idx = lane % (64 / G), rank = idx / W;
                 int seen = 0;
 #pragma unroll
                 for (int r = 0; r < W; ++r) {
-                    if ((((SPLIT >> r) & 1) != 0) != (half == 0)) continue;
+                    if (((GROUPS >> (2 * r)) & 3) != g) continue;
                     if (seen == rank) {
                         j2 = r;
                         j3 = idx - rank * W;
@@ -313,8 +324,13 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
             auto rd = [&](const Pt& q, float (&vr)[H], float (&vi)[H]) {
 #pragma unroll
                 for (int k = 0; k < H; ++k) {
-                    vr[k] = tile[q.cb + k * PP];
-                    if (CPLX) vi[k] = tile[NR * PP + q.cb + k * PP];
+                    if constexpr (CPLX) {
+                        const float2 t = reinterpret_cast<const float2*>(tile)[q.cb + k * PP];
+                        vr[k] = t.x;
+                        vi[k] = t.y;
+                    } else {
+                        vr[k] = tile[q.cb + k * PP];
+                    }
                 }
             };
             auto wr = [&](const Pt& q, const float (&vr)[H], const float (&vi)[H]) {
@@ -324,10 +340,9 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
                 } else {
                     const float sr = q.w23 * q.v.x, si = q.w23 * q.v.y;
 #pragma unroll
-                    for (int k = 0; k < H; ++k) {
-                        tile[q.cb + k * PP] = fmaf(q.rw[k], sr, vr[k]);
-                        tile[NR * PP + q.cb + k * PP] = fmaf(q.rw[k], si, vi[k]);
-                    }
+                    for (int k = 0; k < H; ++k)
+                        reinterpret_cast<float2*>(tile)[q.cb + k * PP] =
+                            make_float2(fmaf(q.rw[k], sr, vr[k]), fmaf(q.rw[k], si, vi[k]));
                 }
             };
             for (int pi = pbeg; pi < pend; pi += 2) {
@@ -511,10 +526,10 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
             const float v = tile[li];
             if (v != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, v);
         } else {
-            const float vr = tile[li], vi = tile[NR * PP + li];
+            const float2 v = reinterpret_cast<const float2*>(tile)[li];
             float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
-            if (vr != 0.f) unsafeAtomicAdd(gp, vr);
-            if (vi != 0.f) unsafeAtomicAdd(gp + 1, vi);
+            if (v.x != 0.f) unsafeAtomicAdd(gp, v.x);
+            if (v.y != 0.f) unsafeAtomicAdd(gp + 1, v.y);
         }
     }
 }
