@@ -115,6 +115,13 @@ __device__ __forceinline__ float2 grid_value(const float2* __restrict__ X, int L
     }
 }
 
+// Fine-grid position of the disk point (k1, k2) of a view along axis d, in the form the
+// gridding spread uses: the point enumeration (which tile owns a point) and the gather (where
+// its window starts) evaluate this one expression, so the two agree to the last bit.
+__device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, double c3d, double halfL) {
+    return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
+}
+
 // One queued point: view m and disk point (k1, k2) of the half disk.
 template <int T, int W>
 __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __restrict__ tile, const int* tt, int m,
@@ -129,7 +136,7 @@ __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         // window start and weights exactly as the gridding spread forms them
-        const double tau = fmin(fmax(a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL, 0.0), (double)a.L);
+        const double tau = fmin(fmax(tau_of(a.s, k1, k2, c[d], c[3 + d], halfL), 0.0), (double)a.L);
         const double left = tau - 0.5 * W;
         const int b0 = (int)floor(left) + 1;
         const float f = (float)((double)b0 - left);  // in (0, 1]
@@ -214,14 +221,28 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
     const int S = (int)floor(2.0 * rk) + 3;  // candidate rows per view
     const int N2 = N * N;
     // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
-    // rounding of the row intervals; the edge tiles also own the clamped cells beyond the grid
-    constexpr double MARGIN = 1e-3, FAR = 1e30;
-    double blo[3], bhi[3];
+    // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
+    // grid.  Each interval is then trimmed to the exact one with the FP64 cell test.
+    constexpr float MARGIN = 1e-2f, FAR = 1e30f;
+    float blo[3], bhi[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
         bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
     }
+    // the point (k1, k2) of the view with columns c lies in the tile: inside the disk and its
+    // clamped cell in the tile per axis
+    auto in_tile = [&](const double* c, int k1, int k2) {
+        if (4 * (k1 * k1 + k2 * k2) > N2) return false;
+        bool in = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int cell = (int)floor(tau_of(a.s, k1, k2, c[d], c[3 + d], halfL));
+            cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
+            in = in && (cell / T == tt[d]);
+        }
+        return in;
+    };
 
     auto flush = [&](int n) {
         for (int qi = tid; qi < n; qi += NTH) {
@@ -233,7 +254,7 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
     int m0 = wk.y;
     while (m0 < wk.z) {  // m0 is uniform
         __syncthreads();  // the counters are reset, the tile is in place
-        // 1. views whose plane meets the tile's circumscribed sphere, at least NTH of them
+        // 1. views whose plane meets the tile, at least NTH of them
         //    (or all that remain), PJ_VPT views per thread per round so that the loads of a
         //    round overlap
         int ni = 0;
@@ -248,8 +269,10 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
 #pragma unroll
             for (int v = 0; v < PJ_VPT; ++v) {
                 const int m = m0 + v * NTH + tid;
+                // the plane meets the tile's cube: distance of the centre at most the cube's
+                // half extent along the normal
                 const double dist = fabs(tc[0] * nv[v].x + tc[1] * nv[v].y + tc[2] * nv[v].z);
-                if (m < wk.z && dist <= Rt + 1e-3) {
+                if (m < wk.z && dist <= 0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3) {
                     const double* c = a.c12 + 6 * (int64_t)m;
                     const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
                     const int sl = atomicAdd(&nimg, 1);
@@ -263,9 +286,10 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
             __syncthreads();  // read by every thread before the next round adds to it
         } while (ni < NTH && m0 < wk.z);
         // 2. one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three
-        //    slabs, plus the disk and half-disk bounds), then the exact cell test per point.
-        //    Queue space is reserved per thread; a reservation that does not fit is retried
-        //    after the full queue has been gathered.
+        //    slabs, plus the disk and half-disk bounds), trimmed to the exact cell test at both
+        //    ends (the cell along a row is monotone in k2, so the points that pass form an
+        //    interval).  Queue space is reserved per thread; a reservation that does not fit
+        //    is retried after the full queue has been gathered.
         const int units = ni * S;
         for (int base = 0; base < units; base += NTH) {
             const int u = base + tid;
@@ -275,24 +299,29 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
                 k1 = img_r[sl] + (u - sl * S);
                 if (k1 >= 0 && 4 * k1 * k1 <= N2) {
                     const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const int kd = (int)sqrt((double)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
-                    double lo = -kd, hi = kd;
+                    const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                    float lo = (float)-kd, hi = (float)kd;
                     bool ok = true;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        const double al = a.s * k1 * c[d] + halfL, be = a.s * c[3 + d];
-                        if (fabs(be) < 1e-9) {
+                        const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
+                        if (fabsf(be) < 1e-6f) {
                             ok = ok && al >= blo[d] && al <= bhi[d];
                         } else {
-                            const double t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
-                            lo = fmax(lo, fmin(t1, t2));
-                            hi = fmin(hi, fmax(t1, t2));
+                            const float t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
+                            lo = fmaxf(lo, fminf(t1, t2));
+                            hi = fminf(hi, fmaxf(t1, t2));
                         }
                     }
-                    klo = (int)ceil(lo);
+                    klo = (int)ceilf(lo);
                     if (k1 == 0) klo = max(klo, 1);
-                    // a row crosses a tile in at most T sqrt(3) / s + 1 points
-                    cnt = ok && hi >= klo ? min((int)floor(hi) - klo + 1, 32) : 0;
+                    int khi = (int)floorf(hi);
+                    if (ok) {
+                        while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
+                        while (khi >= klo && !in_tile(c, k1, khi)) --khi;
+                        // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                        cnt = min(khi - klo + 1, 32);
+                    }
                 }
             }
             bool pend = cnt > 0;
@@ -300,19 +329,7 @@ __global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
                 if (pend) {
                     const int pos = atomicAdd(&qn, cnt);
                     if (pos + cnt <= PJ_QCAP) {
-                        const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                        for (int j = 0; j < cnt; ++j) {
-                            const int k2 = klo + j;
-                            bool in = 4 * (k1 * k1 + k2 * k2) <= N2;
-#pragma unroll
-                            for (int d = 0; d < 3; ++d) {
-                                const double tau = a.s * (k1 * c[d] + k2 * c[3 + d]) + halfL;
-                                int cell = (int)floor(tau);
-                                cell = cell < 0 ? 0 : (cell > L - 1 ? L - 1 : cell);
-                                in = in && (cell / T == tt[d]);
-                            }
-                            queue[pos + j] = in ? (sl << 17) | (k1 << 9) | (k2 + 256) : -1;
-                        }
+                        for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 17) | (k1 << 9) | (klo + j + 256);
                         pend = false;
                     } else {
                         for (int j = pos; j < PJ_QCAP; ++j) queue[j] = -1;
