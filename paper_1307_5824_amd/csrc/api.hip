@@ -141,7 +141,7 @@ const char* firm_last_error(firm_plan p) {
 void firm_plan_destroy(firm_plan p) {
     if (!p) return;
     void* dev[] = {p->S2, p->c12, p->nrm, p->group, p->table, p->shifts, p->kb_poly, p->deconv_ker, p->deconv_atb,
-                   p->tw, p->kerc, p->khat, p->T1, p->T2, p->r, p->p, p->q, p->z, p->tmp, p->partials,
+                   p->tw, p->kerc, p->khat, p->T1, p->T2, p->r, p->p, p->z, p->tmp, p->partials,
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
                    p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec,
@@ -281,7 +281,6 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->T2, (size_t)fft_t2_elems(N, false)));
     chk(dalloc(&p->r, (size_t)n3));
     chk(dalloc(&p->p, (size_t)n3));
-    chk(dalloc(&p->q, (size_t)n3));
     chk(dalloc(&p->z, (size_t)n3));
     chk(dalloc(&p->tmp, (size_t)n3));
     p->npart = 16384;

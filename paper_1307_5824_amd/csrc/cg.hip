@@ -113,23 +113,6 @@ __global__ void __launch_bounds__(VT) k_alpha(const double* part, int n, double*
     }
 }
 
-// x += alpha p, r -= alpha q (FP64 arithmetic, FP32 storage); partial sums of r^2.
-__global__ void __launch_bounds__(VT) k_update(float* __restrict__ x, const float* __restrict__ p,
-                                               float* __restrict__ r, const float* __restrict__ q, int64_t n,
-                                               const double* scal, const int* flags, double* partials) {
-    if (flags[F_ACTIVE] == 0) return;
-    const double a = scal[S_ALPHA];
-    double acc = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)VT + threadIdx.x; i < n; i += (int64_t)gridDim.x * VT) {
-        x[i] = (float)((double)x[i] + a * (double)p[i]);
-        const float rv = (float)((double)r[i] - a * (double)q[i]);
-        r[i] = rv;
-        acc += (double)rv * (double)rv;
-    }
-    const double s = block_reduce(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
 // rr = ||r||^2, rz = <r, z> (= rr without preconditioner), beta = rz_new / rz_old, stop tests.
 __global__ void __launch_bounds__(VT) k_beta(const double* part_rr, int n_rr, const double* part_rz, int n_rz,
                                              double* scal, int* flags) {
@@ -207,7 +190,9 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
     hipStream_t st = p->stream;
     double* scal = p->scal;
     int* flags = p->flags;
-    const int nb_apply = ceil_div((int64_t)N * N / 2, 2 * N >= 1024 ? 8 : (2 * N >= 128 ? 16 : 2048 / (2 * N)));
+    const int nb_apply = fft_apply_cg_partials(p);     // partials of <p, q> per product
+    const int nb_step = fft_apply_cg_step_partials(p);  // partials of ||r||^2 per CG step
+    if (nb_apply <= 0 || nb_apply > p->npart || nb_step <= 0 || nb_step > p->npart) CK(hipErrorInvalidValue);
     const int nb_prec = ceil_div((int64_t)N * N / 2, N >= 1024 ? 8 : (N >= 128 ? 16 : 2048 / N));
     bool pc = (d != nullptr);
     int refinements = 0, fell_back = 0;
@@ -242,12 +227,13 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
     for (;;) {
         for (int i = 0; i < p->check_every; ++i) {
             const float* src = pc ? p->z : p->r;
-            CK(fft_apply_cg(p, src, p->p, p->q, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
+            // p = src + beta p and q = (A*A + lam) p, with alpha = rz / <p, q> formed between the
+            // two halves of the product and the step x += alpha p, r -= alpha q in its last pass
+            CK(fft_apply_cg_front(p, src, p->p, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
             hipLaunchKernelGGL(k_alpha, dim3(1), dim3(VT), 0, st, p->partials, nb_apply, scal, flags);
-            hipLaunchKernelGGL(k_update, dim3(VB), dim3(VT), 0, st, x, p->p, p->r, p->q, n, scal, flags,
-                               p->partials3);
+            CK(fft_apply_cg_step(p, x, p->p, p->r, scal + S_ALPHA, flags + F_ACTIVE, p->partials3));
             if (pc) CK(fft_precond(p, p->dhalf, p->r, p->z, flags + F_ACTIVE, p->partials2));
-            hipLaunchKernelGGL(k_beta, dim3(1), dim3(VT), 0, st, p->partials3, VB, pc ? p->partials2 : nullptr,
+            hipLaunchKernelGGL(k_beta, dim3(1), dim3(VT), 0, st, p->partials3, nb_step, pc ? p->partials2 : nullptr,
                                nb_prec, scal, flags);
             ++it_host;
             if (p->refine_every > 0 && it_host % p->refine_every == 0) {

@@ -172,13 +172,24 @@ k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typenam
     }
 }
 
+// CG step fused into the last pass of the product q = (A*A + lam) p: with alpha already formed,
+// x += alpha p and r -= alpha q (FP64 arithmetic, FP32 storage), and the block partials of
+// ||r||^2; q itself is not stored.
+struct CgStep {
+    float* x;
+    const float* p;
+    float* r;
+    const double* alpha;
+};
+
 // Half spectra (modes 0..L/2 of two real rows) -> real rows, first n_out samples.
 // y = scale * x + lam * xadd.  DOT: also a block partial of sum(xadd * y) in FP64.
-template <int L, bool DOT, class S, bool HOUT>
+// STEP: y is the CG product q, consumed by the CG step (dst unused), partials of ||r||^2.
+template <int L, bool DOT, class S, bool HOUT, bool STEP = false>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch, S* __restrict__ dst, int out_pitch,
            int n_out, S sg, S scale, S lam, const S* __restrict__ xadd, const typename VecOf<S>::V* __restrict__ tw,
-           double* partials, const int* active) {
+           double* partials, const int* active, CgStep step) {
     using V = typename VecOf<S>::V;
     constexpr int C = FftCfg<L, V>::C, T = L / 8, NT = FftCfg<L, V>::THREADS;
     using P = Pen<L, C, true>;
@@ -210,6 +221,8 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
     if (TWL) __syncthreads();  // the twiddle table is in place
     fft_reg<L, C, true>(v, lds, twp, sg);
     double acc = 0.0;
+    double alpha = 0.0;
+    if constexpr (STEP) alpha = *step.alpha;
     if (valid) {
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
@@ -219,6 +232,14 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
                 for (int rr = 0; rr < 2; ++rr) {
                     const int64_t g = (int64_t)(2 * pr + rr) * out_pitch + e;
                     S y = scale * (rr ? v[t].y : v[t].x);
+                    if constexpr (STEP) {
+                        const float pv = ld_nt(step.p + g), xv = ld_nt(step.x + g), rv0 = ld_nt(step.r + g);
+                        st_nt((float)((double)xv + alpha * (double)pv), step.x + g);
+                        const float rv = (float)((double)rv0 - alpha * (double)y);
+                        st_nt(rv, step.r + g);
+                        acc += (double)rv * (double)rv;
+                        continue;
+                    }
                     if (xadd) {
                         const S xv = xadd[g];
                         y += lam * xv;
@@ -229,7 +250,7 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
             }
         }
     }
-    if (DOT) {
+    if (DOT || STEP) {
         __syncthreads();  // every wavefront has finished reading the exchange buffer
         const double s = block_sum<NT>(acc, reinterpret_cast<double*>(lds));
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -432,11 +453,14 @@ __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__
 // inverse transform, keep the first n_in.
 // K16: the spectrum is the 16-bit form of the option khat_bf16 (BF16 codes b, value
 // mu(shell) + sc(shell) b with the per-shell pairs in shtab, or b itself when shtab is null).
-template <int L, class S, bool HALF, bool K16>
+// DOT (the product's half spectrum, columns q3 in [0, L/2]): also a block partial of
+// <x, y> = sum over the full spectrum of (K^ + kadd) |X^|^2 (Parseval, unnormalised transforms),
+// the columns q3 = 0 and q3 = L/2 once and the others twice (X^(-q) = conj X^(q)).
+template <int L, class S, bool HALF, bool K16, bool DOT>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, const float2* __restrict__ shtab,
       S kadd, int nouter, int ncols, int64_t s_outer, int64_t s_elem, int64_t s_group, int n_in,
-      const typename VecOf<S>::V* __restrict__ tw, const int* active) {
+      const typename VecOf<S>::V* __restrict__ tw, const int* active, double* __restrict__ dotp) {
     // HALF: the pencils are zero-padded (n_in = L / 2) and only their first half is kept, which
     // the compiler folds into the first and last stages
     using V = typename VecOf<S>::V;
@@ -447,6 +471,7 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
     constexpr bool TWL = sizeof(S) == 4;
     __shared__ V lds[P::LDS];
     __shared__ V twl[TWL ? FIRM_TWN : 1];
+    __shared__ double red[DOT ? P::NT / 64 : 1];
     if (cg_inactive(active)) return;
     if (TWL)
         for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
@@ -491,10 +516,24 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
     }
     if (TWL) __syncthreads();  // the twiddle table is in place
     fft_reg<L, C, false>(v, lds, twp, (S)-1);
+    // the thread's 8 terms in FP32 (as the product itself), the block sum in FP64
+    S acc8 = 0;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const S k = kv[t] + kadd;
+        if (DOT) acc8 += k * (v[t].x * v[t].x + v[t].y * v[t].y);
         v[t] = mkv<V>(v[t].x * k, v[t].y * k);
+    }
+    if constexpr (DOT) {  // pencils that do not exist hold zeros
+        double acc = (double)acc8 * ((col == 0 || col == ncols - 1) ? 1.0 : 2.0);
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < P::NT / 64; ++w) sum += red[w];
+            dotp[blockIdx.x] = sum;
+        }
     }
     fft_reg<L, C, false>(v, lds, twp, (S)1);
     if (!valid) return;
@@ -540,10 +579,22 @@ hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_out == L)
         hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
-                           dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active);
+                           dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active, CgStep{});
     else
         hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
-                           in_pitch, dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active);
+                           in_pitch, dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active, CgStep{});
+    return hipGetLastError();
+}
+
+// the last pass of the CG product with the CG step (n_out = L / 2)
+template <int L>
+hipError_t launch_c2r_step(hipStream_t st, const float2* src, int nrows, int in_pitch, int out_pitch, const float2* tw,
+                           double* partials, const int* active, CgStep step) {
+    using Cfg = FftCfg<L, float2>;
+    const int blocks = ceil_div(nrows / 2, Cfg::C);
+    hipLaunchKernelGGL((k_rows_c2r<L, false, float, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+                       in_pitch, (float*)nullptr, out_pitch, L / 2, 1.f, 1.f, 0.f, (const float*)nullptr, tw, partials,
+                       active, step);
     return hipGetLastError();
 }
 
@@ -578,7 +629,7 @@ template <int L, class S = float>
 hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec, int nouter, int ncols,
                       int64_t s_outer, int64_t s_elem, int n_in, const typename VecOf<S>::V* tw,
                       const int* active = nullptr, int64_t s_group = -1, S kadd = 0,
-                      const uint16_t* spec16 = nullptr, const float2* shtab = nullptr) {
+                      const uint16_t* spec16 = nullptr, const float2* shtab = nullptr, double* dotp = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
     constexpr int C = Cfg::C;
     if (s_group < 0) s_group = C;
@@ -586,22 +637,27 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
     const int blocks = tail_packed_blocks<C>(nouter, ncols);
     bool k16 = false;
     if constexpr (sizeof(S) == 4) k16 = spec16 != nullptr;
+    const bool half = 2 * n_in == L, dot = dotp != nullptr;
+    if (dot && !half) return hipErrorInvalidValue;  // the dot is formed for the product only
+#define FIRM_MID(H, K, D)                                                                                      \
+    hipLaunchKernelGGL((k_mid<L, S, H, K, D>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd, \
+                       nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active, dotp)
     if (k16) {
         if constexpr (sizeof(S) == 4) {
-            if (2 * n_in == L)
-                hipLaunchKernelGGL((k_mid<L, S, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab,
-                                   kadd, nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
-            else
-                hipLaunchKernelGGL((k_mid<L, S, false, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab,
-                                   kadd, nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+            if (half) {
+                if (dot) FIRM_MID(true, true, true);
+                else FIRM_MID(true, true, false);
+            } else {
+                FIRM_MID(false, true, false);
+            }
         }
-    } else if (2 * n_in == L) {
-        hipLaunchKernelGGL((k_mid<L, S, true, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd,
-                           nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+    } else if (half) {
+        if (dot) FIRM_MID(true, false, true);
+        else FIRM_MID(true, false, false);
     } else {
-        hipLaunchKernelGGL((k_mid<L, S, false, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd,
-                           nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active);
+        FIRM_MID(false, false, false);
     }
+#undef FIRM_MID
     return hipGetLastError();
 }
 
@@ -611,17 +667,20 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
         if (e__ != hipSuccess) return e__; \
     } while (0)
 
-// The five passes of y = crop(IFFT(K^ . FFT(pad x))) + lam x for one N (L = 2N).
-// CG form: the first pass forms p = src + beta p and the last q = . + lam p with <p, q>.
+// The five passes of y = crop(IFFT(K^ . FFT(pad x))) + lam x for one N (L = 2N), as a front
+// (passes A-C) and a back (passes D-E).
+// CG form: the front's first pass forms p = src + beta p and its middle pass the block
+// partials of <p, q> from the spectrum (fft_apply_cg_partials of them); the back's last pass
+// takes the CG step with the alpha formed from them in between (fft_apply_cg_step_partials
+// partials of ||r||^2).
 template <int L>
-hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, float lam, const double* beta,
-                        const int* active, double* partials, hipEvent_t* ev = nullptr) {
+hipError_t apply_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta, const int* active,
+                       double* dotp, hipEvent_t* ev) {
     const int N = L / 2, QP = p->QP;
     hipStream_t st = p->stream;
-    const bool cg = (beta != nullptr);
     if (ev) RET_IF(hipEventRecord(ev[0], st));
     // A: rows along i3, N real -> padded 2N transform, modes 0..N kept
-    if (cg)
+    if (beta)
         RET_IF((launch_r2c<L, true>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw, pvec, beta, active)));
     else
         RET_IF((launch_r2c<L, false>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw)));
@@ -634,23 +693,41 @@ hipError_t apply_passes(firm_plan p, const float* src, float* pvec, float* y, fl
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T1, p->T2, N, N + 1, (int64_t)N * QP, 1, QP, C, 1,
                                                           se_, N, L, -1.f, p->tw, EpiArgs(), active, -1, sg_)));
     if (ev) RET_IF(hipEventRecord(ev[2], st));
-    // C: along i1 for every (q2, q3): forward, times K^, inverse, keep i1 < N.  The plain form
-    // multiplies by K^ + lam / L^3 instead: with the unnormalised inverse that adds exactly
-    // lam x to the cropped output, so that pass E need not read x
-    const float kadd = cg ? 0.f : lam / ((float)L * L * L);
+    // C: along i1 for every (q2, q3): forward, times K^ + lam / L^3, inverse, keep i1 < N.
+    // With the unnormalised inverse the lam term adds exactly lam x to the cropped output, so
+    // that pass E need not read x
+    const float kadd = lam / ((float)L * L * L);
     RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd,
-                          p->khat_bf16 ? p->khat16 : nullptr, p->khat_bf16 == 1 ? p->shtab : nullptr)));
+                          p->khat_bf16 ? p->khat16 : nullptr, p->khat_bf16 == 1 ? p->shtab : nullptr, dotp)));
     if (ev) RET_IF(hipEventRecord(ev[3], st));
+    return hipSuccess;
+}
+
+template <int L>
+hipError_t apply_back(firm_plan p, float* y, const int* active, const CgStep* step, double* partials,
+                      hipEvent_t* ev) {
+    const int N = L / 2, QP = p->QP;
+    hipStream_t st = p->stream;
+    constexpr int C = FftCfg<L, float2>::C;
+    const int64_t ng = (N + 1 + C - 1) / C, sg_ = (int64_t)N * C, se_ = ng * (int64_t)N * C;
     // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
                                                           QP, L, N, 1.f, p->tw, EpiArgs(), active, sg_, -1)));
     if (ev) RET_IF(hipEventRecord(ev[4], st));
-    // E: inverse along q3 (half spectrum -> real), crop (CG form: + lam p and <p, q>)
-    if (cg)
-        return launch_c2r<L, true>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, lam, pvec, p->tw, partials, active);
-    RET_IF((launch_c2r<L, false>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, 0.f, (const float*)nullptr, p->tw)));
+    // E: inverse along q3 (half spectrum -> real), crop; CG form: the CG step instead of a store
+    if (step)
+        RET_IF(launch_c2r_step<L>(st, p->T1, N * N, QP, N, p->tw, partials, active, *step));
+    else
+        RET_IF((launch_c2r<L, false>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, 0.f, (const float*)nullptr, p->tw,
+                                     nullptr, active)));
     if (ev) RET_IF(hipEventRecord(ev[5], st));
     return hipSuccess;
+}
+
+template <int L>
+hipError_t apply_passes(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev = nullptr) {
+    RET_IF(apply_front<L>(p, x, nullptr, lam, nullptr, nullptr, nullptr, ev));
+    return apply_back<L>(p, y, nullptr, nullptr, nullptr, ev);
 }
 
 // FP64 form of the product, for true residuals and the FP64 solver modes: the same
@@ -821,6 +898,26 @@ int fft_cols_per_block(int L, bool dbl) {
     return 0;
 }
 
+namespace {
+template <int L>
+int apply_mid_blocks_t() { return tail_packed_blocks<FftCfg<L, float2>::C>(L, L / 2 + 1); }
+}  // namespace
+
+int fft_apply_cg_partials(firm_plan p) {
+    DISPATCH_L(2 * p->N, apply_mid_blocks_t);
+    return 0;
+}
+
+namespace {
+template <int L>
+int c2r_blocks_t(int N) { return ceil_div(N * N / 2, FftCfg<L, float2>::C); }
+}  // namespace
+
+int fft_apply_cg_step_partials(firm_plan p) {
+    DISPATCH_L(2 * p->N, c2r_blocks_t, p->N);
+    return 0;
+}
+
 int64_t fft_t2_elems(int N, bool dbl) {
     const int C = fft_cols_per_block(2 * N, dbl);
     return (int64_t)2 * N * N * (((N + 1 + C - 1) / C) * C);
@@ -832,18 +929,25 @@ size_t blocked_spectrum_elems(int L, int nouter, int ncols, bool dbl) {
 }
 
 hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam) {
-    DISPATCH_L(2 * p->N, apply_passes, p, x, nullptr, y, lam, nullptr, nullptr, nullptr);
+    DISPATCH_L(2 * p->N, apply_passes, p, x, y, lam);
     return hipErrorInvalidValue;
 }
 
 hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev) {
-    DISPATCH_L(2 * p->N, apply_passes, p, x, nullptr, y, lam, nullptr, nullptr, nullptr, ev);
+    DISPATCH_L(2 * p->N, apply_passes, p, x, y, lam, ev);
     return hipErrorInvalidValue;
 }
 
-hipError_t fft_apply_cg(firm_plan p, const float* r, float* pvec, float* q, float lam, const double* beta_dev,
-                        const int* active, double* partials) {
-    DISPATCH_L(2 * p->N, apply_passes, p, r, pvec, q, lam, beta_dev, active, partials);
+hipError_t fft_apply_cg_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta_dev,
+                              const int* active, double* dotp) {
+    DISPATCH_L(2 * p->N, apply_front, p, src, pvec, lam, beta_dev, active, dotp, nullptr);
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_apply_cg_step(firm_plan p, float* x, const float* pvec, float* r, const double* alpha_dev,
+                             const int* active, double* partials) {
+    const CgStep step{x, pvec, r, alpha_dev};
+    DISPATCH_L(2 * p->N, apply_back, p, nullptr, active, &step, partials, nullptr);
     return hipErrorInvalidValue;
 }
 

@@ -61,7 +61,7 @@ struct firm_plan_s {
     float *rhs = nullptr, *dvec = nullptr;  // FP32 correction right-hand side and solution
 
     // CG workspaces
-    float *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr, *tmp = nullptr;
+    float *r = nullptr, *p = nullptr, *z = nullptr, *tmp = nullptr;
     double* partials = nullptr;  // per-block FP64 partial sums
     int npart = 0;
     double* scal = nullptr;      // device scalars (see cg.hip)
@@ -119,8 +119,17 @@ hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z
 hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam);
 hipError_t fft_khat64_from_kerc64(firm_plan p, const double* kerc64, double2* w1);
 // fused CG variants of the apply passes (cg.hip drives them)
-hipError_t fft_apply_cg(firm_plan p, const float* r, float* pvec, float* q, float lam,
-                        const double* beta_dev, const int* active, double* partials);
+// CG product in two parts: the front forms p = src + beta p (beta on the device), transforms it
+// and multiplies by K^ + lam / (2N)^3, writing fft_apply_cg_partials(p) block partials of
+// <p, (A*A + lam) p> to dotp; the step finishes the product q and, with alpha on the device,
+// takes x += alpha p, r -= alpha q, writing fft_apply_cg_step_partials(p) partials of ||r||^2.
+// Both do nothing while *active == 0.
+hipError_t fft_apply_cg_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta_dev,
+                              const int* active, double* dotp);
+hipError_t fft_apply_cg_step(firm_plan p, float* x, const float* pvec, float* r, const double* alpha_dev,
+                             const int* active, double* partials);
+int fft_apply_cg_step_partials(firm_plan p);
+int fft_apply_cg_partials(firm_plan p);
 
 // ---- spread.hip ----
 hipError_t spread_ker(firm_plan p, float* grid);

@@ -8,21 +8,21 @@
 //
 // Work decomposition: the grid is cut into T^3 tiles.  A workgroup owns one
 // tile (or one tile and a range of images): it tests every image plane of its
-// range against the tile's circumscribed sphere, enumerates the disk points of
-// the surviving images whose cell floor(t + L/2) lies in the tile, and
-// accumulates their full W^3 stencils into a (T + W)^3 LDS tile; the tile is
-// then added to the global grid with one atomic per cell.  Each point is spread
-// exactly once.
+// range against the tile's cube, enumerates the disk points of the surviving
+// images whose cell floor(t + L/2) lies in the tile (an exact k2 interval per
+// row), and accumulates their full W^3 stencils into a (T + W)^3 LDS tile; the
+// tile is then added to the global grid with one atomic per cell.  Each point is
+// spread exactly once.
 //
 // The LDS accumulation uses no atomics (LDS float atomics run at a fraction of
 // the plain read/write rate on this chip).  Each wavefront owns a slab of rows
 // (first tile axis) of the padded tile.  The per-point window weights are
-// computed once, one thread per point, and staged in LDS; then every wavefront
-// walks the staged points whose W rows meet its slab, with its lanes on the
-// W x W footprint of the other two axes: all W rows are read, updated and
-// written back inside the slab.  Within one instruction the lanes' cells are
-// distinct and no two wavefronts write the same row, so the plain
-// read-modify-write is race-free.  Only the half disk (k1 > 0, or k1 = 0 and
+// computed once, one thread per point and axis, and staged in LDS ranked by the
+// window's first row; then every wavefront walks the staged points whose W rows
+// meet its slab, with its lanes on the W x W footprint of the other two axes:
+// all rows of the slab are read, updated and written back.  Within one
+// instruction the lanes' cells are distinct and no two wavefronts write the same
+// row, so the plain read-modify-write is race-free.  Only the half disk (k1 > 0, or k1 = 0 and
 // k2 > 0) is spread: its partner -k is folded in (Ker is real and even; for A*b
 // the pair (k, -k) gives the real part exactly), and k = 0 is added afterwards
 // in closed form.
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
     constexpr int GROUPS = row_groups(RP, W, G);       // lane group of every footprint row
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
     constexpr int NR = SP_WAVES * H;                   // planes, padded to whole slabs
-    constexpr int NV = CPLX ? 2 : 1;                   // real and imaginary parts in separate tiles
+    constexpr int NV = CPLX ? 2 : 1;                   // floats per cell
     // staged point: the weights of the NR tile rows (0 outside the window), then the window
     // weights of axes 1 and 2; stride in floats
     constexpr int PSTR = ((NR + 2 * W) + 3) / 4 * 4;

@@ -64,11 +64,13 @@ def test_bf16_spectrum_product_within_1e3(firm, N, M, mode):
 
 
 def test_bf16_spectrum_refined_solve(firm):
-    """precision 1: 16-bit inner product, FP64 outer residual with the FP32 kernel."""
+    """precision 1: 16-bit inner product, FP64 outer residual with the FP32 kernel.  The
+    right-hand side is FP64, so the solve returns its FP64 iterate, the one the outer residual
+    test stops on (an FP32 copy of it can exceed the tolerance by its own rounding)."""
     N, M = 32, 200
     R, grp, table, Ker = _physical(N, M, 77)
     K = dev(ker_to_centred(Ker, N))
-    atb = dev(np.random.default_rng(3).standard_normal((N, N, N)))
+    atb = dev(np.random.default_rng(3).standard_normal((N, N, N)), torch.float64)
     sols = {}
     for bf in (0, 1):
         plan = firm.Plan(N, R, ctf_group=grp, ctf_table=table, precision=1, lambda_relative=1, khat_bf16=bf)
