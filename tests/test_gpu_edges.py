@@ -3,7 +3,8 @@
 * Axis-aligned views (the 24 rotations of the cube): every sample point lies on the fine grid
   and every cell on a tile boundary, the worst case of the tile enumeration.
 * One view, and one view repeated: Ker is supported on one plane (the oracle pins the
-  single-view kernel to a 2D sum), M copies scale it by M.
+  single-view kernel to a 2D sum), M copies scale it by M; enough copies to overflow the
+  spread's view slots within one round.
 * A zero right-hand side: every solver mode returns x = 0 at once.
 Tolerances as in the parity tests (1e-5 relative L2 for FP32 operators).
 """
@@ -16,6 +17,7 @@ torch = pytest.importorskip("torch")
 
 from gpu_common import ker_to_centred, rel, small_geometry  # noqa: E402
 from oracle import firm as ofirm  # noqa: E402
+from paper_1307_5824_amd import synth  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +73,35 @@ def test_axis_aligned_views(firm, N):
     fv = host(plan.forward_project(dev(V))).astype(np.complex128)
     reff = ofirm.forward_project(V.astype(np.float64), R) * np.conj(ofirm.shift_phase(N, sh))
     assert rel(fv, reff) < TOL
+
+
+def test_many_copies_of_one_view_fill_the_view_slots(firm):
+    """700 copies of one view, each with one of three CTFs.  Every copy meets the same tiles,
+    more than the spread's view slots of one round hold (512 for Ker, 256 for A*b), so the
+    queues are processed and the slots reused in the middle of a round.  With one geometry the
+    oracle sums reduce to one-view ones: Ker = sum over the groups of count * the one-view
+    kernel with that CTF, A*b = the one-view back-projection of sum_m h_m b_m, and every slice
+    of the forward projection is h_m times the one-view slice."""
+    N, M, G = 16, 700, 3
+    print(f"many copies of one view N={N} M={M}", flush=True)
+    R1, _, _, _ = small_geometry(N, 1, 17)
+    rng = np.random.default_rng(18)
+    table = synth.ctf_table(N, synth.defoci(G, rng))
+    grp = rng.integers(0, G, M).astype(np.int32)
+    plan = firm.Plan(N, np.repeat(R1, M, axis=0), ctf_group=grp, ctf_table=table)
+    plan.kernel_precompute()
+    ker_ref = sum(np.count_nonzero(grp == g) * ofirm.kernel_direct(N, R1, ofirm.ctf_weights(N, 1, [g], table)).real
+                  for g in range(G))
+    assert rel(host(plan.kernel_get()).astype(np.float64), ker_to_centred(ker_ref, N)) < TOL
+    P = ofirm.slice_point_count(N)
+    h = ofirm.ctf_weights(N, M, grp, table)
+    b = (rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))).astype(np.complex64)
+    atb = host(plan.backproject(dev(b, torch.complex64))).astype(np.float64)
+    atb_ref = ofirm.back_project((h * b.astype(np.complex128)).sum(axis=0, keepdims=True), N, R1).real
+    assert rel(atb, atb_ref) < TOL
+    V = rng.standard_normal((N, N, N)).astype(np.float32)
+    fv = host(plan.forward_project(dev(V))).astype(np.complex128)
+    assert rel(fv, h * ofirm.forward_project(V.astype(np.float64), R1)) < TOL
 
 
 def test_single_and_repeated_view(firm):
