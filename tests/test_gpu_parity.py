@@ -322,6 +322,25 @@ def test_pcg_unit_diagonal_equals_cg(firm):
     assert rel(host(x2), host(x1)) < 2 * tol
 
 
+def test_pcg_breakdown_falls_back_to_cg(firm):
+    """An indefinite preconditioner (d = -1: <r, z> < 0 after the first step) is a breakdown;
+    the solver restarts as plain CG from the current iterate and still reaches the tolerance,
+    judged by the oracle's residual of the returned x."""
+    N, M = 16, 30
+    R, _, _, _ = small_geometry(N, M, 75)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 0.1 * float(Ker[N - 1, N - 1, N - 1])
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    b = np.random.default_rng(12).standard_normal((N, N, N))
+    x, rep = plan.cg_solve(dev(b), lam, 1e-4, 500, precond=-torch.ones((N, N, N), device="cuda"))
+    print(f"breakdown fallback: {rep['iters']} iterations, fell_back {rep['fell_back']}", flush=True)
+    assert rep["status"] == 0 and rep["fell_back"] == 1
+    xr = host(x).astype(np.float64)
+    res = b - (ofirm.toeplitz_apply_fft(Ker, xr).real + lam * xr)
+    assert np.linalg.norm(res) / np.linalg.norm(b) <= 1.5e-4
+
+
 def test_pcg_iterates_match_oracle(firm):
     """PCG with a non-trivial even diagonal (the inverse of T. Chan's circulant) against the
     oracle's FP64 PCG, 10 steps, within the FP32 rounding envelope of that recursion."""
