@@ -1,0 +1,114 @@
+"""Full-size parity at N = 256, M = 10^5 (the large workload, in the configuration bench.py
+times) on sampled outputs the oracle computes one by one.
+
+* Ker (eq. kernel) at sampled offsets, including the origin and the crop edges, against the
+  FP64 direct sum of oracle/direct.c over all 5.1e9 sample points with their CTFs.
+* The product (eq. property) of a unit impulse at voxel m0 is Ker(n - m0): sampled outputs
+  of the GPU product with the GPU's own kernel against the same direct sums.
+* A*b (eq. backprojection) for slices that are zero except 120 entries in 40 views (the
+  origin of one view included): the sum over views reduces to those 40, so the oracle's
+  direct sum over them gives A*b exactly, while the GPU runs the full 10^5-view launch.
+Tolerances: relative L2 over the samples 1e-5 (as at small sizes); every sampled kernel value
+within 1e-5 Ker(0): a (4N)^3 grid cell sums about 820 window contributions at this size, so
+its FP32 rounding is about sqrt(820) 2^-24 = 1.7e-6 of the largest values; and each value
+within 1e-3 of itself plus 1e-8 Ker(0): far from the origin the FFT leaves an absolute error
+near 1e-9 Ker(0), so this catches a far value that is wrong (a crop or wrap mistake) while
+the global measures cannot see it.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import rel  # noqa: E402
+from oracle import direct as odirect  # noqa: E402
+from oracle import firm as ofirm  # noqa: E402
+from paper_1307_5824_amd import synth  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+N = 256
+
+OFFSETS = np.array([[0, 0, 0], [1, 0, 0], [0, -1, 0], [0, 0, 1], [5, -3, 2], [-17, 40, -9], [60, -45, 30],
+                    [-110, 90, -70], [200, -150, 90], [-255, 0, 255], [255, -255, 128], [3, 254, -251]])
+M0 = np.array([128, 121, 131])
+APPLY_OFFSETS = np.array([[0, 0, 0], [1, 0, 0], [0, -1, 0], [7, 2, -5], [-40, 31, 22], [90, -100, -120],
+                          [-120, 120, 100], [127, -121, 124]])
+
+
+@pytest.fixture(scope="module")
+def firm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1307_5824_amd import firm as f
+    return f
+
+
+@pytest.fixture(scope="module")
+def large(firm):
+    inp = synth.make_inputs("large")
+    print("full size: plan and kernel precompute", flush=True)
+    plan = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
+                     precision=1, lambda_relative=1)
+    plan.kernel_precompute()
+    torch.cuda.synchronize()
+    yield inp, plan
+    plan.close()
+
+
+def _at(vol, idx):
+    t = torch.as_tensor(np.asarray(idx, dtype=np.int64)).cuda()
+    out = vol[t[:, 0], t[:, 1], t[:, 2]]
+    torch.cuda.synchronize()
+    return out.cpu().numpy().astype(np.float64)
+
+
+def test_kernel_and_product_at_full_size_sampled(firm, large):
+    inp, plan = large
+    offs = np.concatenate([OFFSETS, APPLY_OFFSETS])
+    print(f"full size: direct sums at {len(offs)} offsets", flush=True)
+    ref = odirect.kernel_at(offs, N, inp.rotations, inp.ctf_group, inp.ctf_table).real
+    ker_ref, app_ref = ref[:len(OFFSETS)], ref[len(OFFSETS):]
+    got = _at(plan.kernel_get(), OFFSETS + N)
+    err = np.abs(got - ker_ref)
+    for o, r, e in zip(OFFSETS.tolist(), ker_ref, err):
+        print(f"  Ker{tuple(o)} = {r:.6e}, |err| {e:.3e}", flush=True)
+    print(f"kernel: rel L2 {rel(got, ker_ref):.2e}, max |err| / Ker(0) {err.max() / ker_ref[0]:.2e}", flush=True)
+    assert rel(got, ker_ref) < TOL
+    assert err.max() <= TOL * ker_ref[0]
+    assert np.all(err <= 1e-3 * np.abs(ker_ref) + 1e-8 * ker_ref[0])
+    x = torch.zeros((N, N, N), device="cuda")
+    x[tuple(M0)] = 1.0
+    y = plan.apply_AtA(x, 0.0)
+    got = _at(y, M0 + APPLY_OFFSETS)
+    err = np.abs(got - app_ref)
+    print(f"product: rel L2 {rel(got, app_ref):.2e}, max |err| / Ker(0) {err.max() / ker_ref[0]:.2e}", flush=True)
+    assert rel(got, app_ref) < TOL
+    assert err.max() <= TOL * ker_ref[0]
+    assert np.all(err <= 1e-3 * np.abs(app_ref) + 1e-8 * ker_ref[0])
+
+
+def test_backproject_at_full_size_sampled(firm, large):
+    inp, plan = large
+    M, P = plan.M, plan.P
+    rng = np.random.default_rng(256)
+    views = np.sort(rng.choice(M, 40, replace=False))
+    b = torch.zeros((M, P), dtype=torch.complex64, device="cuda")
+    bv = np.zeros((len(views), P), dtype=np.complex64)
+    for i in range(len(views)):
+        ks = rng.choice(P, 3, replace=False)
+        if i == 0:
+            ks[0] = (P - 1) // 2  # the origin, added in closed form
+        bv[i, ks] = (rng.standard_normal(3) + 1j * rng.standard_normal(3)).astype(np.complex64)
+    b[torch.as_tensor(views).cuda()] = torch.as_tensor(bv).cuda()
+    print("full size: back-projection of sparse slices", flush=True)
+    atb = plan.backproject(b)
+    del b
+    vox = rng.integers(0, N, (48, 3))
+    got = _at(atb, vox)
+    h = ofirm.ctf_weights(N, len(views), inp.ctf_group[views], inp.ctf_table)
+    g = ofirm.recentre(bv.astype(np.complex128), N, inp.shifts[views])
+    ref = ofirm.back_project_at(vox - N // 2, g, N, inp.rotations[views], h).real
+    print(f"A*b: rel L2 {rel(got, ref):.2e}", flush=True)
+    assert rel(got, ref) < TOL
