@@ -106,6 +106,19 @@ def counter_workload(args, firm, synth, torch):
           flush=True)
 
 
+def spread_workload(args, firm, synth, torch):
+    """One kernel precompute and one back-projection of the workload's slices (for counter
+    runs on the two gridding kernels)."""
+    inp = synth.make_inputs(args.workload)
+    wl = inp.workload
+    plan = firm.Plan(wl.N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table)
+    b = plan.synth_slices(inp.centers, inp.sigmas, inp.amps, snr=wl.snr, seed=wl.index + 1)
+    plan.kernel_precompute()
+    plan.backproject(b)
+    torch.cuda.synchronize()
+    print(json.dumps({"spread_workload": f"{args.workload}: N={wl.N} M={inp.rotations.shape[0]}"}), flush=True)
+
+
 COPY_BYTES = 256 * 1024 * 1024
 
 
@@ -120,9 +133,10 @@ def main():
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--apply-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["all", "apply"], default="all",
+    ap.add_argument("--only", choices=["all", "apply", "spread"], default="all",
                     help="apply: only the N^3 products on a random even kernel plus a 256 MiB device copy "
-                         "(the workload of the hardware-counter runs and their calibration)")
+                         "(the workload of the hardware-counter runs and their calibration); spread: one "
+                         "kernel precompute and one back-projection (counter runs on the gridding)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (--gpus {args.gpus} requested); the multi-GPU layout is a "
@@ -137,6 +151,9 @@ def main():
     torch.cuda.set_device(0)
     if args.only == "apply":
         counter_workload(args, firm, synth, torch)
+        return
+    if args.only == "spread":
+        spread_workload(args, firm, synth, torch)
         return
     inp = synth.make_inputs(args.workload)
     wl = inp.workload
