@@ -192,8 +192,10 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
     int* flags = p->flags;
     const int nb_apply = fft_apply_cg_partials(p);     // partials of <p, q> per product
     const int nb_step = fft_apply_cg_step_partials(p);  // partials of ||r||^2 per CG step
-    if (nb_apply <= 0 || nb_apply > p->npart || nb_step <= 0 || nb_step > p->npart) CK(hipErrorInvalidValue);
-    const int nb_prec = ceil_div((int64_t)N * N / 2, N >= 1024 ? 8 : (N >= 128 ? 16 : 2048 / N));
+    const int nb_prec = fft_precond_partials(p);        // partials of <r, z> per preconditioner step
+    if (nb_apply <= 0 || nb_apply > p->npart || nb_step <= 0 || nb_step > p->npart || nb_prec <= 0 ||
+        nb_prec > p->npart)
+        CK(hipErrorInvalidValue);
     bool pc = (d != nullptr);
     int refinements = 0, fell_back = 0;
 

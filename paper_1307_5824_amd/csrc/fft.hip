@@ -453,9 +453,9 @@ __global__ void __launch_bounds__(256) k_khat_encode16(const float* __restrict__
 // inverse transform, keep the first n_in.
 // K16: the spectrum is the 16-bit form of the option khat_bf16 (BF16 codes b, value
 // mu(shell) + sc(shell) b with the per-shell pairs in shtab, or b itself when shtab is null).
-// DOT (the product's half spectrum, columns q3 in [0, L/2]): also a block partial of
+// DOT (a half spectrum, columns q3 in [0, ncols - 1]): also a block partial of
 // <x, y> = sum over the full spectrum of (K^ + kadd) |X^|^2 (Parseval, unnormalised transforms),
-// the columns q3 = 0 and q3 = L/2 once and the others twice (X^(-q) = conj X^(q)).
+// the first and last columns once and the others twice (X^(-q) = conj X^(q)).
 template <int L, class S, bool HALF, bool K16, bool DOT>
 __global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
 k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, const float2* __restrict__ shtab,
@@ -638,7 +638,6 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
     bool k16 = false;
     if constexpr (sizeof(S) == 4) k16 = spec16 != nullptr;
     const bool half = 2 * n_in == L, dot = dotp != nullptr;
-    if (dot && !half) return hipErrorInvalidValue;  // the dot is formed for the product only
 #define FIRM_MID(H, K, D)                                                                                      \
     hipLaunchKernelGGL((k_mid<L, S, H, K, D>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd, \
                        nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active, dotp)
@@ -648,14 +647,16 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
                 if (dot) FIRM_MID(true, true, true);
                 else FIRM_MID(true, true, false);
             } else {
-                FIRM_MID(false, true, false);
+                if (dot) FIRM_MID(false, true, true);
+                else FIRM_MID(false, true, false);
             }
         }
     } else if (half) {
         if (dot) FIRM_MID(true, false, true);
         else FIRM_MID(true, false, false);
     } else {
-        FIRM_MID(false, false, false);
+        if (dot) FIRM_MID(false, false, true);
+        else FIRM_MID(false, false, false);
     }
 #undef FIRM_MID
     return hipGetLastError();
@@ -820,13 +821,14 @@ hipError_t precond_passes(firm_plan p, const float* dhalf, const float* r, float
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->S1, p->S1, N, H, (int64_t)N * QPn, 1, QPn,
                                                           (int64_t)N * QPn, 1, QPn, N, N, -1.f, p->tw, EpiArgs(),
                                                           active)));
-    RET_IF((launch_mid<L>(st, p->S1, dhalf, N, H, QPn, (int64_t)N * QPn, N, p->tw, active)));
+    // partials: <r, z> = sum of dhalf |R^|^2 over the spectrum (Parseval, unnormalised
+    // transforms), fft_precond_partials(p) block partials from the middle pass
+    RET_IF((launch_mid<L>(st, p->S1, dhalf, N, H, QPn, (int64_t)N * QPn, N, p->tw, active, -1, 0.f, nullptr,
+                          nullptr, partials)));
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->S1, p->S1, N, H, (int64_t)N * QPn, 1, QPn,
                                                           (int64_t)N * QPn, 1, QPn, N, N, 1.f, p->tw, EpiArgs(),
                                                           active)));
-    if (partials)  // z and the block partials of <r, z>
-        return launch_c2r<L, true, float>(st, p->S1, N * N, QPn, z, N, N, 1.f, 1.f, 0.f, r, p->tw, partials, active);
-    return launch_c2r<L, false, float>(st, p->S1, N * N, QPn, z, N, N, 1.f, 1.f, 0.f, nullptr, p->tw);
+    return launch_c2r<L, false, float>(st, p->S1, N * N, QPn, z, N, N, 1.f, 1.f, 0.f, nullptr, p->tw, nullptr, active);
 }
 
 template <int L>
@@ -915,6 +917,16 @@ int c2r_blocks_t(int N) { return ceil_div(N * N / 2, FftCfg<L, float2>::C); }
 
 int fft_apply_cg_step_partials(firm_plan p) {
     DISPATCH_L(2 * p->N, c2r_blocks_t, p->N);
+    return 0;
+}
+
+namespace {
+template <int L>
+int precond_mid_blocks_t() { return tail_packed_blocks<FftCfg<L, float2>::C>(L, L / 2 + 1); }
+}  // namespace
+
+int fft_precond_partials(firm_plan p) {
+    DISPATCH_L(p->N, precond_mid_blocks_t);
     return 0;
 }
 

@@ -114,8 +114,10 @@ hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2,
                         const double* k0term);
 hipError_t fft_project_grid(firm_plan p, const float* u, float2* t1, float2* w, float2* X);  // L x L x QP
 hipError_t fft_images_r2c(firm_plan p, const float* img, int G, float2* out);  // G x N x QPn half spectra
+// z = IFFT_N(dhalf . FFT_N(r)); partials: also fft_precond_partials(p) block partials of <r, z>
 hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z, const int* active = nullptr,
                        double* partials = nullptr);
+int fft_precond_partials(firm_plan p);
 hipError_t fft_apply_AtA64(firm_plan p, const double* x, double* y, double lam);
 hipError_t fft_khat64_from_kerc64(firm_plan p, const double* kerc64, double2* w1);
 // fused CG variants of the apply passes (cg.hip drives them)
