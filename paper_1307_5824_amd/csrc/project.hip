@@ -187,8 +187,10 @@ __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __
     a.b[(int64_t)m * a.P + (a.P - 1 - idx)] = make_float2(v.x, -v.y);
 }
 
+// Four waves per SIMD (two 512-thread workgroups per CU) up to W = 7; the W = 8 gather needs
+// more than 128 registers and runs at two.
 template <int T, int W, int NTH>
-__global__ void __launch_bounds__(NTH, 4) k_project(ProjArgs a) {
+__global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
     constexpr int PT = T + W;                  // padded tile edge (window starts in [0, T])
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;

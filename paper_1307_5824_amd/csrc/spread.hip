@@ -117,8 +117,9 @@ __device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, do
     return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
 }
 
+// Two workgroups per CU, except the W = 8 complex tile (85 KB of LDS), which fits one.
 template <int T, int W, bool CPLX, int NTH>
-__global__ void __launch_bounds__(NTH, NTH / 128) k_spread(SpreadArgs a) {
+__global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128)) k_spread(SpreadArgs a) {
     constexpr int SP_THREADS = NTH, SP_WAVES = NTH / 64;
     constexpr int PT = T + W;
     constexpr int PADLO = (W + 1) / 2 - 1;
