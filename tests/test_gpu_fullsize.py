@@ -8,6 +8,14 @@ times) on sampled outputs the oracle computes one by one.
 * A*b (eq. backprojection) for slices that are zero except 120 entries in 40 views (the
   origin of one view included): the sum over views reduces to those 40, so the oracle's
   direct sum over them gives A*b exactly, while the GPU runs the full 10^5-view launch.
+* The forward projection (eq. forward-projector, with CTF and shift phase) of a white-noise
+  volume over all 10^5 views (5.1e9 slice values), at 48 sampled (view, point) entries
+  (the first and last views and the slice origin among them) against the oracle's direct
+  sum at those points.
+* CG and T. Chan PCG on (A*A + lam) x = b with the bench's solver settings (lam = 1e-2 Ker(0),
+  tol 1e-5, FP64 true residuals): both converge, and their solutions agree within the bound
+  the residuals give, ||x1 - x2|| <= (||r1|| + ||r2||) / lam, since A*A is positive
+  semidefinite (a property that holds at any size; the product itself is pinned above).
 Tolerances: relative L2 over the samples 1e-5 (as at small sizes); every sampled kernel value
 within 1e-5 Ker(0): a (4N)^3 grid cell sums about 820 window contributions at this size, so
 its FP32 rounding is about sqrt(820) 2^-24 = 1.7e-6 of the largest values; and each value
@@ -112,3 +120,47 @@ def test_backproject_at_full_size_sampled(firm, large):
     ref = ofirm.back_project_at(vox - N // 2, g, N, inp.rotations[views], h).real
     print(f"A*b: rel L2 {rel(got, ref):.2e}", flush=True)
     assert rel(got, ref) < TOL
+
+
+def test_forward_project_at_full_size_sampled(firm, large):
+    inp, plan = large
+    M, P = plan.M, plan.P
+    rng = np.random.default_rng(257)
+    V = rng.standard_normal((N, N, N)).astype(np.float32)
+    print("full size: forward projection over every view", flush=True)
+    bt = plan.forward_project(torch.as_tensor(V).cuda())
+    ms = rng.integers(0, M, 48)
+    ks = rng.integers(0, P, 48)
+    ms[:3] = [0, M - 1, int(rng.integers(0, M))]
+    ks[2] = (P - 1) // 2  # the slice origin
+    got = bt[torch.as_tensor(ms).cuda(), torch.as_tensor(ks).cuda()]
+    torch.cuda.synchronize()
+    got = got.cpu().numpy().astype(np.complex128)
+    del bt
+    xi = np.stack([ofirm.sample_points(N, inp.rotations[m:m + 1])[0, k] for m, k in zip(ms, ks)])
+    h = np.array([ofirm.ctf_weights(N, 1, inp.ctf_group[m:m + 1], inp.ctf_table)[0, k] for m, k in zip(ms, ks)])
+    ph = np.array([ofirm.shift_phase(N, inp.shifts[m:m + 1])[0, k] for m, k in zip(ms, ks)])
+    ref = ofirm.forward_project_at(V.astype(np.float64), xi, chunk=4) * h * np.conj(ph)
+    print(f"forward projection: rel L2 {rel(got, ref):.2e}", flush=True)
+    assert rel(got, ref) < TOL
+
+
+def test_cg_and_chan_pcg_at_full_size(firm, large):
+    inp, plan = large
+    lam, tol = inp.workload.lam, 1e-5
+    g = torch.Generator(device="cuda").manual_seed(258)
+    b = torch.randn((N, N, N), device="cuda", generator=g)
+    print("full size: CG and Chan PCG", flush=True)
+    x1, r1 = plan.cg_solve(b, lam, tol, 3000)
+    d = torch.reciprocal(plan.chan_spectrum(lam))
+    x2, r2 = plan.cg_solve(b, lam, tol, 3000, precond=d)
+    print(f"  CG {r1['iters']} iterations, true rel res {r1['true_rel_res']:.2e}; "
+          f"Chan PCG {r2['iters']} iterations, {r2['true_rel_res']:.2e}", flush=True)
+    for r in (r1, r2):
+        assert r["status"] == 0 and r["true_rel_res"] <= tol * (1 + 1e-6)
+    ker0 = float(plan.kernel_get()[N, N, N])
+    nb = torch.linalg.norm(b.double()).item()
+    dx = torch.linalg.norm(x1.double() - x2.double()).item()
+    bound = (r1["true_rel_res"] + r2["true_rel_res"]) * nb / (lam * ker0)
+    print(f"  ||x1 - x2|| {dx:.3e}, bound {bound:.3e}, ||x1|| {torch.linalg.norm(x1.double()).item():.3e}", flush=True)
+    assert dx <= bound
