@@ -20,11 +20,10 @@ template <> struct VecOf<double> { using V = double2; };
 // Twiddle table copy to LDS in two halves: fetch() loads the thread's share into registers as
 // the kernel's first global load, store() writes it to LDS after the kernel has issued its data
 // loads, so that the table's L2 latency overlaps the loads from HBM instead of preceding them
-// (a copy loop waits for its load before it can store).  Used by the row R2C and column passes
-// (2.2, 1.0 and 1.7 us faster per pass at N = 256).  The middle and row C2R passes keep the
-// copy loop: their data loads are conditional, so the wait before the LDS store also covers
-// them, the store and barrier then follow the data instead of hiding under it, and they ran
-// about 1 us slower.
+// (a copy loop waits for its load before it can store).  The data loads between the two halves
+// must carry no condition: the wait before the store counts outstanding loads, and across a
+// conditional load the compiler can only wait for the data as well, which puts the store and
+// barrier after the data instead of under it.
 template <int NT, class V>
 struct TwCopy {
     static constexpr int R = (FIRM_TWN + NT - 1) / NT;
@@ -229,27 +228,28 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
     __shared__ V lds[P::LDS];  // exchange buffer; after the transform, the DOT reduction's scratch
     __shared__ V twl[TWL ? FIRM_TWN : 1];
     if (cg_inactive(active)) return;
-    if (TWL)
-        for (int i = threadIdx.x; i < FIRM_TWN; i += NT) twl[i] = tw[i];
+    TwCopy<NT, V> twc;
+    if constexpr (TWL) twc.fetch(tw);
     const V* twp = TWL ? twl : tw;
     const int c = P::c(), j = P::j();
     const int pr = blockIdx.x * C + c;
     const bool valid = pr < (nrows >> 1);
+    const int prl = valid ? pr : (nrows >> 1) - 1;  // a pencil that does not exist loads the last one
     V v[8];
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
-        V z = mkv<V>(0, 0);
-        if (valid) {
-            const int m = e <= L / 2 ? e : L - e;
-            const V Ya = src[(int64_t)(2 * pr) * in_pitch + m];
-            const V Yb = src[(int64_t)(2 * pr + 1) * in_pitch + m];
-            z = e <= L / 2 ? mkv<V>(Ya.x - Yb.y, Ya.y + Yb.x)     // Ya + i Yb
-                           : mkv<V>(Ya.x + Yb.y, Yb.x - Ya.y);    // conj Ya + i conj Yb
-        }
-        v[t] = z;
+        const int m = e <= L / 2 ? e : L - e;
+        const V Ya = src[(int64_t)(2 * prl) * in_pitch + m];
+        const V Yb = src[(int64_t)(2 * prl + 1) * in_pitch + m];
+        const V z = e <= L / 2 ? mkv<V>(Ya.x - Yb.y, Ya.y + Yb.x)     // Ya + i Yb
+                               : mkv<V>(Ya.x + Yb.y, Yb.x - Ya.y);    // conj Ya + i conj Yb
+        v[t] = valid ? z : mkv<V>(0, 0);
     }
-    if (TWL) __syncthreads();  // the twiddle table is in place
+    if constexpr (TWL) {
+        twc.store(twl);
+        __syncthreads();  // the twiddle table is in place
+    }
     fft_reg<L, C, true>(v, lds, twp, sg);
     double acc = 0.0;
     double alpha = 0.0;
@@ -507,8 +507,15 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
     __shared__ V twl[TWL ? FIRM_TWN : 1];
     __shared__ double red[DOT ? P::NT / 64 : 1];
     if (cg_inactive(active)) return;
-    if (TWL)
+    // ULD: HALF with a 32-bit spectrum loads its data without a condition, so the FP32 table
+    // copy can be split around the loads (the 16-bit form keeps both: its shell-table lookups
+    // are conditional, and the branch-free loads cost it the registers of its second workgroup)
+    constexpr bool ULD = HALF && !K16;
+    constexpr bool TWS = TWL && ULD;
+    if (TWL && !TWS)
         for (int i = threadIdx.x; i < FIRM_TWN; i += P::NT) twl[i] = tw[i];
+    TwCopy<P::NT, V> twc;
+    if constexpr (TWS) twc.fetch(tw);
     const V* twp = TWL ? twl : tw;
     const int nin = HALF ? L / 2 : n_in;
     const int ng = (ncols + C - 1) / C;  // column groups of the data and spectrum layouts
@@ -523,8 +530,16 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
         const int e = j + t * T;
-        if (HALF && t >= 4) v[t] = mkv<V>(0, 0);  // e >= L / 2
-        else v[t] = (valid && e < nin) ? ld_nt(d0 + e * s_elem) : mkv<V>(0, 0);
+        if (HALF && t >= 4) {
+            v[t] = mkv<V>(0, 0);  // e >= L / 2
+        } else if (ULD) {
+            // e < L / 2 = nin, and a pencil that does not exist has the address of one that
+            // does (tail_packed_pencil), so the load needs no branch
+            const V w = ld_nt(d0 + e * s_elem);
+            v[t] = valid ? w : mkv<V>(0, 0);
+        } else {
+            v[t] = (valid && e < nin) ? ld_nt(d0 + e * s_elem) : mkv<V>(0, 0);
+        }
     }
     // the spectrum values are loaded before the forward transform, which hides their latency
     S kv[8];
@@ -548,6 +563,7 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
             for (int t = 0; t < 8; ++t) kv[t] = (S)__uint_as_float((uint32_t)raw[t] << 16);
         }
     }
+    if constexpr (TWS) twc.store(twl);
     if (TWL) __syncthreads();  // the twiddle table is in place
     fft_reg<L, C, false>(v, lds, twp, (S)-1);
     // the thread's 8 terms in FP32 (as the product itself), the block sum in FP64
@@ -610,6 +626,7 @@ hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows
                       int n_out, S sg, S scale, S lam, const S* xadd, const typename VecOf<S>::V* tw,
                       double* partials = nullptr, const int* active = nullptr) {
     using Cfg = FftCfg<L, typename VecOf<S>::V>;
+    if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_out == L)
         hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
@@ -625,6 +642,7 @@ template <int L>
 hipError_t launch_c2r_step(hipStream_t st, const float2* src, int nrows, int in_pitch, int out_pitch, const float2* tw,
                            double* partials, const int* active, CgStep step) {
     using Cfg = FftCfg<L, float2>;
+    if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     hipLaunchKernelGGL((k_rows_c2r<L, false, float, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
                        in_pitch, (float*)nullptr, out_pitch, L / 2, 1.f, 1.f, 0.f, (const float*)nullptr, tw, partials,
