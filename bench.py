@@ -282,6 +282,45 @@ def main():
     del y32
     print(f"16-bit spectrum: {k16}", file=sys.stderr, flush=True)
 
+    # the learned preconditioner at the size it was trained at: held-out sets of the N = 64
+    # training recipe (the weights were fitted on sets 0 .. 1999), a random right-hand side,
+    # the same tolerance; learned PCG includes the inference, Chan PCG its spectrum
+    held0, nheld = 2000, 5
+    lam64 = synth.WORKLOADS["train"].lam
+    g64 = torch.Generator(device="cuda").manual_seed(64)
+    t64 = {"cg": [], "learned_pcg": [], "chan_pcg": []}
+    it64 = {k: [] for k in t64}
+    st64 = 0
+    for s in range(-1, nheld):   # s = -1: one untimed round (first launches at this size)
+        feat, _, _, p64 = train_precond.make_set(firm, synth, held0 + max(s, 0), lam64, keep_plan=True)
+        rhs = torch.randn((p64.N,) * 3, device="cuda", generator=g64)
+        e = [ev() for _ in range(4)]
+        e[0].record()
+        _, r_cg = p64.cg_solve(rhs, lam64, args.tol, args.max_iter)
+        e[1].record()
+        d64 = p64.precond_from_output(net.forward(feat[None]))
+        _, r_l = p64.cg_solve(rhs, lam64, args.tol, args.max_iter, precond=d64)
+        e[2].record()
+        _, r_c = p64.cg_solve(rhs, lam64, args.tol, args.max_iter,
+                              precond=torch.reciprocal(p64.chan_spectrum(lam64)))
+        e[3].record()
+        torch.cuda.synchronize()
+        p64.close()
+        if s < 0:
+            continue
+        for i, (k, r) in enumerate((("cg", r_cg), ("learned_pcg", r_l), ("chan_pcg", r_c))):
+            t64[k].append(e[i].elapsed_time(e[i + 1]) / 1e3)
+            it64[k].append(r["iters"])
+            st64 = max(st64, r["status"])
+    training_size = {
+        "workload": f"train recipe: N=64, M=10000, held-out sets {held0}-{held0 + nheld - 1}, "
+                    f"lambda={lam64:g} x Ker(0), random right-hand side",
+        **{k: round(float(np.mean(v)), 5) for k, v in t64.items()},
+        "iters": {k: round(float(np.mean(v)), 1) for k, v in it64.items()},
+        "speedup_learned_vs_cg": round(float(np.mean(t64["cg"]) / np.mean(t64["learned_pcg"])), 3),
+        "status": int(st64)}
+    print(f"training size: {training_size}", file=sys.stderr, flush=True)
+
     # roofline of the dominant pass of the product, timed live with HIP events on the plan stream
     plan.apply_AtA_timed(x_probe, wl.lam, 20)   # untimed: the first block after other work runs slower
     pass_ms = plan.apply_AtA_timed(x_probe, wl.lam, 50)
@@ -326,7 +365,8 @@ def main():
             "true_rel_res": {"cg": float(np.max([r[0]["true_rel_res"] for r in reps])),
                              "learned_pcg": float(np.max([r[1]["true_rel_res"] for r in reps])),
                              "chan_pcg": rep_c["true_rel_res"]},
-            "status": int(max(max(r[0]["status"], r[1]["status"]) for r in reps) or rep_c["status"])},
+            "status": int(max(max(r[0]["status"], r[1]["status"]) for r in reps) or rep_c["status"]),
+            "at_training_size": training_size},
         "precompute_ms": round(ph[0], 2),
         "backproject_ms": round(ph[1], 2),
         "forward_project_ms": round(fwd_ms, 2),
