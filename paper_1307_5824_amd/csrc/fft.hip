@@ -292,6 +292,105 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
 }
 
 
+// The Fourier-diagonal preconditioner's outer passes for N <= 64, one workgroup per i1 slab
+// (the N x N slab and its N x (N/2 + 1) half spectrum fit LDS).  FWD: rows along i3 real to
+// half spectrum (two real rows per complex pencil, as k_rows_r2c), then columns along i2
+// forward (as k_cols), written to S1[i1][q2][q3]; !FWD: columns along q2 inverse, then rows
+// half spectrum to real (as k_rows_c2r), written to z[i1][i2][i3].  Two launches instead of
+// four: at these sizes a launch costs its few microseconds whatever it moves.
+template <int L, bool FWD>
+__global__ void __launch_bounds__(FftThr<L * 16 + 4>::value)
+k_precond_slab(const float* __restrict__ r, float2* __restrict__ S1, float* __restrict__ z, int QPn,
+               const float2* __restrict__ tw, const int* active) {
+    using V = float2;
+    constexpr int N = L, H = N / 2 + 1, C = FftCfg<L, V>::C, T = L / 8, NT = FftCfg<L, V>::THREADS;
+    static_assert(N / 2 <= C, "the row pencils of a slab are one chunk");
+    using PR = Pen<L, C, true>;   // rows: lanes along elements
+    using PC = Pen<L, C, false>;  // columns: lanes along columns
+    constexpr int XL = PR::LDS > PC::LDS ? PR::LDS : PC::LDS;
+    __shared__ V lds[XL];
+    __shared__ V sl[N * H];  // the slab's half spectrum [i2 or q2][q3]
+    __shared__ V twl[FIRM_TWN];
+    if (cg_inactive(active)) return;
+    for (int i = threadIdx.x; i < FIRM_TWN; i += NT) twl[i] = tw[i];
+    const int64_t i1 = blockIdx.x;
+    const int c = PR::c(), j = PR::j();  // row pencil c = rows (2c, 2c + 1)
+    const bool rv = c < N / 2;
+    const int cc = PC::c(), jj = PC::j();
+    V v[8];
+    if constexpr (FWD) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = j + t * T;
+            v[t] = rv ? mkv<V>(r[(i1 * N + 2 * c) * N + e], r[(i1 * N + 2 * c + 1) * N + e]) : mkv<V>(0, 0);
+        }
+        __syncthreads();  // the twiddle table is in place
+        fft_reg<L, C, true>(v, lds, twl, -1.f);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8; ++t) lds[PR::idx(j + t * T, c)] = v[t];
+        __syncthreads();
+        if (rv) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int q = j + t * T;
+                if (q < H) {
+                    const V Z = lds[PR::idx(q, c)];
+                    const V Zm = lds[PR::idx((L - q) & (L - 1), c)];
+                    const V D = mkv<V>(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));     // (Z - conj Zm)/2
+                    sl[(2 * c) * H + q] = mkv<V>(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+                    sl[(2 * c + 1) * H + q] = mkv<V>(D.y, -D.x);                        // D / i
+                }
+            }
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < H; c0 += C) {
+            const int col = c0 + cc;
+            const bool cv = col < H;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = cv ? sl[(jj + t * T) * H + col] : mkv<V>(0, 0);
+            fft_reg<L, C, false>(v, lds, twl, -1.f);
+            if (cv) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) S1[(i1 * N + jj + t * T) * QPn + col] = v[t];
+            }
+            __syncthreads();
+        }
+    } else {
+        __syncthreads();  // the twiddle table is in place
+        for (int c0 = 0; c0 < H; c0 += C) {
+            const int col = c0 + cc;
+            const bool cv = col < H;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) v[t] = cv ? S1[(i1 * N + jj + t * T) * QPn + col] : mkv<V>(0, 0);
+            fft_reg<L, C, false>(v, lds, twl, 1.f);
+            if (cv) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) sl[(jj + t * T) * H + col] = v[t];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = j + t * T;
+            const int m = e <= L / 2 ? e : L - e;
+            const V Ya = rv ? sl[(2 * c) * H + m] : mkv<V>(0, 0);
+            const V Yb = rv ? sl[(2 * c + 1) * H + m] : mkv<V>(0, 0);
+            v[t] = e <= L / 2 ? mkv<V>(Ya.x - Yb.y, Ya.y + Yb.x)     // Ya + i Yb
+                              : mkv<V>(Ya.x + Yb.y, Yb.x - Ya.y);    // conj Ya + i conj Yb
+        }
+        fft_reg<L, C, true>(v, lds, twl, 1.f);
+        if (rv) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int e = j + t * T;
+                z[(i1 * N + 2 * c) * N + e] = v[t].x;
+                z[(i1 * N + 2 * c + 1) * N + e] = v[t].y;
+            }
+        }
+    }
+}
+
 // Pencil of the middle pass over nouter rows of ncols columns, C pencils per block.  When C
 // does not divide ncols, the ncols % C columns of every row's last, partial group are packed C
 // to a block (pencils of consecutive rows), in the first blocks of the grid (started first:
@@ -872,6 +971,17 @@ hipError_t precond_passes(firm_plan p, const float* dhalf, const float* r, float
                           double* partials) {
     const int N = L, H = N / 2 + 1, QPn = p->QPn;
     hipStream_t st = p->stream;
+    if constexpr (L <= 64) {  // slab kernels around the middle pass: 3 launches instead of 5
+        constexpr int NT = FftCfg<L, float2>::THREADS;
+        hipLaunchKernelGGL((k_precond_slab<L, true>), dim3(N), dim3(NT), 0, st, r, p->S1, (float*)nullptr, QPn,
+                           p->tw, active);
+        RET_IF(hipGetLastError());
+        RET_IF((launch_mid<L>(st, p->S1, dhalf, N, H, QPn, (int64_t)N * QPn, N, p->tw, active, -1, 0.f, nullptr,
+                              nullptr, partials)));
+        hipLaunchKernelGGL((k_precond_slab<L, false>), dim3(N), dim3(NT), 0, st, (const float*)nullptr, p->S1, z,
+                           QPn, p->tw, active);
+        return hipGetLastError();
+    }
     RET_IF((launch_r2c<L, false, float>(st, r, N * N, N, N, p->S1, QPn, H, -1.f, p->tw, nullptr, nullptr, active)));
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->S1, p->S1, N, H, (int64_t)N * QPn, 1, QPn,
                                                           (int64_t)N * QPn, 1, QPn, N, N, -1.f, p->tw, EpiArgs(),

@@ -279,7 +279,7 @@ def test_cg_converges_and_true_residual(firm):
     assert abs(tr - rep["true_rel_res"]) <= 1e-6
 
 
-@pytest.mark.parametrize("N", [8, 16, 32])
+@pytest.mark.parametrize("N", [8, 16, 32, 64, 128])
 def test_precond_apply_matches_oracle(firm, N):
     """z = F^{-1}(d . F r) on the periodic N^3 grid (eq. circ1) vs the oracle with numpy FFTs."""
     rng = np.random.default_rng(60 + N)
