@@ -465,3 +465,118 @@ def test_backprojection_of_hermitian_data_is_real():
 def test_electron_wavelength_matches_paper_figure():
     """Fig. 2 of the paper quotes 2.51 pm, the relativistic wavelength at 200 kV."""
     assert abs(synth.electron_wavelength(200.0) * 100.0 - 2.51) < 0.005
+
+
+# ------------------------------------- sampled direct sums against the full arrays --
+
+@pytest.mark.parametrize("N,M", [(8, 4), (16, 3)])
+def test_kernel_at_matches_full_kernel(N, M):
+    """The sampled direct sums of eq. kernel (numpy and C) equal the full-array Ker, which is
+    itself pinned by A*(A x) = Ker * x.  Offsets cover the corners (+-(N-1)) and mixed signs."""
+    rng = _rng(30 + N)
+    R = synth.haar_rotations(M, rng)
+    table = synth.ctf_table(N, [1.2e4, 2.9e4])
+    grp = rng.integers(0, 2, M).astype(np.int32)
+    h = firm.ctf_weights(N, M, grp, table)
+    Ker = firm.kernel_direct(N, R, h)
+    offs = np.concatenate([rng.integers(-N + 1, N, size=(10, 3)),
+                           [[N - 1, -(N - 1), 1], [-(N - 1), N - 1, -(N - 1)], [0, 0, 0], [3, -2, 0]]])
+    ref = np.array([firm.kernel_value(Ker, N, o) for o in offs])
+    scale = np.sum(h * h)
+    assert np.max(np.abs(firm.kernel_at(offs, N, R, h) - ref)) <= 1e-11 * scale
+    assert np.max(np.abs(direct.kernel_at(offs, N, R, grp, table) - ref)) <= 1e-9 * scale
+
+
+@pytest.mark.parametrize("N,M", [(8, 4), (16, 3)])
+def test_back_project_at_matches_full_back_projection(N, M):
+    """The sampled direct sums of eq. backprojection (numpy and C, with CTF and re-centring of
+    shifted images) equal the full-array A*, which is pinned by the adjoint identity with A and
+    the projection-slice theorem.  Non-Hermitian data, so a sign slip in the phase shows."""
+    rng = _rng(40 + N)
+    R = synth.haar_rotations(M, rng)
+    table = synth.ctf_table(N, [1.5e4, 2.4e4])
+    grp = rng.integers(0, 2, M).astype(np.int32)
+    h = firm.ctf_weights(N, M, grp, table)
+    P = firm.slice_point_count(N)
+    b = (rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))).astype(np.complex64)
+    sh = rng.uniform(-2, 2, size=(M, 2))
+    g = firm.recentre(b.astype(np.complex128), N, sh)
+    full = firm.back_project(g, N, R, h)
+    vox = np.concatenate([rng.integers(-N // 2, N // 2, size=(10, 3)),
+                          [[-N // 2, -N // 2, -N // 2], [N // 2 - 1, N // 2 - 1, N // 2 - 1], [0, 0, 0]]])
+    ref = np.array([full[v[0] + N // 2, v[1] + N // 2, v[2] + N // 2] for v in vox])
+    scale = np.sum(np.abs(b))
+    assert np.max(np.abs(firm.back_project_at(vox, g, N, R, h) - ref)) <= 1e-11 * scale
+    assert np.max(np.abs(direct.backproject_at(vox, b, N, R, grp, table, sh) - ref)) <= 1e-9 * scale
+    # the shift enters with the re-centring sign: without it the values differ at O(1)
+    wrong = firm.back_project_at(vox, firm.recentre(b.astype(np.complex128), N, -sh), N, R, h)
+    assert np.max(np.abs(wrong - ref)) > 1e-2 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------ FSC shells (section 4) --
+
+# Plane waves cos(2 pi <j, n> / N + phase) at N = 16, each placing its power at +-j.  The shell
+# of each j is read off by hand from |j| and the shell bounds 0.5 + (i-1) <= |j| < 0.5 + i of
+# section 4 (the paper's eps = 1e-4 moves no lattice point: |j|^2 is an integer).  None: |j|
+# outside shells 1 .. N/2 - 1 (the mean, and |j| >= 7.5).
+_FSC_WAVES = [
+    # j          |j|     shell  amplitude  sign in V1
+    ((1, 0, 0), 1, 1.0, +1), ((1, 1, 0), 1, 0.5, -1),
+    ((1, 1, 1), 2, 1.0, +1), ((2, 0, 0), 2, 2.0, +1), ((2, 1, 1), 2, 1.5, -1),
+    ((2, 2, 0), 3, 1.0, -1), ((3, 0, 0), 3, 1.0, -1), ((2, 2, 2), 3, 0.7, -1),
+    ((3, 2, 1), 4, 1.0, +1), ((4, 1, 1), 4, 1.0, -1),
+    ((4, 2, 2), 5, 2.0, +1), ((4, 3, 0), 5, 1.0, +1),
+    ((6, 0, 0), 6, 1.0, -1), ((5, 3, 1), 6, 3.0, +1),
+    ((7, 0, 0), 7, 1.0, +1), ((7, 2, 0), 7, 1.0, +1), ((6, 3, 2), 7, 2.0, -1),
+    ((0, 0, 0), None, 5.0, -1), ((7, 3, 0), None, 4.0, -1), ((8, 0, 0), None, 4.0, -1),
+]
+
+
+def test_fsc_shell_membership():
+    N = 16
+    rng = _rng(18)
+    n = np.indices((N, N, N)) - N // 2
+    V1 = np.zeros((N, N, N))
+    V2 = np.zeros((N, N, N))
+    num = np.zeros(N // 2)
+    den = np.zeros(N // 2)
+    for j, shell, a, s in _FSC_WAVES:
+        wave = a * np.cos(2 * np.pi * np.tensordot(np.array(j), n, axes=1) / N + rng.uniform(0, 2 * np.pi))
+        V1 += s * wave
+        V2 += wave
+        if shell is not None:
+            num[shell] += s * a * a
+            den[shell] += a * a
+    got = firm.fsc(V1, V2)
+    assert got.shape == (N // 2 - 1,)
+    assert np.allclose(got, num[1:] / den[1:], atol=1e-12)
+
+
+# ------------------------------------------------ noise level (SNR reading) --
+
+def test_noise_sigma_closed_form():
+    """SNR = mean clean power per Fourier sample / noise power per sample."""
+    rng = _rng(19)
+    M, P = 7, 113
+    c1, c2 = 3.0, 0.5
+    mag = np.where(rng.uniform(size=(M, P)) < 0.5, c1, c2)
+    b = mag * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(M, P)))
+    snr = 0.05
+    expect = math.sqrt(np.mean(mag ** 2) / snr)
+    assert abs(firm.noise_sigma(b, snr) - expect) <= 1e-12 * expect
+    b1 = 2.0 * np.exp(1j * rng.uniform(0, 2 * np.pi, size=(M, P)))
+    assert abs(firm.noise_sigma(b1, 4.0) - 1.0) <= 1e-12
+    assert firm.noise_sigma(b, float("inf")) == 0.0
+
+
+def test_noise_at_sigma_realises_the_snr():
+    """Hermitian noise drawn at noise_sigma(b, snr) has clean/noise power ratio snr (to the
+    sampling error of 4e5 draws)."""
+    rng = _rng(20)
+    N, M = 32, 500
+    P = firm.slice_point_count(N)
+    b = (rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))) * 0.3
+    snr = 1.0 / 30.0
+    nz = firm.hermitian_noise(N, M, rng.standard_normal((M, P, 2)), firm.noise_sigma(b, snr))
+    ratio = np.mean(np.abs(b) ** 2) / np.mean(np.abs(nz) ** 2)
+    assert abs(ratio / snr - 1.0) < 0.01

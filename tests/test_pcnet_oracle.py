@@ -1,5 +1,7 @@
 """Pins of the preconditioner-network oracle: convolution by its definition written as loops,
 identity filters, adjoints, Parseval, and central finite differences for every gradient."""
+import math
+
 import numpy as np
 import pytest
 
@@ -205,3 +207,23 @@ def test_full_chain_gradients_kaporin():
         lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], *args, objective="kaporin")
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 1e-12, (layer, fd, grads[layer][0][idx])
+
+
+@pytest.mark.parametrize("N2,g", [(32, 8), (32, 16), (64, 32)])
+def test_pool_features_block_loop(N2, g):
+    """Pooled features against an explicit loop over the coarse cells: coarse centred index u
+    averages |K^| over the fine frequencies q_d in [(u_d - g/2) s, (u_d - g/2) s + s), s = 2N/g,
+    read from the FFT-order spectrum at q mod 2N."""
+    rng = np.random.default_rng(71)
+    khat = rng.standard_normal((N2, N2, N2))
+    ker0, lam = 3.7, 0.02
+    s = N2 // g
+    ref = np.empty((g, g, g))
+    idx = [np.arange((u - g // 2) * s, (u - g // 2) * s + s) % N2 for u in range(g)]
+    for u1 in range(g):
+        for u2 in range(g):
+            for u3 in range(g):
+                blk = np.abs(khat[np.ix_(idx[u1], idx[u2], idx[u3])])
+                ref[u1, u2, u3] = math.log(blk.sum() / s ** 3 / ker0 + lam)
+    got = pcnet.pool_features(khat, ker0, lam, g)
+    assert np.max(np.abs(got - ref)) <= 1e-12
