@@ -172,7 +172,8 @@ def main():
     net = firm.PCNet(max_batch=1)
     net.set_params(train_precond.load_weights())
     state = {}
-    res = firm.inference_res(N)   # the network's grid: 4^3 spectrum samples per feature, as in training
+    res = firm.inference_res(N)   # the network's grid
+    t_l = torch.empty((N, N, N), device="cuda")
 
     def step():
         e = [ev() for _ in range(7)]
@@ -183,7 +184,8 @@ def main():
         e[2].record()
         x, rep = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter)
         e[3].record()
-        d = plan.precond_from_output(net.forward(plan.kernel_features(wl.lam, res=res)[None]))
+        o = net.forward(plan.kernel_features(wl.lam, res=res)[None])[0]
+        d = plan.precond_from_output(o, plan.chan_spectrum(wl.lam, out=t_l))
         e[4].record()
         _, rep_l = plan.cg_solve(atb, wl.lam, args.tol, args.max_iter, precond=d)
         e[5].record()
@@ -193,6 +195,7 @@ def main():
         torch.cuda.synchronize()
         state["atb"] = atb
         state["x"] = x
+        state["o"] = o
         return [e[i].elapsed_time(e[i + 1]) for i in range(6)], (rep, rep_l)
 
     for i in range(args.warmup):
@@ -224,6 +227,13 @@ def main():
     e[2].record()
     torch.cuda.synchronize()
     chan_ms = [e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2])]
+    # the untrained network's form at the trained network's mean level: a constant floor under
+    # Chan's spectrum (what the network's spatial variation adds is measured against it)
+    ker0 = float(plan.kernel_get()[N, N, N].item())
+    floor = float(torch.exp(state["o"].double().mean()).item())
+    d_fl = torch.reciprocal(t_chan + floor * ker0)
+    _, rep_f = plan.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter, precond=d_fl)
+    del d_fl
 
     # the forward projector on the reconstruction, and the data residual ||A x - b|| / ||b||
     # (slice by slice in blocks, so that no second full copy of b is formed)
@@ -292,13 +302,13 @@ def main():
     it64 = {k: [] for k in t64}
     st64 = 0
     for s in range(-1, nheld):   # s = -1: one untimed round (first launches at this size)
-        feat, _, _, p64 = train_precond.make_set(firm, synth, held0 + max(s, 0), lam64, keep_plan=True)
+        feat, t64_, _, p64, _ = train_precond.make_set(firm, synth, held0 + max(s, 0), lam64, keep_plan=True)
         rhs = torch.randn((p64.N,) * 3, device="cuda", generator=g64)
         e = [ev() for _ in range(4)]
         e[0].record()
         _, r_cg = p64.cg_solve(rhs, lam64, args.tol, args.max_iter)
         e[1].record()
-        d64 = p64.precond_from_output(net.forward(feat[None]))
+        d64 = p64.precond_from_output(net.forward(feat[None])[0], p64.chan_spectrum(lam64))
         _, r_l = p64.cg_solve(rhs, lam64, args.tol, args.max_iter, precond=d64)
         e[2].record()
         _, r_c = p64.cg_solve(rhs, lam64, args.tol, args.max_iter,
@@ -359,9 +369,12 @@ def main():
             "learned_inference": round(ph[3] / 1e3, 4),
             "chan_pcg": round(sum(chan_ms) / 1e3, 4),
             "chan_spectrum": round(chan_ms[0] / 1e3, 4),
+            "const_floor_pcg": round(rep_f["t_ms"] / 1e3, 4),
+            "const_floor": round(floor, 5),
             "speedup_learned_vs_cg": round(ph[2] / (ph[3] + ph[4]), 3),
             "iters": {"cg": int(np.mean([r[0]["iters"] for r in reps])),
-                      "learned_pcg": int(np.mean([r[1]["iters"] for r in reps])), "chan_pcg": rep_c["iters"]},
+                      "learned_pcg": int(np.mean([r[1]["iters"] for r in reps])), "chan_pcg": rep_c["iters"],
+                      "const_floor_pcg": rep_f["iters"]},
             "true_rel_res": {"cg": float(np.max([r[0]["true_rel_res"] for r in reps])),
                              "learned_pcg": float(np.max([r[1]["true_rel_res"] for r in reps])),
                              "chan_pcg": rep_c["true_rel_res"]},

@@ -218,20 +218,24 @@ firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, cons
                               const double* amps, double snr, uint64_t seed, void* b_dev);
 
 /* ---- learned Fourier-diagonal preconditioner ----------------------------------------
- * A 3D conv net maps f = log(|K^| pooled to res^3 / Ker(0) + lam_rel) to a log diagonal on the
- * res^3 frequency grid: o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
+ * A 3D conv net maps f = log(|K^| pooled to res^3 / Ker(0) + lam_rel) to a log floor on the
+ * res^3 frequency grid: o = c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular
  * padding, 1 -> 32 -> 32 -> 32 -> 1 channels (c2, c3 on BF16 matrix cores, FP32 accumulation).
  * res is a power of two in [32, 256]; the network is fully convolutional, so weights trained
- * at one res apply at another (training uses res 32 at N = 64, i.e. (2N/res)^3 = 4^3 spectrum
- * samples per feature; inference at N keeps that ratio with res = N/2).
- * d = exp(U sym(o)) / Ker(0) on the N^3 grid (sym: o(u) + o(-u) halved; U: periodic trilinear
- * interpolation) is the diagonal of z = F^{-1}(d . F r).  |K^| is the unnormalised DFT_2N of the
- * circulant column (the Fourier multiplier of the embedded product).  Training objectives:
+ * at one res apply at another.
+ * The diagonal of z = F^{-1}(d . F r) is d = 1 / (t + Ker(0) exp(U sym(o))) on the N^3 grid, with
+ * t the Fourier diagonal of A*A + lambda (firm_chan_spectrum, T. Chan's circulant spectrum), sym
+ * o(u) + o(-u) halved and U periodic trilinear interpolation: the network sets a floor under the
+ * analytic spectrum (a floor of 0 is Chan's 1 / t; a network whose last layer has zero weights
+ * gives the constant floor exp(b4)).  |K^| is the unnormalised DFT_2N of the circulant column (the
+ * Fourier multiplier of the embedded product).  Objectives (firm_pcnet_loss_grad):
  *   0  probe loss E ||P (A*A + lambda) z - z||^2 / E ||z||^2, a per-frequency quadratic in d by
  *      Parseval (statistics from firm_probe_stats);
  *   1  Kaporin: log(mean(d t)) - mean(log(d t)), the log of Kaporin's condition number of
- *      P (A*A + lambda) per unknown up to a constant, with t the Fourier diagonal of
- *      A*A + lambda (firm_chan_spectrum); >= 0, zero iff d is proportional to 1 / t. */
+ *      P (A*A + lambda) per unknown up to a constant; zero iff d is proportional to 1 / t;
+ *   2  a loss whose gradient with respect to log d the caller supplies, e.g. the unrolled PCG
+ *      error of firm_pcg_unrolled (the default training objective: section 3.3's CG minimises
+ *      the energy-norm error over its Krylov space, and this loss measures what k steps leave). */
 typedef struct firm_pcnet_s* firm_pcnet;
 
 /* Number of network parameters; host parameter arrays hold w1 [32][1][27], b1 [32],
@@ -247,27 +251,46 @@ firm_status firm_pcnet_get_params(firm_pcnet net, float* params_host);
  * ... : about 1.6 GB at res 128, B 1). */
 firm_status firm_pcnet_forward(firm_pcnet net, const float* feat_dev, int res, float* out_dev, int B);
 /* Mean loss of B samples at size N (N <= 8 res) under `objective`, features [B][res^3], and (if
- * grad_host) the parameter gradients (host, NPARAM floats).  objective 0: A_dev, B_dev [B][N^3] probe statistics (centred order)
- * from firm_probe_stats and sumc host [B]; objective 1: A_dev [B][N^3] the Fourier diagonals t
- * from firm_chan_spectrum (t > 0; B_dev and sumc may be NULL).  ker0: host [B], Ker(0) of each
- * sample's kernel.  FIRM_ERR_ARG for an objective other than 0 or 1. */
+ * grad_host) the parameter gradients (host, NPARAM floats).  t_dev [B][N^3]: the Fourier
+ * diagonals t of each sample (firm_chan_spectrum, t > 0).  objective 0: A_dev, B_dev [B][N^3]
+ * probe statistics (centred order) from firm_probe_stats and sumc host [B]; objective 1: A_dev,
+ * B_dev and sumc unused (may be NULL); objective 2: A_dev [B][N^3] the gradient of the caller's
+ * loss with respect to log d, *loss set to 0 (loss may be NULL).  ker0: host [B], Ker(0) of each
+ * sample's kernel.  FIRM_ERR_ARG for another objective. */
 firm_status firm_pcnet_loss_grad(firm_pcnet net, const float* feat_dev, int res, int B, int N, int objective,
-                                 const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
-                                 double* loss, float* grad_host);
-/* One Adam step (Kingma & Ba 2015) on the mean loss of firm_pcnet_loss_grad. */
+                                 const float* t_dev, const float* A_dev, const float* B_dev, const double* sumc,
+                                 const double* ker0, double* loss, float* grad_host);
+/* One Adam step (Kingma & Ba 2015) on the mean loss of firm_pcnet_loss_grad (same arguments): step
+ * size lr for every parameter except the output bias b4 (the log of the floor's level), which
+ * steps at lr_floor (the floor is exp of the output, so the weights move it through products of
+ * many activations while b4 moves it directly). */
 firm_status firm_pcnet_train_step(firm_pcnet net, const float* feat_dev, int res, int B, int N, int objective,
-                                  const float* A_dev, const float* B_dev, const double* sumc, const double* ker0,
-                                  double lr, double* loss);
+                                  const float* t_dev, const float* A_dev, const float* B_dev, const double* sumc,
+                                  const double* ker0, double lr, double lr_floor, double* loss);
 const char* firm_pcnet_last_error(firm_pcnet net);
+
+/* Unrolled PCG objective for the preconditioner d_dev (N^3, centred frequency order, d > 0,
+ * d(q) = d(-q)): for each probe z (probes_dev [nprobes][N^3]), b = (A*A + lambda) z and x_k the
+ * k-th iterate of PCG from x0 = 0 (section 3.3, preconditioned by z = F^{-1}(d . F r));
+ * *loss (host) = mean over the probes of ||z - x_k||_T^2 / ||z||_T^2 in the energy norm of
+ * T = A*A + lambda (lambda read as by firm_apply_AtA).  grad_dev (N^3, centred; NULL: loss only) =
+ * d loss / d log d, from the recursion's adjoint with its step lengths and ratios held fixed: x_k
+ * minimises the error over its Krylov space, so that is the derivative of the minimum (the
+ * envelope theorem).  FP32 vectors, FP64 scalars.  k in [1, 1000]; uses (k + 7) N^3 floats of
+ * plan workspace (allocated on first use).  FIRM_ERR_BREAKDOWN if the loss is not finite. */
+firm_status firm_pcg_unrolled(firm_plan plan, const float* d_dev, const float* probes_dev, int nprobes, int k,
+                              double lambda, double* loss, float* grad_dev);
 
 /* Features of the plan's kernel: feat_dev [res^3] = log(mean |K^| over (2N/res)^3 blocks /
  * Ker(0) + lam_rel), centred frequency order, with K^ the unnormalised DFT_2N of the circulant
  * column ((2N)^3 times the spectrum of firm_kernel_spectrum).  res: power of two in [32, 2N]
  * (and <= 256). */
 firm_status firm_kernel_features(firm_plan plan, double lam_rel, int res, float* feat_dev);
-/* d_dev [N^3] (centred) = exp(U sym(out)) / Ker(0) from a network output out_dev [res^3]
- * (N <= 8 res). */
-firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, int res, float* d_dev);
+/* d_dev [N^3] (centred) = 1 / (t + Ker(0) exp(U sym(out))) from a network output out_dev [res^3]
+ * (N <= 8 res) and the Fourier diagonal t_dev [N^3] of A*A + lambda (firm_chan_spectrum).
+ * Allocates res^3 floats of scratch for the call and synchronises the plan stream. */
+firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, int res, const float* t_dev,
+                                     float* d_dev);
 /* Probe statistics on the centred N^3 grid for nprobes real probes z (probes_dev [nprobes][N^3]):
  * A = sum |F u|^2, B = sum Re(conj(F u) F z) with u = (A*A + lambda) z (FP32 product), and
  * *sumc = sum ||F z||^2 (host). */

@@ -7,13 +7,16 @@ is real, symmetric and positive definite.  d comes from a small network:
   features  f = log(|K^| pooled to G^3 / Ker(0) + lambda_rel)       (G = 32 by default, any power
             of two up to 2N: the network is fully convolutional; K^ = DFT_2N of the circulant
             column, unnormalised: the Fourier multiplier of the embedded product)
-  network   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))            (3^3 convolutions,
+  network   o = c4(relu(c3(relu(c2(relu(c1(f)))))))                 (3^3 convolutions,
             circular padding, channels 1 -> C -> C -> C -> 1)
   symmetric s(u) = (o(u) + o(-u)) / 2 on the centred G^3 frequency grid
-  diagonal  d(q) = exp(U s (q)) / Ker(0),  U = periodic trilinear interpolation from the
-            G^3 grid to the N^3 frequency grid (q -> coarse coordinate q G / N)
+  diagonal  d(q) = 1 / (t(q) + Ker(0) exp(U s (q))),  U = periodic trilinear interpolation from
+            the G^3 grid to the N^3 frequency grid (q -> coarse coordinate q G / N), t the Fourier
+            diagonal of A*A + lambda (T. Chan's optimal circulant spectrum).  The network learns a
+            floor mu(q) = exp(U s (q)) under the analytic spectrum: mu -> 0 is Chan's 1 / t, and
+            a network whose last layer has zero weights gives the constant floor exp(b4).
 
-Two training objectives:
+Objectives:
 
 probe loss  E_z ||P (A*A + lambda) z - z||^2 / E ||z||^2.  With u = (A*A + lambda) z and
             Parseval, for a fixed set of probes it is a per-frequency quadratic in d:
@@ -26,6 +29,10 @@ Kaporin     the log of Kaporin's condition number of P (A*A + lambda):
             T = A*A + lambda (T. Chan's optimal circulant), and det P = prod d, so
             log K / n = log(mean_q d t) - mean_q log d + const.  It is >= 0 with equality iff
             d is proportional to 1 / t, and invariant to scaling d.
+unrolled    the energy-norm error left after k steps of PCG (section 3.3: CG minimises that
+            norm over the Krylov space): for a probe z and b = T z, x_k the k-th PCG iterate
+            from x0 = 0, L = ||z - x_k||_T^2 / ||z||_T^2.  Its minimiser is not 1 / t: it
+            rewards the clustering of the preconditioned spectrum that CG's convergence rests on.
 
 Every gradient here is hand-written and pinned by central finite differences.
 """
@@ -69,18 +76,20 @@ def conv3d_backward(x, w, dy):
     return dx, dw, db
 
 
-def init_params(C=32, seed=0, zero_last=True):
-    """He-scaled random weights; the last layer starts at zero so the untrained network is the
-    analytic diagonal d = 1 / (pooled |K^| + lambda)."""
+def init_params(C=32, seed=0, zero_last=True, floor=1.0):
+    """He-scaled random weights; with zero_last the last layer's weights start at zero and its
+    bias at log(floor), so the untrained network is the constant floor: d = 1 / (t + floor Ker(0))."""
     rng = np.random.default_rng(seed)
     shapes = [(C, 1), (C, C), (C, C), (1, C)]
     params = []
     for i, (co, ci) in enumerate(shapes):
         std = np.sqrt(2.0 / (ci * 27))
         w = rng.standard_normal((co, ci, 3, 3, 3)) * std
+        b = np.zeros(co)
         if zero_last and i == 3:
             w[:] = 0.0
-        params.append((w, np.zeros(co)))
+            b[:] = np.log(floor)
+        params.append((w, b))
     return params
 
 
@@ -96,7 +105,7 @@ MFMA_LAYERS = (1, 2)
 
 
 def net_forward(f, params, emulate_bf16=False):
-    """o = -f + c4(relu(c3(relu(c2(relu(c1(f))))))); returns o and the cache for backward.
+    """o = c4(relu(c3(relu(c2(relu(c1(f))))))); returns o and the cache for backward.
     emulate_bf16 rounds the inputs and weights of the C -> C layers to bfloat16, where the
     GPU's matrix cores read them (the cache keeps the unrounded activations)."""
     x0 = f[None]
@@ -109,7 +118,7 @@ def net_forward(f, params, emulate_bf16=False):
             z = conv3d(h, w, b)
         cache.append((h, z))
         h = np.maximum(z, 0.0) if i < len(params) - 1 else z
-    return -f + h[0], cache
+    return h[0], cache
 
 
 def net_backward(do, params, cache, emulate_bf16=False):
@@ -129,7 +138,7 @@ def net_backward(do, params, cache, emulate_bf16=False):
             dx, _, _ = conv3d_backward(h, params[i][0], g)
         grads[i] = (dw, db)
         g = dx
-    return grads, g[0] - do
+    return grads, g[0]
 
 
 # ----------------------------------------------------------------- features --
@@ -201,9 +210,14 @@ def upsample_adjoint(g, N, gc=G):
     return out
 
 
-def diagonal(o, N, ker0):
-    """d on the centred N^3 grid from the raw network output o."""
-    return np.exp(upsample(symmetrise(o), N)) / ker0
+def floor_field(o, N):
+    """mu(q) = exp(U sym(o)) on the centred N^3 grid, in units of Ker(0)."""
+    return np.exp(upsample(symmetrise(o), N))
+
+
+def diagonal(o, N, ker0, t):
+    """d = 1 / (t + Ker(0) mu) on the centred N^3 grid from the raw network output o."""
+    return 1.0 / (t + ker0 * floor_field(o, N))
 
 
 # ----------------------------------------------------------------- probe loss --
@@ -247,19 +261,25 @@ def kaporin_grad_logd(d, t):
     return dt / np.sum(dt) - 1.0 / dt.size
 
 
-def loss_and_grads(f, params, N, ker0, A, B, C, emulate_bf16=False, objective="probe"):
-    """Loss of the network on one sample and the gradients of every parameter.
-    objective "probe": A, B, C are the probe statistics; "kaporin": A is the Fourier diagonal t
-    of A*A + lambda on the centred N^3 grid (B and C unused)."""
+def loss_and_grads(f, params, N, ker0, t, A=None, B=None, C=None, emulate_bf16=False, objective="probe"):
+    """Loss of the network on one sample and the gradients of every parameter.  t is the Fourier
+    diagonal of A*A + lambda on the centred N^3 grid.  objective "probe": A, B, C are the probe
+    statistics; "kaporin": no statistics; "logd": A is the gradient of some loss with respect to
+    log d (for instance unrolled_pcg_grad_logd), and the returned loss is None."""
     o, cache = net_forward(f, params, emulate_bf16)
-    d = diagonal(o, N, ker0)
+    mu = floor_field(o, N)
+    d = 1.0 / (t + ker0 * mu)
     if objective == "kaporin":
-        L = kaporin_loss(d, A)
-        gs = upsample_adjoint(kaporin_grad_logd(d, A), N, f.shape[0])
+        L = kaporin_loss(d, t)
+        glogd = kaporin_grad_logd(d, t)
+    elif objective == "logd":
+        L = None
+        glogd = A
     else:
         L = probe_loss(d, A, B, C)
-        gd = probe_loss_grad_d(d, A, B, C)
-        gs = upsample_adjoint(gd * d, N, f.shape[0])        # through exp and U
+        glogd = probe_loss_grad_d(d, A, B, C) * d
+    # log d = -log(t + Ker(0) exp(U s)): d log d / d (U s) = -Ker(0) mu d
+    gs = upsample_adjoint(glogd * (-ker0 * mu * d), N, f.shape[0])
     go = symmetrise(gs)                          # symmetrise is self-adjoint
     grads, _ = net_backward(go, params, cache, emulate_bf16)
     return L, grads, d
@@ -286,3 +306,70 @@ def unflatten_params(vec, C=32):
 def precond_apply(d, r):
     """z = F^{-1}(d . F r), d on the centred grid."""
     return np.fft.ifftn(np.fft.ifftshift(d) * np.fft.fftn(r)).real
+
+
+# ------------------------------------------------------------ unrolled PCG objective --
+
+def _pcg_steps(apply, d, b, k):
+    """k steps of PCG from x0 = 0 on apply(x) = b with P = precond_apply(d, .): the iterate x_k,
+    the residuals r_0 .. r_{k-1} and the step lengths alpha_i and ratios beta_i (section 3.3,
+    preconditioned)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    s = precond_apply(d, r)
+    p = s.copy()
+    rho = float(np.sum(r * s))
+    rs, alphas, betas = [], [], []
+    for _ in range(k):
+        rs.append(r.copy())
+        q = apply(p)
+        a = rho / float(np.sum(p * q))
+        x = x + a * p
+        r = r - a * q
+        s = precond_apply(d, r)
+        rho_new = float(np.sum(r * s))
+        bt = rho_new / rho
+        p = s + bt * p
+        rho = rho_new
+        alphas.append(a)
+        betas.append(bt)
+    return x, rs, alphas, betas
+
+
+def unrolled_pcg_loss(apply, d, z, k):
+    """||z - x_k||_T^2 / ||z||_T^2 with T = apply, b = T z and x_k the k-th PCG iterate."""
+    b = apply(z)
+    x, _, _, _ = _pcg_steps(apply, d, b, k)
+    e = z - x
+    return float(np.sum(e * apply(e)) / np.sum(z * b))
+
+
+def unrolled_pcg_grad_logd(apply, d, z, k):
+    """Loss and gradient of unrolled_pcg_loss with respect to log d(q) on the centred grid.
+
+    x_k is the minimiser of the energy-norm error over the preconditioned Krylov space; holding
+    the recursion's scalars alpha_i, beta_i fixed, x_k is a fixed polynomial combination of
+    (P T)^j P b, so by the envelope theorem the derivative of the minimum equals the derivative
+    of that combination.  Reverse pass (adjoints Pbar, Sbar, Rbar of p_i, s_i = P r_i, r_i):
+        xbar = -2 T e / ||z||_T^2,
+        Pbar_i = alpha_i xbar + beta_i Pbar_{i+1} - alpha_i T Rbar_{i+1},   Sbar_i = Pbar_i,
+        Rbar_i = Rbar_{i+1} + P Sbar_i,
+        dL/dd(q) += Re(conj(F Sbar_i)(q) (F r_i)(q)) / N^3   (P = F^{-1} diag(d) F, Parseval).
+    """
+    b = apply(z)
+    x, rs, alphas, betas = _pcg_steps(apply, d, b, k)
+    e = z - x
+    u = apply(e)
+    nz = float(np.sum(z * b))
+    L = float(np.sum(e * u) / nz)
+    xbar = -2.0 * u / nz
+    Pbar = np.zeros_like(z)
+    Rbar = np.zeros_like(z)
+    g = np.zeros(z.shape)
+    for i in range(k - 1, -1, -1):
+        beta_term = betas[i] * Pbar if i < k - 1 else 0.0
+        Pbar = alphas[i] * xbar + beta_term - alphas[i] * apply(Rbar)
+        Sbar = Pbar
+        g += np.real(np.conj(np.fft.fftn(Sbar)) * np.fft.fftn(rs[i]))
+        Rbar = Rbar + precond_apply(d, Sbar)
+    return L, np.fft.fftshift(g) / z.size * d

@@ -2,6 +2,7 @@
 
 Usage: python -m paper_1307_5824_amd.build
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -9,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfirm.so")
-SOURCES = ["api.hip", "fft.hip", "spread.hip", "cg.hip", "synth.hip", "pcnet.hip", "precond.hip", "project.hip", "images.hip"]
+SOURCES = ["api.hip", "fft.hip", "spread.hip", "cg.hip", "synth.hip", "pcnet.hip", "precond.hip", "project.hip", "images.hip", "unroll.hip"]
 ARCH = os.environ.get("FIRM_OFFLOAD_ARCH", "gfx950")
 
 
@@ -28,13 +29,20 @@ def build(verbose=False):
              "-munsafe-fp-atomics", "-Wno-unused-result"]
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
+    cmds = []
     for src in SOURCES:
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmds.append([hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj])
+        objs.append(obj)
+
+    def compile_one(cmd):
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(compile_one, c) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

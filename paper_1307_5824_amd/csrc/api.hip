@@ -145,7 +145,7 @@ void firm_plan_destroy(firm_plan p) {
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
                    p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec,
-                   p->img_ws, p->khat16, p->shtab};
+                   p->img_ws, p->khat16, p->shtab, p->uws, p->usc};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->host_scal) (void)hipHostFree(p->host_scal);
@@ -640,7 +640,10 @@ firm_status firm_probe_stats(firm_plan p, const float* probes, int nprobes, doub
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
     const int64_t N = p->N, n3 = N * N * N;
-    if (!p->S2) FIRM_HIP(p, hipMalloc((void**)&p->S2, (size_t)(N * N * p->QPn) * sizeof(float2)));
+    if (!p->S2) {
+        firm_status s = ensure_ws(p, (void**)&p->S2, &p->s2_bytes, (size_t)(N * N * p->QPn) * sizeof(float2));
+        if (s != FIRM_OK) return s;
+    }
     hipStream_t st = p->stream;
     FIRM_HIP(p, fill_zero(A, n3 * sizeof(float), st));
     FIRM_HIP(p, fill_zero(B, n3 * sizeof(float), st));
@@ -667,6 +670,26 @@ firm_status firm_chan_spectrum(firm_plan p, double lambda, float* t) {
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
     FIRM_HIP(p, chan_spectrum(p, lambda_eff(p, lambda), t));
+    return FIRM_OK;
+}
+
+firm_status firm_pcg_unrolled(firm_plan p, const float* d, const float* probes, int nprobes, int k, double lambda,
+                              double* loss, float* grad) {
+    if (!p || !d || !probes || !loss) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (nprobes < 1) return firm_fail(p, FIRM_ERR_ARG, "nprobes must be >= 1");
+    if (k < 1 || k > 1000) return firm_fail(p, FIRM_ERR_ARG, "k must be in [1, 1000]");
+    if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
+    if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    const int64_t N = p->N;
+    firm_status s = ensure_ws(p, (void**)&p->uws, &p->uws_bytes,
+                              (size_t)unrolled_workspace_floats((int)N, k) * sizeof(float));
+    if (s == FIRM_OK)
+        s = ensure_ws(p, (void**)&p->usc, &p->usc_bytes, (size_t)unrolled_scalar_count(k) * sizeof(double));
+    if (s == FIRM_OK && !p->S2)
+        s = ensure_ws(p, (void**)&p->S2, &p->s2_bytes, (size_t)(N * N * p->QPn) * sizeof(float2));
+    if (s != FIRM_OK) return s;
+    FIRM_HIP(p, pcg_unrolled(p, d, probes, nprobes, k, (float)lambda_eff(p, lambda), p->uws, p->usc, loss, grad));
+    if (!std::isfinite(*loss)) return firm_fail(p, FIRM_ERR_BREAKDOWN, "unrolled PCG: non-finite loss");
     return FIRM_OK;
 }
 

@@ -69,6 +69,7 @@ struct firm_plan_s {
     float* dhalf = nullptr;      // preconditioner diagonal / N^3, FFT order, blocked [q2][q3 group][q1][C]
     float2* S1 = nullptr;        // PCG FFT workspace [N][N][QPn]
     float2* S2 = nullptr;        // second half-spectrum workspace (probe statistics), on first use
+    size_t s2_bytes = 0;
     int QPn = 0;
 
     // gridding workspaces (allocated on first use, kept)
@@ -84,6 +85,8 @@ struct firm_plan_s {
     double* partials2 = nullptr;
     double* partials3 = nullptr;
     void* img_ws = nullptr; size_t img_ws_bytes = 0;  // image spectra workspace (Step 1), on first use
+    float* uws = nullptr; size_t uws_bytes = 0;        // unrolled-PCG vectors, on first use
+    double* usc = nullptr; size_t usc_bytes = 0;       // unrolled-PCG scalars, on first use
 };
 
 // status helpers (api.cpp)
@@ -156,6 +159,12 @@ int64_t synth_images_scratch(int N, int M);  // doubles of device scratch synth_
 // ---- synth.hip ----
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,
                         float2* b, double* power_dev);
+
+// ---- unroll.hip ----
+int64_t unrolled_workspace_floats(int N, int k);
+int unrolled_scalar_count(int k);
+hipError_t pcg_unrolled(firm_plan p, const float* d, const float* probes, int nprobes, int k, float lam, float* ws,
+                        double* sc, double* loss_host, float* grad);
 
 // ---- cg.hip ----
 firm_status cg_solve(firm_plan p, const float* atb, float* x, double lam, double tol, int max_iter,

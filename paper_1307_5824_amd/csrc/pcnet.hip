@@ -4,7 +4,9 @@
 // of z = F^{-1}(d . F r) (circulant diagonalisation, section 2.3, eq. circ1).
 //
 // Network (C channels, circular padding, cross-correlation with 3^3 filters):
-//   o = -f + c4(relu(c3(relu(c2(relu(c1(f)))))))
+//   o = c4(relu(c3(relu(c2(relu(c1(f)))))))
+// The diagonal is d = 1 / (t + Ker(0) exp(U sym(o))) with t the Fourier diagonal of A*A + lambda
+// (T. Chan's circulant spectrum): the network learns a floor under the analytic spectrum.
 // Layers c2, c3 (C -> C) are implicit GEMMs on the matrix cores: one wavefront computes a
 // 32-voxel row segment x 32 output channels tile with v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32
 // accumulation), K = 27 taps x C input channels; forward and backward-data share the kernel
@@ -126,10 +128,10 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const __bf16* __restrict__ x,
 
 // ------------------------------------------------------------------ layer 4 --
 
-// o[b][v] = -f[b][v] + b4 + sum_tap sum_ci w4[ci][tap] h3[b][v + off][ci]
-__global__ void __launch_bounds__(256) k_conv_last(const float* __restrict__ h, const float* __restrict__ f,
-                                                   const float* __restrict__ w4, const float* __restrict__ b4,
-                                                   float* __restrict__ o, int B, int g) {
+// o[b][v] = b4 + sum_tap sum_ci w4[ci][tap] h3[b][v + off][ci]
+__global__ void __launch_bounds__(256) k_conv_last(const float* __restrict__ h, const float* __restrict__ w4,
+                                                   const float* __restrict__ b4, float* __restrict__ o, int B,
+                                                   int g) {
     __shared__ float ws[CH * 27];
     for (int i = threadIdx.x; i < CH * 27; i += 256) ws[i] = w4[i];
     __syncthreads();
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(256) k_conv_last(const float* __restrict__ h, 
 #pragma unroll 8
             for (int ci = 0; ci < CH; ++ci) z = fmaf(ws[ci * 27 + t], hn[ci], z);
         }
-        o[i] = z - f[i];
+        o[i] = z;
     }
 }
 
@@ -220,17 +222,19 @@ __global__ void __launch_bounds__(256) k_wgrad_last(const float* __restrict__ go
 }
 
 // Adam on FP32 masters (Kingma & Ba 2015): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
-// p -= lr mhat / (sqrt(vhat) + eps); gradients scaled by gscale.
+// p -= lr mhat / (sqrt(vhat) + eps); gradients scaled by gscale.  The last parameter (the output
+// bias: the log of the floor's level) steps at lr_last.
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1, float c2,
-                       float gscale) {
+                       float* __restrict__ v, int n, float lr, float lr_last, float b1, float b2, float eps, float c1,
+                       float c2, float gscale) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float rate = i == n - 1 ? lr_last : lr;
         const float gi = g[i] * gscale;
         const float mi = b1 * m[i] + (1.f - b1) * gi;
         const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+        p[i] -= rate * (mi / c1) / (sqrtf(vi / c2) + eps);
     }
 }
 
@@ -272,29 +276,42 @@ __device__ __forceinline__ float upsample_at(const float* s, int i1, int i2, int
     return (x00 * (1 - tb) + x01 * tb) * (1 - ta) + (x10 * (1 - tb) + x11 * tb) * ta;
 }
 
-// d(q) = exp(U s (q)) / ker0 on the centred N^3 grid
-__global__ void k_diag_from_s(const float* __restrict__ s, float* __restrict__ d, int N, int g, float inv_ker0) {
+// floor mu = exp(U s) and diagonal d = 1 / (t + ker0 mu) at fine index (i1, i2, i3)
+__device__ __forceinline__ float floor_diag(const float* s, const float* t, int64_t i, int N, int g, float ker0,
+                                            float& mu) {
+    const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
+    mu = expf(upsample_at(s, i1, i2, i3, N, g));
+    return 1.f / (t[i] + ker0 * mu);
+}
+
+// d = 1 / (t + ker0 exp(U s)) on the centred N^3 grid
+__global__ void k_diag_from_s(const float* __restrict__ s, const float* __restrict__ t, float* __restrict__ d, int N,
+                              int g, float ker0) {
     const int64_t n = (int64_t)N * N * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        d[i] = expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0;
+        float mu;
+        d[i] = floor_diag(s, t, i, N, g, ker0, mu);
     }
 }
 
-// per sample: d = exp(U s)/ker0, loss partial sum (d^2 A - 2 d B) (+ C added on the host),
-// g(q) = (2 d A - 2 B) d / sumC  (gradient of the loss with respect to log d)
-__global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, const float* __restrict__ A,
-                                                   const float* __restrict__ Bs, float* __restrict__ gr, int N,
-                                                   int g, float inv_ker0, float inv_sumc, double* partials) {
+// Every objective's gradient with respect to log d is mapped to U s by
+// d log d / d (U s) = -ker0 mu d (log d = -log(t + ker0 exp(U s))).
+
+// probe objective: loss partial sums (d^2 A - 2 d B) (+ C added on the host) and
+// gr = dL/d(U s), with dL/dlog d = (2 d A - 2 B) d / sumC
+__global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, const float* __restrict__ t,
+                                                   const float* __restrict__ A, const float* __restrict__ Bs,
+                                                   float* __restrict__ gr, int N, int g, float ker0, float inv_sumc,
+                                                   double* partials) {
     __shared__ double red[4];
     const int64_t n = (int64_t)N * N * N;
     double acc = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const float d = expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0;
+        float mu;
+        const float d = floor_diag(s, t, i, N, g, ker0, mu);
         const float a = A[i], bb = Bs[i];
         acc += (double)d * d * a - 2.0 * (double)d * bb;
-        gr[i] = (2.f * d * a - 2.f * bb) * d * inv_sumc;
+        gr[i] = (2.f * d * a - 2.f * bb) * d * inv_sumc * (-ker0 * mu * d);
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -302,16 +319,15 @@ __global__ void __launch_bounds__(256) k_loss_grad(const float* __restrict__ s, 
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
-// Kaporin objective, pass 1: d = exp(U s) / ker0, block partials of sum d t and sum log(d t)
+// Kaporin objective, pass 1: block partials of sum d t and sum log(d t)
 __global__ void __launch_bounds__(256) k_kap_sums(const float* __restrict__ s, const float* __restrict__ t, int N,
-                                                  int g, float inv_ker0, double* partials, int nblk) {
+                                                  int g, float ker0, double* partials, int nblk) {
     __shared__ double red[8];
     const int64_t n = (int64_t)N * N * N;
     double a1 = 0.0, a2 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const float u = upsample_at(s, i1, i2, i3, N, g);
-        const double dt = (double)expf(u) * inv_ker0 * t[i];
+        float mu;
+        const double dt = (double)floor_diag(s, t, i, N, g, ker0, mu) * t[i];
         a1 += dt;
         a2 += log(dt);
     }
@@ -330,14 +346,26 @@ __global__ void __launch_bounds__(256) k_kap_sums(const float* __restrict__ s, c
     }
 }
 
-// Kaporin objective, pass 2: gradient with respect to log d, g = d t / sum(d t) - 1 / n
+// Kaporin objective, pass 2: dL/dlog d = d t / sum(d t) - 1 / n, mapped to U s
 __global__ void k_kap_grad(const float* __restrict__ s, const float* __restrict__ t, float* __restrict__ gr, int N,
-                           int g, float inv_ker0, double inv_sum, double inv_n) {
+                           int g, float ker0, double inv_sum, double inv_n) {
     const int64_t n = (int64_t)N * N * N;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int i1 = (int)(i / ((int64_t)N * N)), i2 = (int)((i / N) % N), i3 = (int)(i % N);
-        const double dt = (double)expf(upsample_at(s, i1, i2, i3, N, g)) * inv_ker0 * t[i];
-        gr[i] = (float)(dt * inv_sum - inv_n);
+        float mu;
+        const float d = floor_diag(s, t, i, N, g, ker0, mu);
+        const double dt = (double)d * t[i];
+        gr[i] = (float)(dt * inv_sum - inv_n) * (-ker0 * mu * d);
+    }
+}
+
+// a given gradient with respect to log d, mapped to U s
+__global__ void k_logd_grad(const float* __restrict__ s, const float* __restrict__ t, const float* __restrict__ gl,
+                            float* __restrict__ gr, int N, int g, float ker0) {
+    const int64_t n = (int64_t)N * N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        float mu;
+        const float d = floor_diag(s, t, i, N, g, ker0, mu);
+        gr[i] = gl[i] * (-ker0 * mu * d);
     }
 }
 
@@ -470,7 +498,7 @@ hipError_t forward(firm_pcnet n, const float* feat, int B, int g) {
                        n->w2f, n->prm + OFF_B2, nullptr, n->h2, n->h2b, B, g);
     hipLaunchKernelGGL((k_conv_mfma<true>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, n->stream, n->h2b,
                        n->w3f, n->prm + OFF_B3, nullptr, n->h3, n->h3b, B, g);
-    hipLaunchKernelGGL(k_conv_last, dim3(nblk(nv)), dim3(256), 0, n->stream, n->h3, feat, n->prm + OFF_W4,
+    hipLaunchKernelGGL(k_conv_last, dim3(nblk(nv)), dim3(256), 0, n->stream, n->h3, n->prm + OFF_W4,
                        n->prm + OFF_B4, n->o, B, g);
     return hipGetLastError();
 }
@@ -548,14 +576,17 @@ firm_status firm_pcnet_forward(firm_pcnet n, const float* feat, int res, float* 
     return FIRM_OK;
 }
 
-// Loss (mean over the batch) and parameter gradients for B samples at size N.  A and Bs are
+// Loss (mean over the batch) and parameter gradients for B samples at size N.  t, A and Bs are
 // [B][N^3] device arrays on the centred grid; sumc and ker0 are host arrays of B values.
 firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B, int N, int objective,
-                                 const float* A, const float* Bs, const double* sumc, const double* ker0,
-                                 double* loss, float* grad_host) {
-    if (objective != 0 && objective != 1) return net_fail(n, FIRM_ERR_ARG, "objective must be 0 (probe) or 1 (Kaporin)");
-    if (!n || !feat || !A || !ker0 || !loss || (objective == 0 && (!Bs || !sumc)))
-        return firm_fail(nullptr, FIRM_ERR_ARG, "null argument");
+                                 const float* t, const float* A, const float* Bs, const double* sumc,
+                                 const double* ker0, double* loss, float* grad_host) {
+    if (!n) return firm_fail(nullptr, FIRM_ERR_ARG, "null network");
+    if (objective < 0 || objective > 2)
+        return net_fail(n, FIRM_ERR_ARG, "objective must be 0 (probe), 1 (Kaporin) or 2 (given log-d gradient)");
+    if (!feat || !t || !ker0 || (objective != 2 && !loss) || (objective != 1 && !A) ||
+        (objective == 0 && (!Bs || !sumc)))
+        return net_fail(n, FIRM_ERR_ARG, "null argument");
     if (B < 1 || B > n->bmax) return net_fail(n, FIRM_ERR_ARG, "batch out of range");
     if (N < 8 || N > 256 || (N & (N - 1))) return net_fail(n, FIRM_ERR_ARG, "N must be a power of two in [8, 256]");
     if (!valid_res(res) || N > 8 * res) return net_fail(n, FIRM_ERR_ARG, "res must be a power of two in [32, 256], N <= 8 res");
@@ -580,17 +611,18 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B
     double total = 0.0;
     for (int b = 0; b < B; ++b) {
         const float* sb = n->s + (int64_t)b * GV;
+        const float* tb = t + b * n3;
+        const float k0 = (float)ker0[b];
         if (objective == 0) {
-            hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, Bs + b * n3, n->gtmp, N,
-                               g, (float)(1.0 / ker0[b]), (float)(1.0 / sumc[b]), n->part);
+            hipLaunchKernelGGL(k_loss_grad, dim3(lblocks), dim3(256), 0, st, sb, tb, A + b * n3, Bs + b * n3, n->gtmp,
+                               N, g, k0, (float)(1.0 / sumc[b]), n->part);
             NHIP(n, hipMemcpyAsync(n->hpart, n->part, lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
             NHIP(n, hipStreamSynchronize(st));
             double sp = 0.0;
             for (int i = 0; i < lblocks; ++i) sp += n->hpart[i];
             total += sp / sumc[b] + 1.0;
-        } else {
-            hipLaunchKernelGGL(k_kap_sums, dim3(lblocks), dim3(256), 0, st, sb, A + b * n3, N, g,
-                               (float)(1.0 / ker0[b]), n->part, lblocks);
+        } else if (objective == 1) {
+            hipLaunchKernelGGL(k_kap_sums, dim3(lblocks), dim3(256), 0, st, sb, tb, N, g, k0, n->part, lblocks);
             NHIP(n, hipMemcpyAsync(n->hpart, n->part, 2 * lblocks * sizeof(double), hipMemcpyDeviceToHost, st));
             NHIP(n, hipStreamSynchronize(st));
             double sdt = 0.0, slog = 0.0;
@@ -601,12 +633,14 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B
             if (!(sdt > 0) || !std::isfinite(sdt) || !std::isfinite(slog))
                 return net_fail(n, FIRM_ERR_ARG, "Kaporin objective needs t > 0 and a finite diagonal");
             total += std::log(sdt / (double)n3) - slog / (double)n3;
-            hipLaunchKernelGGL(k_kap_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, A + b * n3, n->gtmp, N, g,
-                               (float)(1.0 / ker0[b]), 1.0 / sdt, 1.0 / (double)n3);
+            hipLaunchKernelGGL(k_kap_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, tb, n->gtmp, N, g, k0, 1.0 / sdt,
+                               1.0 / (double)n3);
+        } else {
+            hipLaunchKernelGGL(k_logd_grad, dim3(nblk(n3)), dim3(256), 0, st, sb, tb, A + b * n3, n->gtmp, N, g, k0);
         }
         hipLaunchKernelGGL(k_upsample_adj, dim3(nblk(GV)), dim3(256), 0, st, n->gtmp, n->gs + (int64_t)b * GV, N, g);
     }
-    *loss = total / B;
+    if (loss) *loss = objective == 2 ? 0.0 : total / B;
     hipLaunchKernelGGL(k_symmetrise, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->gs, n->go, B, g);
     // backward
     NHIP(n, fill_zero(n->grad, NPARAM * sizeof(float), st));
@@ -636,32 +670,55 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B
 }
 
 firm_status firm_pcnet_train_step(firm_pcnet n, const float* feat, int res, int B, int N, int objective,
-                                  const float* A, const float* Bs, const double* sumc, const double* ker0, double lr,
-                                  double* loss) {
-    firm_status s = firm_pcnet_loss_grad(n, feat, res, B, N, objective, A, Bs, sumc, ker0, loss, nullptr);
+                                  const float* t, const float* A, const float* Bs, const double* sumc,
+                                  const double* ker0, double lr, double lr_floor, double* loss) {
+    if (!n) return firm_fail(nullptr, FIRM_ERR_ARG, "null network");
+    if (!(lr > 0.0) || !std::isfinite(lr) || !(lr_floor >= 0.0) || !std::isfinite(lr_floor))
+        return net_fail(n, FIRM_ERR_ARG, "lr must be finite and > 0, lr_floor finite and >= 0");
+    firm_status s = firm_pcnet_loss_grad(n, feat, res, B, N, objective, t, A, Bs, sumc, ker0, loss, nullptr);
     if (s != FIRM_OK) return s;
     n->step += 1;
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
     hipLaunchKernelGGL(k_adam, dim3(nblk(NPARAM)), dim3(256), 0, n->stream, n->prm, n->grad, n->m, n->v,
-                       (int)NPARAM, (float)lr, b1, b2, 1e-8f, c1, c2, 1.f / (float)B);
+                       (int)NPARAM, (float)lr, (float)lr_floor, b1, b2, 1e-8f, c1, c2, 1.f / (float)B);
     NHIP(n, pack(n));
     return FIRM_OK;
 }
 
-// d (centred N^3) = exp(U sym(out)) / Ker(0) of the plan's kernel, out on the res^3 grid
-firm_status firm_precond_from_output(firm_plan p, const float* out, int res, float* d) {
-    if (!p || !out || !d) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+// symmetrise the network output into s (res^3 floats) and form d on the plan's grid
+firm_status diag_from_output(firm_plan p, const float* out, int res, const float* t, float* d, float* s) {
+    const int64_t GV = (int64_t)res * res * res;
+    hipLaunchKernelGGL(k_symmetrise, dim3(nblk(GV)), dim3(256), 0, p->stream, out, s, 1, res);
+    const int64_t n3 = (int64_t)p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_diag_from_s, dim3(nblk(n3)), dim3(256), 0, p->stream, s, t, d, p->N, res, (float)p->ker0);
+    return FIRM_OK;
+}
+
+firm_status precond_args(firm_plan p, const float* out, int res, const float* t, float* d) {
+    if (!p || !out || !t || !d) return firm_fail(p, FIRM_ERR_ARG, "null argument");
     if (!valid_res(res) || p->N > 8 * res)
         return firm_fail(p, FIRM_ERR_ARG, "res must be a power of two in [32, 256], N <= 8 res");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel");
+    return FIRM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// d (centred N^3) = 1 / (t + Ker(0) exp(U sym(out))) for the plan's kernel, out on the res^3 grid
+firm_status firm_precond_from_output(firm_plan p, const float* out, int res, const float* t, float* d) {
+    firm_status st = precond_args(p, out, res, t, d);
+    if (st != FIRM_OK) return st;
     const int64_t GV = (int64_t)res * res * res;
     float* s = nullptr;
     FIRM_HIP(p, hipMalloc((void**)&s, GV * sizeof(float)));
-    hipLaunchKernelGGL(k_symmetrise, dim3(nblk(GV)), dim3(256), 0, p->stream, out, s, 1, res);
-    const int64_t n3 = (int64_t)p->N * p->N * p->N;
-    hipLaunchKernelGGL(k_diag_from_s, dim3(nblk(n3)), dim3(256), 0, p->stream, s, d, p->N, res,
-                       (float)(1.0 / p->ker0));
+    diag_from_output(p, out, res, t, d, s);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     (void)hipFree(s);

@@ -78,12 +78,13 @@ def _load():
         "firm_pcnet_set_params": (i, [vp, vp]),
         "firm_pcnet_get_params": (i, [vp, vp]),
         "firm_pcnet_forward": (i, [vp, vp, i, vp, i]),
-        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
-        "firm_pcnet_train_step": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, d, ctypes.POINTER(d)]),
+        "firm_pcnet_loss_grad": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, vp, ctypes.POINTER(d), vp]),
+        "firm_pcnet_train_step": (i, [vp, vp, i, i, i, i, vp, vp, vp, vp, vp, d, d, ctypes.POINTER(d)]),
+        "firm_pcg_unrolled": (i, [vp, vp, vp, i, i, d, ctypes.POINTER(d), vp]),
         "firm_chan_spectrum": (i, [vp, d, vp]),
         "firm_pcnet_last_error": (ctypes.c_char_p, [vp]),
         "firm_kernel_features": (i, [vp, d, i, vp]),
-        "firm_precond_from_output": (i, [vp, vp, i, vp]),
+        "firm_precond_from_output": (i, [vp, vp, i, vp, vp]),
         "firm_probe_stats": (i, [vp, vp, i, d, vp, vp, ctypes.POINTER(d)]),
         "firm_synth_normals": (i, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, vp]),
     }
@@ -327,12 +328,27 @@ def _plan_kernel_features(self, lam_rel, res=32, out=None):
     return out
 
 
-def _plan_precond_from_output(self, o, out=None):
+def _plan_precond_from_output(self, o, t, out=None):
+    """d = 1 / (t + Ker(0) exp(U sym(o))) for a network output o (res^3) and the Fourier diagonal t."""
     res = int(o.shape[-1])
     self._req(o, res ** 3, self._torch.float32)
+    self._req(t, self.N ** 3, self._torch.float32)
     out = self._vol(out)
-    _check(lib.firm_precond_from_output(self.h, _ptr(o), res, _ptr(out)), self.h)
+    _check(lib.firm_precond_from_output(self.h, _ptr(o), res, _ptr(t), _ptr(out)), self.h)
     return out
+
+
+def _plan_pcg_unrolled(self, d, probes, k, lam, with_grad=True, out=None):
+    """Mean unrolled-PCG loss over the probes and (with_grad) its gradient in log d (N^3)."""
+    t = self._torch
+    P = probes.shape[0] if probes.dim() == 4 else 1
+    self._req(probes, P * self.N ** 3, t.float32)
+    self._req(d, self.N ** 3, t.float32)
+    g = self._vol(out) if with_grad else None
+    loss = ctypes.c_double()
+    _check(lib.firm_pcg_unrolled(self.h, _ptr(d), _ptr(probes), int(P), int(k), float(lam), ctypes.byref(loss),
+                                 _ptr(g)), self.h)
+    return loss.value, g
 
 
 def _plan_probe_stats(self, probes, lam):
@@ -362,6 +378,7 @@ def _plan_synth_normals(self, seed, offset, shape):
 
 Plan.kernel_features = _plan_kernel_features
 Plan.precond_from_output = _plan_precond_from_output
+Plan.pcg_unrolled = _plan_pcg_unrolled
 Plan.probe_stats = _plan_probe_stats
 Plan.synth_normals = _plan_synth_normals
 Plan.chan_spectrum = _plan_chan_spectrum
@@ -418,30 +435,34 @@ class PCNet:
         self._chk(lib.firm_pcnet_forward(self.h, _ptr(feat), res, _ptr(out), int(B)))
         return out
 
-    OBJECTIVES = {"probe": 0, "kaporin": 1}
+    OBJECTIVES = {"probe": 0, "kaporin": 1, "logd": 2}
 
-    def loss_grad(self, feat, N, A, Bs=None, sumc=None, ker0=None, with_grad=True, objective="probe"):
-        """Mean loss over the batch and (with_grad) the parameter gradients.  objective "probe":
-        A, Bs, sumc are probe statistics; "kaporin": A holds the Fourier diagonals t."""
+    def loss_grad(self, feat, N, t, A=None, Bs=None, sumc=None, ker0=None, with_grad=True, objective="probe"):
+        """Mean loss over the batch and (with_grad) the parameter gradients.  t: the Fourier
+        diagonals [B][N^3]; objective "probe": A, Bs, sumc are probe statistics; "kaporin": no
+        statistics; "logd": A is the gradient of the caller's loss in log d (the loss reads 0)."""
         B = feat.shape[0]
         sc = None if sumc is None else np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
         g = np.zeros(PCNet.NPARAM, dtype=np.float32) if with_grad else None
         self._chk(lib.firm_pcnet_loss_grad(self.h, _ptr(feat), int(feat.shape[-1]), int(B), int(N),
-                                           self.OBJECTIVES[objective], _ptr(A),
+                                           self.OBJECTIVES[objective], _ptr(t), _ptr(A),
                                            _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
                                            k0.ctypes.data_as(ctypes.c_void_p), ctypes.byref(loss),
                                            None if g is None else g.ctypes.data_as(ctypes.c_void_p)))
         return loss.value, g
 
-    def train_step(self, feat, N, A, Bs=None, sumc=None, ker0=None, lr=1e-3, objective="probe"):
+    def train_step(self, feat, N, t, A=None, Bs=None, sumc=None, ker0=None, lr=1e-3, objective="probe",
+                   lr_floor=None):
+        """One Adam step; lr_floor (default lr) is the step of the output bias, the floor's level."""
         B = feat.shape[0]
         sc = None if sumc is None else np.ascontiguousarray(np.asarray(sumc, dtype=np.float64))
         k0 = np.ascontiguousarray(np.asarray(ker0, dtype=np.float64))
         loss = ctypes.c_double()
         self._chk(lib.firm_pcnet_train_step(self.h, _ptr(feat), int(feat.shape[-1]), int(B), int(N),
-                                            self.OBJECTIVES[objective], _ptr(A),
+                                            self.OBJECTIVES[objective], _ptr(t), _ptr(A),
                                             _ptr(Bs), None if sc is None else sc.ctypes.data_as(ctypes.c_void_p),
-                                            k0.ctypes.data_as(ctypes.c_void_p), float(lr), ctypes.byref(loss)))
+                                            k0.ctypes.data_as(ctypes.c_void_p), float(lr),
+                                            float(lr if lr_floor is None else lr_floor), ctypes.byref(loss)))
         return loss.value

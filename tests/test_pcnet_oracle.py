@@ -114,8 +114,10 @@ def test_full_chain_gradients_finite_differences():
     A = rng.uniform(0.5, 2.0, (N, N, N))
     B = rng.uniform(0.1, 0.5, (N, N, N))
     Cs = rng.uniform(0.5, 1.0, (N, N, N))
+    t = rng.uniform(0.5, 2.0, (N, N, N))
+    t = 0.5 * (t + np.roll(t[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
     ker0 = 3.0
-    L, grads, _ = pcnet.loss_and_grads(f, params, N, ker0, A, B, Cs)
+    L, grads, _ = pcnet.loss_and_grads(f, params, N, ker0, t, A, B, Cs)
     # a step of 1e-6 stays clear of the ReLU kinks (a few dozen pre-activations lie within 1e-4
     # of zero); FP64 round-off then limits the agreement to ~1e-5 relative
     h = 1e-6
@@ -123,31 +125,32 @@ def test_full_chain_gradients_finite_differences():
         w, b = params[layer]
         wp = [list(p) for p in params]
         wp[layer][0] = w.copy(); wp[layer][0][idx] += h
-        lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+        lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, t, A, B, Cs)
         wp[layer][0] = w.copy(); wp[layer][0][idx] -= h
-        lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+        lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, t, A, B, Cs)
         fd = (lp - lm) / (2 * h)
-        assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 1e-12, (layer, fd, grads[layer][0][idx])
+        # absolute floor: FP64 round-off of a loss of order 1 divided by the step
+        assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 5e-10, (layer, fd, grads[layer][0][idx])
     wp = [list(p) for p in params]
     b3 = params[3][1]
     wp[3][1] = b3 + h
-    lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+    lp, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, t, A, B, Cs)
     wp[3][1] = b3 - h
-    lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, A, B, Cs)
+    lm, _, _ = pcnet.loss_and_grads(f, [tuple(p) for p in wp], N, ker0, t, A, B, Cs)
     assert abs((lp - lm) / (2 * h) - grads[3][1][0]) <= 5e-5 * abs(grads[3][1][0]) + 1e-12
 
 
-def test_untrained_network_is_inverse_pooled_spectrum():
-    """With the last layer at zero, d = 1 / (pooled |K^| + lambda Ker(0)) up to interpolation."""
+def test_untrained_network_is_a_constant_floor():
+    """With the last layer's weights at zero and its bias log(mu), d = 1 / (t + mu Ker(0))."""
     rng = _rng(7)
     G = pcnet.G
-    params = pcnet.init_params(4, seed=2)
+    params = pcnet.init_params(4, seed=2, floor=0.25)
     f = rng.standard_normal((G, G, G))
-    f = pcnet.symmetrise(f)
     o, _ = pcnet.net_forward(f, params)
-    assert np.allclose(o, -f)
-    d = pcnet.diagonal(o, G, 2.0)
-    assert np.allclose(d, np.exp(-f) / 2.0)
+    assert np.allclose(o, np.log(0.25))
+    t = rng.uniform(0.1, 3.0, (16, 16, 16))
+    d = pcnet.diagonal(o, 16, 2.0, t)
+    assert np.allclose(d, 1.0 / (t + 0.5))
 
 
 def test_bf16_rounding():
@@ -195,7 +198,7 @@ def test_full_chain_gradients_kaporin():
     f = 0.2 * rng.standard_normal((pcnet.G,) * 3)
     t = rng.uniform(0.5, 2.0, (N, N, N))
     t = 0.5 * (t + np.roll(t[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
-    args = (N, 2.0, t, None, None)
+    args = (N, 2.0, t)
     L, grads, _ = pcnet.loss_and_grads(f, params, *args, objective="kaporin")
     h = 1e-6
     for layer, idx in [(0, (1, 0, 0, 1, 2)), (1, (0, 1, 2, 2, 0)), (2, (1, 1, 1, 1, 1)), (3, (0, 1, 0, 0, 0))]:
@@ -227,3 +230,104 @@ def test_pool_features_block_loop(N2, g):
                 ref[u1, u2, u3] = math.log(blk.sum() / s ** 3 / ker0 + lam)
     got = pcnet.pool_features(khat, ker0, lam, g)
     assert np.max(np.abs(got - ref)) <= 1e-12
+
+
+# ------------------------------------------------ unrolled PCG objective --
+
+def _toeplitz_system(N, M, seed, lam_rel=0.01):
+    rng = _rng(seed)
+    from paper_1307_5824_amd import synth
+    R = synth.haar_rotations(M, rng)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = lam_rel * Ker[N - 1, N - 1, N - 1]
+
+    def apply(v):
+        return ofirm.toeplitz_apply_fft(Ker, v).real + lam * v
+    return Ker, lam, apply, rng
+
+
+def test_unrolled_loss_is_the_krylov_energy_error():
+    """The k-step PCG iterate is the energy-norm minimiser over the preconditioned Krylov space
+    span{(P T)^j P b}: the loss equals the error of that minimiser, computed by a dense
+    least-squares solve in the T inner product (a definition independent of the recursion)."""
+    N, k = 8, 5
+    Ker, lam, apply, rng = _toeplitz_system(N, 6, 11)
+    t = ofirm.chan_circulant_spectrum(Ker, N, lam)
+    d = 1.0 / (t + 0.1 * Ker[N - 1, N - 1, N - 1])
+    z = rng.standard_normal((N, N, N))
+    b = apply(z)
+    V = [pcnet.precond_apply(d, b)]
+    for _ in range(k - 1):
+        V.append(pcnet.precond_apply(d, apply(V[-1])))
+    V = np.stack([v.reshape(-1) / np.linalg.norm(v) for v in V], axis=1)
+    TV = np.stack([apply(V[:, j].reshape(z.shape)).reshape(-1) for j in range(k)], axis=1)
+    c = np.linalg.solve(V.T @ TV, V.T @ b.reshape(-1))
+    e = z.reshape(-1) - V @ c
+    ref = float(e @ apply(e.reshape(z.shape)).reshape(-1) / np.sum(z * b))
+    got = pcnet.unrolled_pcg_loss(apply, d, z, k)
+    assert abs(got - ref) <= 1e-8 * ref
+
+
+def test_unrolled_gradient_finite_differences():
+    """The frozen-scalar reverse pass equals central differences of the loss along random even
+    directions in log d (the loss of the recursion itself, so this pins the envelope argument)."""
+    N, k = 8, 6
+    Ker, lam, apply, rng = _toeplitz_system(N, 5, 12)
+    t = ofirm.chan_circulant_spectrum(Ker, N, lam)
+    d = 1.0 / (t + 0.2 * Ker[N - 1, N - 1, N - 1])
+    z = rng.standard_normal((N, N, N))
+    L, g = pcnet.unrolled_pcg_grad_logd(apply, d, z, k)
+    assert abs(L - pcnet.unrolled_pcg_loss(apply, d, z, k)) <= 1e-12 * L
+    # P is invariant to scaling d, so the gradient in log d sums to zero
+    assert abs(g.sum()) <= 1e-6 * np.abs(g).sum()
+    h = 1e-5
+    for _ in range(3):
+        v = rng.standard_normal(d.shape)
+        v = 0.5 * (v + np.roll(v[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+        fd = (pcnet.unrolled_pcg_loss(apply, d * np.exp(h * v), z, k)
+              - pcnet.unrolled_pcg_loss(apply, d * np.exp(-h * v), z, k)) / (2 * h)
+        assert abs(fd - np.sum(g * v)) <= 2e-3 * abs(fd), (fd, np.sum(g * v))
+
+
+def test_unrolled_loss_one_step_with_exact_inverse():
+    """On a circulant operator with d its inverse spectrum, one PCG step is exact: loss 0 and zero
+    gradient."""
+    N = 8
+    rng = _rng(13)
+    s = rng.uniform(0.5, 3.0, (N, N, N))
+    s = 0.5 * (s + np.roll(s[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+
+    def apply(v):
+        return pcnet.precond_apply(s, v)
+    z = rng.standard_normal((N, N, N))
+    L, g = pcnet.unrolled_pcg_grad_logd(apply, 1.0 / s, z, 1)
+    assert L <= 1e-24 and np.max(np.abs(g)) <= 1e-12
+
+
+def test_full_chain_gradients_given_logd():
+    """Network, symmetrisation, upsampling and the floor under a loss whose log-d gradient is
+    given: the chain equals central differences of sum(G log d) in the parameters."""
+    rng = _rng(14)
+    N, C = 8, 2
+    params = pcnet.init_params(C, seed=4, zero_last=False)
+    params = [(w * 0.3, b + 0.01 * rng.standard_normal(b.shape)) for w, b in params]
+    f = 0.2 * rng.standard_normal((pcnet.G,) * 3)
+    t = rng.uniform(0.5, 2.0, (N, N, N))
+    t = 0.5 * (t + np.roll(t[::-1, ::-1, ::-1], 1, axis=(0, 1, 2)))
+    Gl = rng.standard_normal((N, N, N))
+    ker0 = 2.0
+
+    def lin(ps):
+        o, _ = pcnet.net_forward(f, ps)
+        return float(np.sum(Gl * np.log(pcnet.diagonal(o, N, ker0, t))))
+    _, grads, _ = pcnet.loss_and_grads(f, params, N, ker0, t, Gl, objective="logd")
+    h = 1e-6
+    for layer, idx in [(0, (1, 0, 0, 1, 2)), (2, (1, 1, 1, 1, 1)), (3, (0, 1, 0, 0, 0))]:
+        w = params[layer][0]
+        wp = [list(p) for p in params]
+        wp[layer][0] = w.copy(); wp[layer][0][idx] += h
+        lp = lin([tuple(p) for p in wp])
+        wp[layer][0] = w.copy(); wp[layer][0][idx] -= h
+        lm = lin([tuple(p) for p in wp])
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grads[layer][0][idx]) <= 5e-5 * abs(fd) + 1e-12, (layer, fd, grads[layer][0][idx])
