@@ -291,6 +291,16 @@ firm_status firm_kernel_features(firm_plan plan, double lam_rel, int res, float*
  * Allocates res^3 floats of scratch for the call and synchronises the plan stream. */
 firm_status firm_precond_from_output(firm_plan plan, const float* out_dev, int res, const float* t_dev,
                                      float* d_dev);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): firm_precond_from_output with its res^3 scratch (the
+ * symmetrised network output) in a static device array of 128^3 floats (8 MiB on every GPU the
+ * library runs on, held until the process ends) instead of a per-call allocation.  res <= 128
+ * (FIRM_ERR_ARG beyond, checked before any device work); other arguments as firm_precond_from_output.
+ * Enqueued on the plan stream; returns without synchronising.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other streams, other threads) race, calls in order
+ * on one stream do not.  Nothing needs clearing: each call writes the entries it reads. */
+firm_status firm_precond_from_output_noalloc(firm_plan plan, const float* out_dev, int res, const float* t_dev,
+                                             float* d_dev);
 /* Probe statistics on the centred N^3 grid for nprobes real probes z (probes_dev [nprobes][N^3]):
  * A = sum |F u|^2, B = sum Re(conj(F u) F z) with u = (A*A + lambda) z (FP32 product), and
  * *sumc = sum ||F z||^2 (host). */

@@ -317,6 +317,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     up(p->rowstart, rowstart.data(), rowstart.size() * sizeof(int));
     up(p->tiles_ker, wk.data(), wk.size() * sizeof(int));
     up(p->tiles_atb, wa.data(), wa.size() * sizeof(int));
+    if (e == hipSuccess) e = noalloc_scratch_setup();
     if (e != hipSuccess) {
         firm_plan_destroy(p);
         return firm_fail(nullptr, FIRM_ERR_HIP, std::string("plan upload: ") + hipGetErrorString(e));

@@ -160,6 +160,9 @@ int64_t synth_images_scratch(int N, int M);  // doubles of device scratch synth_
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,
                         float2* b, double* power_dev);
 
+// ---- pcnet.hip ----
+hipError_t noalloc_scratch_setup();  // device address of the no-allocation scratch, current device
+
 // ---- unroll.hip ----
 int64_t unrolled_workspace_floats(int N, int k);
 int unrolled_scalar_count(int k);

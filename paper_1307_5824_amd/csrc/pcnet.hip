@@ -15,9 +15,16 @@
 // [batch][voxel][C], stored in FP32 and as BF16 copies for the matrix cores.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "firm_internal.h"
+
+// Scratch of firm_precond_from_output_noalloc: the symmetrised network output on grids up to
+// 128^3 (8 MiB on every GPU the library runs on, held until the process ends).  In host code this
+// name is a host-side stand-in: kernels receive the device address from hipGetSymbolAddress.
+constexpr int NOALLOC_MAX_RES = 128;
+static __device__ __align__(256) float scratch[NOALLOC_MAX_RES * NOALLOC_MAX_RES * NOALLOC_MAX_RES];
 
 namespace {
 
@@ -707,7 +714,34 @@ firm_status precond_args(firm_plan p, const float* out, int res, const float* t,
     return FIRM_OK;
 }
 
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_dev[MAX_DEVICES] = {};  // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t scratch_address(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_dev[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
+
 }  // namespace
+
+// Set-up of the no-allocation entry point on the current device (called by firm_plan_create).
+hipError_t noalloc_scratch_setup() {
+    float* s = nullptr;
+    return scratch_address(&s);
+}
 
 extern "C" {
 
@@ -723,6 +757,21 @@ firm_status firm_precond_from_output(firm_plan p, const float* out, int res, con
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     (void)hipFree(s);
     if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("precond_from_output: ") + hipGetErrorString(e));
+    return FIRM_OK;
+}
+
+// firm_precond_from_output with the symmetrised output in the static scratch (res <= 128): no
+// allocation, enqueued on the plan stream without synchronising.  Nothing needs clearing: the
+// symmetrisation writes every entry the diagonal kernel reads.
+firm_status firm_precond_from_output_noalloc(firm_plan p, const float* out, int res, const float* t, float* d) {
+    firm_status st = precond_args(p, out, res, t, d);
+    if (st != FIRM_OK) return st;
+    if (res > NOALLOC_MAX_RES)
+        return firm_fail(p, FIRM_ERR_ARG, "res must be <= 128: the no-allocation scratch holds 128^3 floats");
+    float* s = nullptr;
+    FIRM_HIP(p, scratch_address(&s));
+    diag_from_output(p, out, res, t, d, s);
+    FIRM_HIP(p, hipGetLastError());
     return FIRM_OK;
 }
 

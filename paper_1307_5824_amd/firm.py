@@ -85,6 +85,7 @@ def _load():
         "firm_pcnet_last_error": (ctypes.c_char_p, [vp]),
         "firm_kernel_features": (i, [vp, d, i, vp]),
         "firm_precond_from_output": (i, [vp, vp, i, vp, vp]),
+        "firm_precond_from_output_noalloc": (i, [vp, vp, i, vp, vp]),
         "firm_probe_stats": (i, [vp, vp, i, d, vp, vp, ctypes.POINTER(d)]),
         "firm_synth_normals": (i, [vp, ctypes.c_uint64, ctypes.c_uint64, i64, vp]),
     }
