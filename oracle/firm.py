@@ -242,6 +242,24 @@ def toeplitz_apply_fft(Ker, x):
     return y
 
 
+def toeplitz_operator(Ker, workers=None):
+    """x -> (Ker * x) for a real, even kernel Ker ((2N-1)^3, offsets -N+1..N-1) and real x: the
+    product of toeplitz_apply_fft (the 2N circulant embedding, eq. circ1 in three dimensions), with
+    the embedding's spectrum computed once and real-to-complex FFTs (scipy.fft on `workers` threads)
+    so that N = 256 products take seconds.  The spectrum of a real even column is real."""
+    import scipy.fft as sfft
+    Ker = np.asarray(Ker, dtype=np.float64)
+    N = (Ker.shape[0] + 1) // 2
+    lam = sfft.rfftn(circulant_first_column(Ker, N), workers=workers).real
+
+    def apply(x):
+        xp = np.zeros((2 * N,) * 3)
+        xp[:N, :N, :N] = x
+        y = sfft.irfftn(lam * sfft.rfftn(xp, workers=workers), s=xp.shape, workers=workers)
+        return y[:N, :N, :N]
+    return apply
+
+
 def toeplitz_dense(Ker, N):
     """The N^3 x N^3 matrix T[(n), (l)] = Ker(n - l) (eq. toep3)."""
     i = np.indices((N, N, N)).reshape(3, -1)

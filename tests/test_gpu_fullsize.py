@@ -164,3 +164,63 @@ def test_cg_and_chan_pcg_at_full_size(firm, large):
     bound = (r1["true_rel_res"] + r2["true_rel_res"]) * nb / (lam * ker0)
     print(f"  ||x1 - x2|| {dx:.3e}, bound {bound:.3e}, ||x1|| {torch.linalg.norm(x1.double()).item():.3e}", flush=True)
     assert dx <= bound
+
+
+def test_solves_at_full_size_against_the_fp64_oracle(firm, large):
+    """Convergence certified by the FP64 oracle rather than the library's own FP64 product.
+
+    The operator is A*A + lam with the plan's kernel (pinned against the direct sums of eq. kernel
+    at sampled offsets above), copied to the host in FP64; the oracle applies it through the 2N
+    circulant embedding with scipy's FFTs on all host cores.
+    * The FP32 solutions of plain CG, T. Chan PCG and the learned PCG at the bench's settings
+      (precision 1, tol 1e-5) have an oracle relative residual within tol (plus 1%: the oracle and
+      the library round the FP64 residual differently).
+    * The iterate x_10 of FP32 CG (precision 0) and of FP64 CG (precision 2) on the same right-hand
+      side match the oracle's FP64 CG x_10: to 1e-9 for FP64 CG, and for FP32 CG to 1e-5 (at
+      condition ~1e2, ten steps amplify FP32 rounding to well below that)."""
+    import os
+
+    from paper_1307_5824_amd import train_precond
+    inp, plan = large
+    lam_rel, tol = inp.workload.lam, 1e-5
+    g = torch.Generator(device="cuda").manual_seed(259)
+    b = torch.randn((N, N, N), device="cuda", generator=g)
+    ker = plan.kernel_get()
+    ker0 = float(ker[N, N, N])
+    Kf = ker[1:, 1:, 1:].cpu().numpy().astype(np.float64)
+    del ker
+    lam = lam_rel * ker0
+    workers = min(16, os.cpu_count() or 1)
+    T = ofirm.toeplitz_operator(Kf, workers=workers)
+    del Kf
+    bh = b.cpu().numpy().astype(np.float64)
+    nb = np.linalg.norm(bh)
+
+    def oracle_rel_res(x):
+        xh = x.cpu().numpy().astype(np.float64)
+        return float(np.linalg.norm(bh - T(xh) - lam * xh) / nb)
+    net = firm.PCNet(max_batch=1)
+    net.set_params(train_precond.load_weights())
+    t = plan.chan_spectrum(lam_rel)
+    d_learned = plan.precond_from_output(net.forward(plan.kernel_features(lam_rel, res=firm.inference_res(N))[None])[0], t)
+    for name, pc in (("cg", None), ("chan", torch.reciprocal(t)), ("learned", d_learned)):
+        print(f"full size: {name} solve and its oracle residual", flush=True)
+        x, rep = plan.cg_solve(b, lam_rel, tol, 3000, precond=pc)
+        rr = oracle_rel_res(x)
+        print(f"  {name}: {rep['iters']} iterations, library true rel res {rep['true_rel_res']:.3e}, "
+              f"oracle {rr:.3e}", flush=True)
+        assert rep["status"] == 0 and rr <= tol * 1.01
+        del x
+    del d_learned, t
+    # matched iterates
+    k = 10
+    print("full size: oracle FP64 CG, 10 iterations", flush=True)
+    x_ref = ofirm.cg(lambda v: T(v) + lam * v, bh, iters=k)
+    for prec, bound in ((0, 1e-5), (2, 1e-9)):
+        p2 = firm.Plan(N, inp.rotations[:1], precision=prec, lambda_relative=1)
+        p2.kernel_set(plan.kernel_get())
+        x, rep = p2.cg_solve(b if prec == 0 else b.double(), lam_rel, 0.0, k)   # FP64 x from precision 2
+        err = rel(x.cpu().numpy(), x_ref)
+        print(f"  precision {prec}: x_{k} rel err vs oracle {err:.3e} ({rep['iters']} iterations)", flush=True)
+        assert rep["iters"] == k and err < bound
+        p2.close()

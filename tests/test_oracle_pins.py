@@ -210,6 +210,21 @@ def test_embedding_matches_brute(N):
     assert np.linalg.norm(a - b) <= 1e-12 * np.linalg.norm(a)
 
 
+@pytest.mark.parametrize("N", [8, 16])
+def test_real_toeplitz_operator_matches_embedding(N):
+    """The real-FFT form with a precomputed spectrum equals the complex embedding product and the
+    brute-force convolution for a real even kernel."""
+    rng = _rng(21 + N)
+    K = rng.standard_normal((2 * N - 1,) * 3)
+    K = 0.5 * (K + K[::-1, ::-1, ::-1])
+    x = rng.standard_normal((N, N, N))
+    op = firm.toeplitz_operator(K, workers=2)
+    ref = firm.toeplitz_apply_fft(K, x).real
+    assert np.max(np.abs(op(x) - ref)) <= 1e-12 * np.max(np.abs(ref))
+    if N == 8:
+        assert np.max(np.abs(op(x) - firm.toeplitz_apply_brute(K, x))) <= 1e-11 * np.max(np.abs(ref))
+
+
 def test_embedding_wrap_value_is_free():
     """Any value in the wrap slot gives the same cropped product (the reading of the
     embedding index map at i = N + 1)."""
