@@ -123,6 +123,18 @@ firm_status firm_kernel_get(firm_plan plan, float* ker_dev);
  * reuse a stored kernel or apply any Toeplitz kernel. */
 firm_status firm_kernel_set(firm_plan plan, const float* ker_dev);
 
+/* Fourier-space regularizer (section 5: damping of high frequencies).  Adds mu L_p to the operator
+ * of every later product and solve, (A*A + lambda I + mu L_p) x = A*b, with
+ *   L_p = crop F_2N^{-1} diag(w^p) F_2N pad,   w(q) = sum_d 4 sin^2(pi q_d / 2N),
+ * the same zero-padded 2N embedding as the product (pad, crop: the N^3 volume inside (2N)^3 zeros).
+ * w is the symbol of the 7-point negative Laplacian, so L_1 x is that stencil with zero values
+ * outside the volume; L_p is positive semidefinite for every p.  It enters the product's spectrum
+ * (no extra memory traffic), the FP64 product and T. Chan's spectrum (firm_chan_spectrum).  order:
+ * 0 (none, the default) .. 3; mu >= 0 in the units of lambda (times Ker(0) with lambda_relative).
+ * Takes effect at once if a kernel exists (the spectrum is rebuilt from the kernel), else when one
+ * is computed or set.  firm_kernel_get still returns Ker. */
+firm_status firm_set_regularizer(firm_plan plan, int order, double mu);
+
 /* Step 2 (section 3.4): atb_dev (N^3 floats) = Re A*(re-centred b) (eq. backprojection)
  * for slices b_dev (device, M x P complex64).  Exact real part for any b: the
  * spread uses the pair (k, -k) as b(k) + conj(b(-k)). */

@@ -260,6 +260,35 @@ def toeplitz_operator(Ker, workers=None):
     return apply
 
 
+# ------------------------------------------------------- Fourier-space regularizer --
+
+def laplacian_symbol(L):
+    """w(q) = sum_d 4 sin^2(pi q_d / L) on the L-periodic grid, q in FFT order: the DFT of the
+    7-point negative Laplacian stencil (6 at the centre, -1 at the six neighbours)."""
+    a = 4.0 * np.sin(np.pi * np.arange(L) / L) ** 2
+    return a[:, None, None] + a[None, :, None] + a[None, None, :]
+
+
+def regularizer_apply(x, order):
+    """L_p x = crop(F_2N^{-1}(w^p . F_2N(pad x))): the damping of high frequencies that section 5
+    names as a Fourier-space regularizer, read as powers of the discrete Laplacian's symbol on the
+    product's zero-padded 2N grid (the same pad and crop as the circulant embedding)."""
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    xp = np.zeros((2 * N,) * 3)
+    xp[:N, :N, :N] = x
+    y = np.fft.ifftn(laplacian_symbol(2 * N) ** order * np.fft.fftn(xp))
+    return y[:N, :N, :N].real
+
+
+def regularizer_kernel(N, order):
+    """The Toeplitz kernel of L_p on offsets -N < o < N ((2N-1)^3, indexed like kernel_direct): the
+    inverse DFT of w^p on the 2N grid read at its circulant positions (o mod 2N)."""
+    c = np.fft.ifftn(laplacian_symbol(2 * N) ** order).real
+    o = np.arange(-N + 1, N) % (2 * N)
+    return c[np.ix_(o, o, o)]
+
+
 def toeplitz_dense(Ker, N):
     """The N^3 x N^3 matrix T[(n), (l)] = Ker(n - l) (eq. toep3)."""
     i = np.indices((N, N, N)).reshape(3, -1)

@@ -367,6 +367,18 @@ firm_status read_ker0(firm_plan p) {
 
 double lambda_eff(firm_plan p, double lam) { return p->lambda_relative ? lam * p->ker0 : lam; }
 
+// The product's spectrum from the circulant column kerc (in the plan): Ker(0), then the spectrum
+// with the damping term of the plan's regularizer (its weight read like lambda) and its 16-bit copy.
+firm_status spectrum_from_kerc(firm_plan p) {
+    firm_status s = read_ker0(p);
+    if (s != FIRM_OK) return s;
+    p->reg_mu_eff = lambda_eff(p, p->reg_mu);
+    FIRM_HIP(p, fft_khat_from_kerc(p, (float2*)p->ws1));
+    p->have_kernel = true;
+    p->khat64_valid = false;
+    return FIRM_OK;
+}
+
 }  // namespace
 
 firm_status ensure_fp64(firm_plan p) {
@@ -425,10 +437,7 @@ firm_status firm_kernel_precompute(firm_plan p) {
     FIRM_HIP(p, spread_ker(p, grid));
     FIRM_HIP(p, fft_ker_grid(p, grid, h1, h2, chalf));
     FIRM_HIP(p, kerc_from_half(p, chalf));
-    FIRM_HIP(p, fft_khat_from_kerc(p, (float2*)p->ws1));
-    p->have_kernel = true;
-    p->khat64_valid = false;
-    return read_ker0(p);
+    return spectrum_from_kerc(p);
 }
 
 firm_status firm_kernel_get(firm_plan p, float* ker) {
@@ -444,10 +453,20 @@ firm_status firm_kernel_set(firm_plan p, const float* ker) {
     firm_status s = ensure_ws(p, &p->ws1, &p->ws1_bytes, N2 * N2 * (size_t)p->QP * sizeof(float2));
     if (s != FIRM_OK) return s;
     FIRM_HIP(p, kerc_from_centred(p, ker));
-    FIRM_HIP(p, fft_khat_from_kerc(p, (float2*)p->ws1));
-    p->have_kernel = true;
-    p->khat64_valid = false;
-    return read_ker0(p);
+    return spectrum_from_kerc(p);
+}
+
+firm_status firm_set_regularizer(firm_plan p, int order, double mu) {
+    if (!p) return firm_fail(nullptr, FIRM_ERR_ARG, "null plan");
+    if (order < 0 || order > 3) return firm_fail(p, FIRM_ERR_ARG, "order must be in [0, 3]");
+    if (!(mu >= 0.0) || !std::isfinite(mu)) return firm_fail(p, FIRM_ERR_ARG, "mu must be finite and >= 0");
+    p->reg_order = mu > 0.0 ? order : 0;
+    p->reg_mu = order > 0 ? mu : 0.0;
+    if (!p->have_kernel) return FIRM_OK;  // applied when the kernel's spectrum is built
+    const size_t N2 = 2 * p->N;
+    firm_status s = ensure_ws(p, &p->ws1, &p->ws1_bytes, N2 * N2 * (size_t)p->QP * sizeof(float2));
+    if (s != FIRM_OK) return s;
+    return spectrum_from_kerc(p);
 }
 
 firm_status firm_kernel_spectrum(firm_plan p, float* khat) {

@@ -510,6 +510,23 @@ __device__ __forceinline__ bool khat_blocked_q(int64_t i, int L, int C, int ng, 
     return q3 <= L / 2;
 }
 
+// Fourier-space damping term of the multiplier: kh(q) += coef w(q)^order, with
+// w(q) = sum_d 4 sin^2(pi q_d / L) the symbol of the 7-point negative Laplacian on the L-periodic
+// grid (q in FFT order; the symbol is even, so the axis order of the blocked layout is immaterial).
+template <class S>
+__global__ void __launch_bounds__(256) k_khat_reg(S* __restrict__ kh, int L, int C, int ng, double coef, int order) {
+    const int64_t n = (int64_t)L * ng * L * C;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int q1, q2, q3;
+        if (!khat_blocked_q(i, L, C, ng, q1, q2, q3)) continue;
+        const double s1 = sin(M_PI * q1 / L), s2 = sin(M_PI * q2 / L), s3 = sin(M_PI * q3 / L);
+        const double w = 4.0 * (s1 * s1 + s2 * s2 + s3 * s3);
+        double wp = 1.0;
+        for (int k = 0; k < order; ++k) wp *= w;
+        kh[i] = (S)((double)kh[i] + coef * wp);
+    }
+}
+
 // pass 1: per-shell sum and count (block-private in LDS, then added to the global totals)
 __global__ void __launch_bounds__(256) k_khat_shell_sum(const float* __restrict__ kh, int L, int C, int ng,
                                                         double* __restrict__ gsum, unsigned* __restrict__ gcnt) {
@@ -998,9 +1015,23 @@ hipError_t precond_passes(firm_plan p, const float* dhalf, const float* r, float
 
 template <int L>
 hipError_t khat_f32(firm_plan p, float2* w1) { return khat_passes<L, float>(p, p->kerc, w1, p->khat, p->tw); }
+// adds the plan's damping term (if any) to a blocked spectrum of L-point pencils
+template <int L, class S>
+hipError_t khat_add_reg(firm_plan p, S* kh) {
+    if (p->reg_order <= 0 || !(p->reg_mu_eff > 0.0)) return hipSuccess;
+    constexpr int C = FftCfg<L, typename VecOf<S>::V>::C;
+    const int N = L / 2, ng = (N + 1 + C - 1) / C;
+    const int64_t n = (int64_t)L * ng * L * C;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    const double coef = p->reg_mu_eff / ((double)L * L * L);  // the spectrum carries 1 / L^3
+    hipLaunchKernelGGL(k_khat_reg<S>, dim3(blocks), dim3(256), 0, p->stream, kh, L, C, ng, coef, p->reg_order);
+    return hipGetLastError();
+}
+
 template <int L>
 hipError_t khat_f64(firm_plan p, const double* k64, double2* w1) {
-    return khat_passes<L, double>(p, k64, w1, p->khat64, p->tw64);
+    RET_IF((khat_passes<L, double>(p, k64, w1, p->khat64, p->tw64)));
+    return khat_add_reg<L, double>(p, p->khat64);
 }
 
 // Forward N^3 real-to-half-spectrum transform: out [N][N][QPn] complex, FFT order, q3 in [0, N/2].
@@ -1137,6 +1168,7 @@ namespace {
 template <int L>
 hipError_t khat_f32_all(firm_plan p, float2* w1) {
     RET_IF(khat_f32<L>(p, w1));
+    RET_IF((khat_add_reg<L, float>(p, p->khat)));
     if (!p->khat_bf16) return hipSuccess;
     constexpr int C = FftCfg<L, float2>::C;
     const int N = L / 2, ng = (N + 1 + C - 1) / C;

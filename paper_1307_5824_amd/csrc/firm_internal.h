@@ -21,6 +21,9 @@ struct firm_plan_s {
     int lambda_relative = 0;    // lambda multiplies Ker(0)
     double inner_tol = 1e-3;    // relative tolerance of each FP32 correction (precision 1)
     double ker0 = 0.0;          // Ker(0) of the current kernel
+    int reg_order = 0;          // Fourier-space damping: order p of mu L_p (0 = none)
+    double reg_mu = 0.0;        // its weight as given (times Ker(0) with lambda_relative)
+    double reg_mu_eff = 0.0;    // the weight in the operator's units, set when the spectrum is built
     hipStream_t stream = nullptr;
     std::string err;
 

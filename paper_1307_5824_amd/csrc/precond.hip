@@ -101,6 +101,37 @@ __global__ void k_half_to_centred(const float2* __restrict__ h, int N, int QPn, 
     }
 }
 
+// T. Chan's spectrum of the damping term mu L_p on the centred N^3 grid, added to out.  The symbol
+// w^p = (sum_d a(theta_d))^p, a = 2 - 2 cos, expands by the multinomial theorem into products of
+// per-axis powers a^i, whose kernels (2 - S - S^-1)^i have the taps (-1)^o C(2i, i + o), |o| <= i;
+// Chan's Fejer-weighted fold of a product kernel is the product of the per-axis folds
+// sum_o (1 - |o| / N) (-1)^o C(2i, i + o) cos(2 pi q o / N).
+__device__ double chan_axis(int i, int q, int N) {
+    double s = 0.0, binom = 1.0;  // C(2i, i + o) for o = i down to -i
+    for (int o = i; o >= -i; --o) {
+        const double tap = ((o & 1) ? -1.0 : 1.0) * binom;
+        s += (1.0 - fabs((double)o) / N) * tap * cos(2.0 * M_PI * (double)q * o / N);
+        const int k = i - o;  // binom = C(2i, k); next C(2i, k + 1)
+        binom = binom * (2 * i - k) / (k + 1);
+    }
+    return s;
+}
+
+__global__ void k_chan_reg(float* __restrict__ out, int N, double mu, int order) {
+    const int64_t n = (int64_t)N * N * N;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int q[3] = {(int)(i / ((int64_t)N * N)) - N / 2, (int)((i / N) % N) - N / 2, (int)(i % N) - N / 2};
+        double acc = 0.0, fact[8] = {1, 1, 2, 6, 24, 120, 720, 5040};
+        for (int a = 0; a <= order; ++a)
+            for (int b = 0; a + b <= order; ++b) {
+                const int c = order - a - b;
+                acc += fact[order] / (fact[a] * fact[b] * fact[c]) * chan_axis(a, q[0], N) * chan_axis(b, q[1], N) *
+                       chan_axis(c, q[2], N);
+            }
+        out[i] = (float)((double)out[i] + mu * acc);
+    }
+}
+
 }  // namespace
 
 hipError_t chan_spectrum(firm_plan p, double lam, float* out) {
@@ -112,6 +143,8 @@ hipError_t chan_spectrum(firm_plan p, double lam, float* out) {
     e = fft_forward_r2c(p, p->tmp, p->S1);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_half_to_centred, dim3(blocks), dim3(256), 0, p->stream, p->S1, p->N, p->QPn, (float)lam, out);
+    if (p->reg_order > 0 && p->reg_mu_eff > 0.0)
+        hipLaunchKernelGGL(k_chan_reg, dim3(blocks), dim3(256), 0, p->stream, out, p->N, p->reg_mu_eff, p->reg_order);
     return hipGetLastError();
 }
 

@@ -58,6 +58,7 @@ def _load():
         "firm_kernel_precompute": (i, [vp]),
         "firm_kernel_get": (i, [vp, vp]),
         "firm_kernel_set": (i, [vp, vp]),
+        "firm_set_regularizer": (i, [vp, i, d]),
         "firm_kernel_spectrum": (i, [vp, vp]),
         "firm_backproject": (i, [vp, vp, vp]),
         "firm_forward_project": (i, [vp, vp, vp]),
@@ -210,6 +211,10 @@ class Plan:
     def kernel_set(self, ker):
         self._req(ker, (2 * self.N) ** 3, self._torch.float32)
         _check(lib.firm_kernel_set(self.h, _ptr(ker)), self.h)
+
+    def set_regularizer(self, order, mu):
+        """Fourier-space damping mu L_p added to A*A + lambda (order p in 0..3, mu like lambda)."""
+        _check(lib.firm_set_regularizer(self.h, int(order), float(mu)), self.h)
 
     def kernel_spectrum(self, out=None):
         if out is None:

@@ -595,3 +595,55 @@ def test_noise_at_sigma_realises_the_snr():
     nz = firm.hermitian_noise(N, M, rng.standard_normal((M, P, 2)), firm.noise_sigma(b, snr))
     ratio = np.mean(np.abs(b) ** 2) / np.mean(np.abs(nz) ** 2)
     assert abs(ratio / snr - 1.0) < 0.01
+
+
+# ------------------------------------------------ Fourier-space regularizer (section 5) --
+
+def _stencil_zero_boundary(x):
+    """6 x(n) - sum of the six neighbours, with zero values outside the volume."""
+    xp = np.pad(x, 1)
+    c = xp[1:-1, 1:-1, 1:-1]
+    nb = (xp[2:, 1:-1, 1:-1] + xp[:-2, 1:-1, 1:-1] + xp[1:-1, 2:, 1:-1] + xp[1:-1, :-2, 1:-1]
+          + xp[1:-1, 1:-1, 2:] + xp[1:-1, 1:-1, :-2])
+    return 6.0 * c - nb
+
+
+def _stencil_periodic(x):
+    return 6.0 * x - sum(np.roll(x, s, axis=a) for a in range(3) for s in (1, -1))
+
+
+def test_regularizer_order1_is_the_dirichlet_laplacian_stencil():
+    x = _rng(50).standard_normal((8, 8, 8))
+    assert np.max(np.abs(firm.regularizer_apply(x, 1) - _stencil_zero_boundary(x))) <= 1e-12
+
+
+def test_regularizer_order2_is_the_periodic_stencil_twice_on_the_padded_grid():
+    N = 8
+    x = _rng(51).standard_normal((N, N, N))
+    xp = np.zeros((2 * N,) * 3)
+    xp[:N, :N, :N] = x
+    ref = _stencil_periodic(_stencil_periodic(xp))[:N, :N, :N]
+    assert np.max(np.abs(firm.regularizer_apply(x, 2) - ref)) <= 1e-11
+
+
+def test_regularizer_kernel_taps_and_toeplitz_form():
+    N = 8
+    r1 = firm.regularizer_kernel(N, 1)
+    ref = np.zeros_like(r1)
+    c = N - 1
+    ref[c, c, c] = 6.0
+    for a in range(3):
+        for sgn in (1, -1):
+            idx = [c, c, c]
+            idx[a] += sgn
+            ref[tuple(idx)] = -1.0
+    assert np.max(np.abs(r1 - ref)) <= 1e-12
+    r2 = firm.regularizer_kernel(N, 2)
+    o = np.indices(r2.shape) - c
+    assert np.max(np.abs(r2[np.abs(o).sum(0) > 2])) <= 1e-12 and abs(r2.sum()) <= 1e-10
+    assert abs(r2[c, c, c] - 42.0) <= 1e-10          # 6^2 + 6 (each neighbour squared)
+    x = _rng(52).standard_normal((N, N, N))
+    for p, r in ((1, r1), (2, r2), (3, firm.regularizer_kernel(N, 3))):
+        y = firm.toeplitz_apply_fft(r, x).real
+        assert np.max(np.abs(y - firm.regularizer_apply(x, p))) <= 1e-10
+        assert float(np.sum(x * y)) >= 0.0            # positive semidefinite
