@@ -229,6 +229,22 @@ firm_status firm_synth_images(firm_plan plan, int B, const double* centers, cons
 firm_status firm_synth_slices(firm_plan plan, int B, const double* centers, const double* sigmas,
                               const double* amps, double snr, uint64_t seed, void* b_dev);
 
+/* Sampled blob volume for accuracy measurements: V_dev (N^3 floats, centred order) =
+ * sum_b a_b exp(-||n - c_b||^2 / (2 s_b^2)) at the voxels n = i - N/2 (section 3.1's sampling of
+ * the potential), the volume whose slices firm_synth_slices gives in closed form.  centers (B x 3),
+ * sigmas (> 0), amps: host doubles in voxel units; B in [1, 320]. */
+firm_status firm_synth_volume(firm_plan plan, int B, const double* centers, const double* sigmas,
+                              const double* amps, float* V_dev);
+
+/* Fourier shell correlation of section 4 between V1_dev and V2_dev (N^3 floats, device): for the
+ * shells i = 1 .. N/2 - 1, Shell_i = {j : 0.5 + (i-1) + 1e-4 <= ||j|| < 0.5 + i + 1e-4},
+ *   FSC(i) = sum_{Shell_i} F(V1) conj F(V2) / sqrt(sum |F(V1)|^2 sum |F(V2)|^2)
+ * (against the true volume, the Fourier cross-resolution), and the modified forms restricted to
+ * the frequencies outside / inside the cone of half-angle cone_deg about the third axis (the
+ * missing cone of a random conical tilt series at tilt 90 - cone_deg degrees).  fsc_host (host,
+ * 3 x (N/2 - 1) doubles): rows all, outside, inside; NaN where a shell region is empty. */
+firm_status firm_fsc(firm_plan plan, const float* V1_dev, const float* V2_dev, double cone_deg, double* fsc_host);
+
 /* ---- learned Fourier-diagonal preconditioner ----------------------------------------
  * A 3D conv net maps f = log(|K^| pooled to res^3 / Ker(0) + lam_rel) to a log floor on the
  * res^3 frequency grid: o = c4(relu(c3(relu(c2(relu(c1(f))))))) with 3^3 filters, circular

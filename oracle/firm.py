@@ -449,6 +449,26 @@ def fsc(V1, V2, eps=1e-4):
     return np.array(out)
 
 
+def fsc_cone(V1, V2, cone_deg, inside, eps=1e-4):
+    """The modified FSC of section 4: the shell sums restricted to the frequencies inside (or
+    outside) the cone of half-angle cone_deg about the third axis, the missing cone of a random
+    conical tilt series.  NaN where a shell has no such frequency."""
+    N = V1.shape[0]
+    F1 = np.fft.fftshift(np.fft.fftn(np.fft.ifftshift(V1)))
+    F2 = np.fft.fftshift(np.fft.fftn(np.fft.ifftshift(V2)))
+    j = np.indices((N, N, N)) - N // 2
+    rad = np.sqrt((j * j).sum(0))
+    in_cone = np.abs(j[2]) > rad * np.cos(np.deg2rad(cone_deg))
+    region = in_cone if inside else ~in_cone
+    out = []
+    for i in range(1, N // 2):
+        s = (rad >= 0.5 + (i - 1) + eps) & (rad < 0.5 + i + eps) & region
+        num = np.sum(F1[s] * np.conj(F2[s]))
+        den = np.sqrt(np.sum(np.abs(F1[s]) ** 2) * np.sum(np.abs(F2[s]) ** 2))
+        out.append((num / den).real if den > 0 else np.nan)
+    return np.array(out)
+
+
 # ------------------------------------------------------------ noise --
 
 def hermitian_noise(N, M, z, sigma):

@@ -10,7 +10,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfirm.so")
-SOURCES = ["api.hip", "fft.hip", "spread.hip", "cg.hip", "synth.hip", "pcnet.hip", "precond.hip", "project.hip", "images.hip", "unroll.hip"]
+SOURCES = ["api.hip", "fft.hip", "spread.hip", "cg.hip", "synth.hip", "pcnet.hip", "precond.hip", "project.hip", "images.hip", "unroll.hip", "eval.hip"]
 ARCH = os.environ.get("FIRM_OFFLOAD_ARCH", "gfx950")
 
 

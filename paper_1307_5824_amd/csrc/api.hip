@@ -639,6 +639,50 @@ firm_status firm_synth_slices(firm_plan p, int B, const double* centers, const d
     return FIRM_OK;
 }
 
+firm_status firm_synth_volume(firm_plan p, int B, const double* centers, const double* sigmas, const double* amps,
+                              float* V) {
+    if (!p || !V || (B > 0 && (!centers || !sigmas || !amps))) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (B < 1 || B > 320) return firm_fail(p, FIRM_ERR_ARG, "B must be in [1, 320]");
+    std::vector<double> bl((size_t)B * 5);
+    for (int i = 0; i < B; ++i) {
+        if (!(sigmas[i] > 0.0) || !std::isfinite(sigmas[i])) return firm_fail(p, FIRM_ERR_ARG, "volume blobs need sigma > 0");
+        for (int d = 0; d < 3; ++d) bl[5 * i + d] = centers[3 * i + d];
+        bl[5 * i + 3] = sigmas[i];
+        bl[5 * i + 4] = amps[i];
+    }
+    double* dbl = nullptr;
+    FIRM_HIP(p, hipMalloc((void**)&dbl, bl.size() * sizeof(double)));
+    hipError_t e = hipMemcpyAsync(dbl, bl.data(), bl.size() * sizeof(double), hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = synth_volume(p, B, dbl, V);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(dbl);
+    if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("synth volume: ") + hipGetErrorString(e));
+    return FIRM_OK;
+}
+
+firm_status firm_fsc(firm_plan p, const float* V1, const float* V2, double cone_deg, double* out) {
+    if (!p || !V1 || !V2 || !out) return firm_fail(p, FIRM_ERR_ARG, "null argument");
+    if (!(cone_deg >= 0.0 && cone_deg <= 90.0)) return firm_fail(p, FIRM_ERR_ARG, "cone_deg must be in [0, 90]");
+    const int64_t N = p->N;
+    const int S = fsc_max_shells();
+    if (N / 2 > S) return firm_fail(p, FIRM_ERR_ARG, "N too large for the shell table");
+    if (!p->S2) {
+        firm_status s = ensure_ws(p, (void**)&p->S2, &p->s2_bytes, (size_t)(N * N * p->QPn) * sizeof(float2));
+        if (s != FIRM_OK) return s;
+    }
+    FIRM_HIP(p, fsc_sums(p, V1, V2, cone_deg, p->partials3));
+    std::vector<double> h((size_t)9 * S);
+    FIRM_HIP(p, hipMemcpyAsync(h.data(), p->partials3, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+    FIRM_HIP(p, hipStreamSynchronize(p->stream));
+    const int nsh = (int)(N / 2 - 1);
+    for (int r = 0; r < 3; ++r)
+        for (int i = 1; i <= nsh; ++i) {
+            const double num = h[(3 * r) * S + i], d1 = h[(3 * r + 1) * S + i], d2 = h[(3 * r + 2) * S + i];
+            out[r * nsh + i - 1] = d1 > 0.0 && d2 > 0.0 ? num / std::sqrt(d1 * d2) : std::nan("");
+        }
+    return FIRM_OK;
+}
+
 }  // extern "C"
 
 extern "C" {

@@ -162,9 +162,16 @@ int64_t synth_images_scratch(int N, int M);  // doubles of device scratch synth_
 // ---- synth.hip ----
 hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr, uint64_t seed,
                         float2* b, double* power_dev);
+hipError_t synth_volume(firm_plan p, int B, const double* blobs_dev, float* V);  // blobs B x (c, s, a)
 
 // ---- pcnet.hip ----
 hipError_t noalloc_scratch_setup();  // device address of the no-allocation scratch, current device
+
+// ---- eval.hip ----
+// per (region all / outside / inside the cone, quantity Re(F1 conj F2) / |F1|^2 / |F2|^2, shell)
+// sums, 9 x fsc_max_shells() doubles at sums_dev (shell index i at offset i; i = 0 unused)
+hipError_t fsc_sums(firm_plan p, const float* V1, const float* V2, double cone_deg, double* sums_dev);
+int fsc_max_shells();
 
 // ---- unroll.hip ----
 int64_t unrolled_workspace_floats(int N, int k);

@@ -9,6 +9,7 @@
 // h_m(||omega_k||) and by exp(-i <omega_k, s_m>) for an image shifted by s_m.
 // Noise draws come from Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC 2011)
 // keyed by the seed with counter (m, j, 0, 0), j the half-disk index.
+#include <algorithm>
 #include <cmath>
 
 #include "firm_internal.h"
@@ -169,4 +170,35 @@ hipError_t synth_slices(firm_plan p, int B, const double* blobs_dev, double snr,
         e = hipGetLastError();
     }
     return e;
+}
+
+namespace {
+
+// V(n) = sum_b a_b exp(-||n - c_b||^2 / (2 s_b^2)) on the N^3 grid, n = i - N/2 (section 3.1's volume
+// sampling of the blob potential); blobs B x 5 as (c, s, a).
+__global__ void __launch_bounds__(256) k_blob_volume(const double* __restrict__ blobs, int B, int N,
+                                                     float* __restrict__ V) {
+    __shared__ double bl[5 * 320];
+    for (int i = threadIdx.x; i < 5 * B; i += 256) bl[i] = blobs[i];
+    __syncthreads();
+    const int64_t n = (int64_t)N * N * N;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double x = (double)(i / ((int64_t)N * N)) - N / 2, y = (double)((i / N) % N) - N / 2,
+                     z = (double)(i % N) - N / 2;
+        double v = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const double dx = x - bl[5 * b], dy = y - bl[5 * b + 1], dz = z - bl[5 * b + 2], s = bl[5 * b + 3];
+            v += bl[5 * b + 4] * exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s * s));
+        }
+        V[i] = (float)v;
+    }
+}
+
+}  // namespace
+
+hipError_t synth_volume(firm_plan p, int B, const double* blobs_dev, float* V) {
+    const int64_t n = (int64_t)p->N * p->N * p->N;
+    hipLaunchKernelGGL(k_blob_volume, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 8192)), dim3(256), 0,
+                       p->stream, blobs_dev, B, p->N, V);
+    return hipGetLastError();
 }

@@ -59,6 +59,8 @@ def _load():
         "firm_kernel_get": (i, [vp, vp]),
         "firm_kernel_set": (i, [vp, vp]),
         "firm_set_regularizer": (i, [vp, i, d]),
+        "firm_synth_volume": (i, [vp, i, vp, vp, vp, vp]),
+        "firm_fsc": (i, [vp, vp, vp, d, vp]),
         "firm_kernel_spectrum": (i, [vp, vp]),
         "firm_backproject": (i, [vp, vp, vp]),
         "firm_forward_project": (i, [vp, vp, vp]),
@@ -305,6 +307,25 @@ class Plan:
         self._req(out, self.M * self.N * self.N, self._torch.float32)
         _check(lib.firm_synth_images(self.h, int(c.shape[0]), cp, sp, ap, float(snr), int(seed), _ptr(out)), self.h)
         return out
+
+    def synth_volume(self, centers, sigmas, amps, out=None):
+        """The sampled blob volume (N^3) whose slices synth_slices gives in closed form."""
+        c, cp = _host(np.asarray(centers).reshape(-1, 3), np.float64)
+        s, sp = _host(np.ravel(sigmas), np.float64)
+        a, ap = _host(np.ravel(amps), np.float64)
+        out = self._vol(out)
+        _check(lib.firm_synth_volume(self.h, int(c.shape[0]), cp, sp, ap, _ptr(out)), self.h)
+        return out
+
+    def fsc(self, V1, V2, cone_deg=0.0):
+        """Fourier shell correlation (section 4): (3, N/2 - 1) array, rows all shells' frequencies,
+        outside and inside the cone of half-angle cone_deg about the third axis."""
+        self._req(V1, self.N ** 3, self._torch.float32)
+        self._req(V2, self.N ** 3, self._torch.float32)
+        out = np.zeros(3 * (self.N // 2 - 1))
+        _check(lib.firm_fsc(self.h, _ptr(V1), _ptr(V2), float(cone_deg), out.ctypes.data_as(ctypes.c_void_p)),
+               self.h)
+        return out.reshape(3, self.N // 2 - 1)
 
     def synth_slices(self, centers, sigmas, amps, snr=float("inf"), seed=0, out=None):
         c, cp = _host(np.asarray(centers).reshape(-1, 3), np.float64)

@@ -16,6 +16,8 @@ random orientations stand in for them):
   uneven   N=128, 100 blobs, M=50,000,  90% vMF(kappa=5) + 10% Haar, 20 groups, SNR 1/20, lambda=1e-2
   train    N=64,  per set kappa~U[0,20], 1..20 groups, M=10,000 (preconditioner training)
   large    N=256, 300 blobs, M=100,000, vMF(kappa=10), 50 groups, SNR 1/30, lambda=1e-2
+  rct      N=256, 300 blobs, M=100,000, random conical tilt at 60 degrees (the paper's experiment
+           geometry), 3 groups, SNR 1, lambda=1e-2
 """
 import dataclasses
 
@@ -37,6 +39,7 @@ class Workload:
     snr: float            # inf = noiseless
     lam: float
     index: int
+    tilt_deg: float = 0.0  # > 0: random conical tilt series at this tilt, uniform azimuth
 
 
 WORKLOADS = {
@@ -45,6 +48,7 @@ WORKLOADS = {
     "uneven": Workload("uneven", 128, 100, 50_000, 5.0, 0.1, 2.0, 20, 0.05, 1e-2, 2),
     "train": Workload("train", 64, 40, 10_000, -1.0, 0.1, 2.0, -1, 0.1, 1e-2, 3),
     "large": Workload("large", 256, 300, 100_000, 10.0, 0.0, 2.0, 50, 1.0 / 30.0, 1e-2, 4),
+    "rct": Workload("rct", 256, 300, 100_000, 0.0, 0.0, 2.0, 3, 1.0, 1e-2, 5, tilt_deg=60.0),
 }
 
 
@@ -102,6 +106,16 @@ def rotations_with_directions(d, rng):
     r1 = np.cos(psi)[:, None] * a + np.sin(psi)[:, None] * b
     r2 = np.cross(d, r1)
     return np.stack([r1, r2, d], axis=1)
+
+
+def rct_rotations(M, tilt_deg, rng):
+    """A random conical tilt series (section 4): viewing directions at the tilt angle from +e3 with
+    azimuths uniform in [0, 2 pi), uniform in-plane angles.  The slices then miss the cone of
+    half-angle 90 - tilt degrees about e3 in Fourier space."""
+    t = np.deg2rad(tilt_deg)
+    phi = rng.random(M) * 2 * np.pi
+    d = np.stack([np.sin(t) * np.cos(phi), np.sin(t) * np.sin(phi), np.full(M, np.cos(t))], axis=1)
+    return rotations_with_directions(d, rng)
 
 
 def mixed_rotations(M, kappa, uniform_frac, rng):
@@ -183,7 +197,7 @@ def make_inputs(workload, M=None, set_index=None):
     if kappa < 0:                      # per-set draws of the training recipe
         kappa = float(rr.uniform(0.0, 20.0))
         groups = int(rc.integers(1, 21))
-    R = mixed_rotations(M, kappa, wl.uniform_frac, rr)
+    R = rct_rotations(M, wl.tilt_deg, rr) if wl.tilt_deg > 0 else mixed_rotations(M, kappa, wl.uniform_frac, rr)
     shifts = rs.uniform(-wl.shift_px, wl.shift_px, size=(M, 2)) if wl.shift_px > 0 else None
     if groups > 0:
         table = ctf_table(wl.N, defoci(groups, rc))

@@ -647,3 +647,46 @@ def test_regularizer_kernel_taps_and_toeplitz_form():
         y = firm.toeplitz_apply_fft(r, x).real
         assert np.max(np.abs(y - firm.regularizer_apply(x, p))) <= 1e-10
         assert float(np.sum(x * y)) >= 0.0            # positive semidefinite
+
+
+# ------------------------------------------------ random conical tilt and the missing cone --
+
+def test_rct_views_and_missing_cone():
+    """Every RCT viewing direction is at the tilt angle from e3, the rotations are proper, and no
+    sample point of any slice falls inside the cone of half-angle 90 - tilt about e3."""
+    rng = _rng(60)
+    R = synth.rct_rotations(500, 60.0, rng)
+    assert np.allclose(R[:, 2, 2], 0.5, atol=1e-12)
+    assert np.allclose(np.einsum("mij,mkj->mik", R, R), np.eye(3), atol=1e-12)
+    assert np.allclose(np.linalg.det(R), 1.0)
+    xi = firm.sample_points(16, R).reshape(-1, 3)
+    r = np.linalg.norm(xi, axis=1)
+    nz = r > 0
+    polar = np.degrees(np.arccos(np.abs(xi[nz, 2]) / r[nz]))
+    assert polar.min() >= 30.0 - 1e-9
+    assert polar.min() <= 30.0 + 0.5          # the cone's edge is reached
+
+
+def test_fsc_cone_membership():
+    """Plane waves placed inside and outside a 30-degree cone about the third axis: the modified
+    FSC keeps each one in its own region (cone membership by hand from the angle to e3)."""
+    N = 16
+    rng = _rng(61)
+    n = np.indices((N, N, N)) - N // 2
+    # j, shell, inside the 30-degree cone?, sign in V1
+    waves = [((0, 0, 3), 3, True, -1), ((3, 0, 0), 3, False, +1), ((1, 0, 3), 3, True, +1),
+             ((2, 0, 2), 3, False, -1), ((1, 1, 5), 5, True, -1), ((4, 1, 2), 5, False, +1),
+             ((0, 2, 6), 6, True, +1), ((6, 0, 1), 6, False, -1)]
+    V1 = np.zeros((N, N, N))
+    V2 = np.zeros((N, N, N))
+    for j, _, _, sg in waves:
+        w = np.cos(2 * np.pi * np.tensordot(np.array(j), n, axes=1) / N + rng.uniform(0, 2 * np.pi))
+        V1 += sg * w
+        V2 += w
+    for inside in (True, False):
+        got = firm.fsc_cone(V1, V2, 30.0, inside)
+        for i in range(1, N // 2):
+            sel = [sg for j, sh, ins, sg in waves if sh == i and ins == inside]
+            if sel:   # (shells without a wave correlate round-off only)
+                assert abs(got[i - 1] - np.mean(sel)) <= 1e-12, (inside, i)
+    assert np.allclose(firm.fsc_cone(V1, V2, 0.0, False), firm.fsc(V1, V2), equal_nan=True)
