@@ -64,23 +64,82 @@ def measured_traffic(pass_index):
         return None
 
 
-def cpu_baseline(N, seed=0):
-    """The FP64 oracle's Toeplitz product at size N (numpy FFTs through the circulant embedding),
-    timed once on the host: a bounded sample of the same workload (one product)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(N, synth, seed=0):
+    """The FP64 oracle timed on all host cores (a bounded sample of the same work, about 20 s):
+    * value: FP64 Toeplitz products per second at size N through the 2N circulant embedding
+      (scipy FFTs on every core), with the rates at N/4 and N/2 beside it;
+    * the small workload's full oracle (direct kernel sum, direct back-projection, 20 FP64 CG
+      iterations on the Toeplitz product);
+    * the direct kernel sum of eq. kernel per offset at size N over all the headline workload's
+      sample points (oracle/direct.c on every core), and the full (2N-1)^3 kernel extrapolated
+      from it (labelled as such);
+    * the mid workload's FP64 CG to 1e-5, extrapolated from the time of one FP64 iteration times
+      the iterations the GPU's FP64-refined CG needs there (238)."""
     import numpy as np
 
+    from oracle import blobs, direct
     from oracle import firm as ofirm
+    cores = os.cpu_count() or 1
     rng = np.random.default_rng(seed)
-    K = rng.standard_normal((2 * N - 1,) * 3)
+    rates = {}
+    for n, reps in ((N // 4, 5), (N // 2, 3), (N, 2)):
+        K = rng.standard_normal((2 * n - 1,) * 3)
+        K = 0.5 * (K + K[::-1, ::-1, ::-1])
+        T = ofirm.toeplitz_operator(K, workers=cores)
+        x = rng.standard_normal((n, n, n))
+        T(x)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            y = T(x)
+        rates[n] = reps / (time.perf_counter() - t0)
+        del K, T, x, y
+    # the mid workload's CG iteration: one product plus the vector updates, FP64
+    n = N // 4
+    K = rng.standard_normal((2 * n - 1,) * 3)
     K = 0.5 * (K + K[::-1, ::-1, ::-1])
-    x = rng.standard_normal((N, N, N))
+    T = ofirm.toeplitz_operator(K, workers=cores)
+    b = rng.standard_normal((n, n, n))
     t0 = time.perf_counter()
-    y = ofirm.toeplitz_apply_fft(K, x)
-    dt = time.perf_counter() - t0
-    del y
-    return {"value": 1.0 / dt, "unit": "applies/s", "cores": 1, "kind": "oracle",
-            "sample": f"one FP64 Toeplitz product at N={N} through the 2N circulant embedding "
-                      f"(numpy single-threaded FFTs, random even kernel): {dt:.1f} s"}
+    ofirm.cg(lambda v: T(v) + 1.0 * v, b, iters=10)
+    it_s = (time.perf_counter() - t0) / 10
+    # the small workload end to end
+    inp = synth.make_inputs("small")
+    Ns = inp.workload.N
+    t0 = time.perf_counter()
+    V = blobs.sample_volume(Ns, inp.centers, inp.sigmas, inp.amps)
+    bsl = ofirm.forward_project(V, inp.rotations)
+    Ker = ofirm.kernel_direct(Ns, inp.rotations).real
+    atb = ofirm.back_project(bsl, Ns, inp.rotations).real
+    Ts = ofirm.toeplitz_operator(Ker, workers=cores)
+    ofirm.cg(lambda v: Ts(v) + inp.workload.lam * v, atb, iters=20)
+    c1_s = time.perf_counter() - t0
+    # the direct kernel sum per offset over the headline workload's 5.1e9 sample points
+    big = synth.make_inputs("large")
+    offs = np.array([[-40, 25, 90]])
+    t0 = time.perf_counter()
+    direct.kernel_at(offs, N, big.rotations, big.ctf_group, big.ctf_table, nthreads=cores)
+    per_off = (time.perf_counter() - t0) / len(offs)
+    return {"value": round(rates[N], 4), "unit": "applies/s", "cores": cores, "kind": "oracle",
+            "sample": f"FP64 Toeplitz products at N={N} through the 2N circulant embedding (scipy FFTs on "
+                      f"{cores} threads, random even kernel), 2 timed",
+            "cpu_model": cpu_model(),
+            "applies_per_s": {str(k): round(v, 4) for k, v in rates.items()},
+            "small_full_oracle_s": round(c1_s, 3),
+            "direct_kernel_s_per_offset": round(per_off, 3),
+            "direct_kernel_full_s_extrapolated": round(per_off * (2 * N - 1) ** 3, 0),
+            "mid_cg_iteration_s": round(it_s, 5),
+            "mid_cg_to_1e-5_s_extrapolated": round(it_s * 238, 3)}
 
 
 def counter_workload(args, firm, synth, torch):
@@ -433,7 +492,7 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(N)
+        out["cpu_baseline"] = cpu_baseline(N, synth)
     print(json.dumps(out), flush=True)
 
 
