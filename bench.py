@@ -2,13 +2,15 @@
 
 One step is one pass of the whole hot path over one synthetic data set already resident in
 HBM: kernel precompute (gridding + FFTs + circulant spectrum), back-projection A*b, a plain CG
-solve to the tolerance, the learned preconditioner's inference (features, network, diagonal),
-the learned-PCG solve to the same tolerance, and a block of back-to-back A*A products.  The
-headline value is A*A products per second at N = 256 (HIP events around the product block);
-the JSON line also carries the time to the tolerance of plain CG and learned PCG (and, timed
-once after the steps, PCG with T. Chan's analytic diagonal), the precompute and
-back-projection times, the roofline of the dominant FFT pass and the FP64 oracle timed on the
-host.
+solve to the tolerance, the learned preconditioner's inference (features, network, Chan's
+spectrum, diagonal), the learned-PCG solve to the same tolerance, and a block of back-to-back
+A*A products.  The headline value is A*A products per second at N = 256 (HIP events around the
+product block).  The JSON line also carries the time to the tolerance of plain CG and learned
+PCG (and, timed once after the steps, PCG with T. Chan's analytic diagonal and with a constant
+floor under it at the network's mean level), the precompute and back-projection times with their
+gridding rates, the forward projection and step 1 on real-space images, the paper's
+random-conical-tilt accuracy experiment (Fourier cross-resolution outside and inside the missing
+cone), the roofline of the dominant FFT pass and the FP64 oracle timed on the host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
 """
@@ -366,33 +368,6 @@ def main():
     del imgs, b_img
     print(f"images: synth {synth_img_ms:.1f} ms, images_to_slices {img2sl_ms:.1f} ms", file=sys.stderr, flush=True)
 
-    # the 16-bit spectrum (option khat_bf16; reduced precision, so not `value`): products/s, the
-    # product's error against the FP32 spectrum's, and the refined solve to the same tolerance
-    k16 = {}
-    y32 = plan.apply_AtA(x_probe, wl.lam)
-    for mode, name in ((1, "shell_offset_scale"), (2, "plain")):
-        p16 = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
-                        precision=args.precision, lambda_relative=1, khat_bf16=mode)
-        p16.kernel_set(plan.kernel_get())
-        y16 = p16.apply_AtA(x_probe, wl.lam)
-        err16 = (torch.linalg.norm((y16 - y32).double()) / torch.linalg.norm(y32.double())).item()
-        e = [ev() for _ in range(3)]
-        e[0].record()
-        for _ in range(args.apply_reps):
-            p16.apply_AtA(x_probe, wl.lam, y16)
-        e[1].record()
-        _, rep16 = p16.cg_solve(state["atb"], wl.lam, args.tol, args.max_iter)
-        e[2].record()
-        torch.cuda.synchronize()
-        k16[name] = {"applies_per_s": round(args.apply_reps / (e[0].elapsed_time(e[1]) / 1e3), 2),
-                     "product_rel_err_vs_fp32_spectrum": float(f"{err16:.3g}"),
-                     "cg_time_to_tol_s": round(e[1].elapsed_time(e[2]) / 1e3, 4), "cg_iters": rep16["iters"],
-                     "cg_true_rel_res": rep16["true_rel_res"]}
-        p16.close()
-        del y16
-    del y32
-    print(f"16-bit spectrum: {k16}", file=sys.stderr, flush=True)
-
     # the learned preconditioner at the size it was trained at: held-out sets of the N = 64
     # training recipe (the weights were fitted on sets 0 .. 1999), a random right-hand side,
     # the same tolerance; learned PCG includes the inference, Chan PCG its spectrum
@@ -447,6 +422,20 @@ def main():
                 "passes_ms": [round(v, 4) for v in pass_ms],
                 "apply_model_gbs": round(sum(pb) / (sum(pass_ms) / 1e3) / 1e9, 1)}
 
+    # gridding rates (unit: a sample point of the half disk; the k = 0 samples are added in closed
+    # form): each point updates W^3 grid cells; per update the LDS tile is read and written once
+    # (4 + 4 bytes for the real kernel grid, 8 + 8 for the complex A*b grid).  The phases include
+    # the grid's FFTs, about 1% of them
+    W = 7
+    npts = wl.M * (firm.firm_slice_points(N) - 1) // 2
+    lds_peak = 128.0 * 256 * 2.4e9     # B/s: 128 B per clock per CU, 256 CUs, 2.4 GHz
+    gridding = {}
+    for name, ms, lds_b in (("kernel_spread", ph[0], 8), ("backprojection_spread", ph[1], 16)):
+        ups = npts * W ** 3 / (ms / 1e3)
+        gridding[name] = {"points": npts, "points_per_s": float(f"{npts / (ms / 1e3):.4g}"),
+                          "updates_per_s": float(f"{ups:.4g}"), "lds_bytes_per_update": lds_b,
+                          "lds_bound_frac": round(ups * lds_b / lds_peak, 4)}
+
     out = {
         "metric": "A*A applies/s at N=256; time-to-1e-5 residual, learned-PCG vs plain CG",
         "value": round(applies_per_s, 2),
@@ -486,7 +475,7 @@ def main():
         "forward_project_ms": round(fwd_ms, 2),
         "data_rel_residual": round(data_res, 5),
         "images_to_slices_ms": round(img2sl_ms, 2),
-        "khat_bf16": k16,
+        "gridding": gridding,
         "rct": rct,
         "synth_images_ms": round(synth_img_ms, 2),
         "roofline": roofline,
