@@ -12,6 +12,8 @@ precompute, back-projection and the solvers to 1e-5, each checked against the FP
   operator the library solves, its values pinned by the sampled direct sums) is within tol.
 * uneven, 16-bit kernel spectrum (both forms): the product within 1e-3 of the oracle's FP64
   product, and the FP64-refined solve to 1e-5 under the oracle.
+* mid with lambda read literally (1e-2 absolute instead of relative to Ker(0)): plain CG stops at
+  its 3000-iteration limit above 1e-5 (the reading the workloads do not take).
 Tolerances as at full size: sampled values to 1e-5 relative L2 and 1e-5 Ker(0) each.
 """
 import os
@@ -124,8 +126,18 @@ def test_mid_workload_end_to_end(firm):
     plan.kernel_precompute()
     _check_kernel(plan, inp, N)
     _check_backprojection(plan, inp, N, inp.rotations.shape[0], 64)
-    _check_solves(firm, plan, inp, N, _oracle_operator(plan, N, inp.workload.lam), 65)
+    b, _ = _check_solves(firm, plan, inp, N, _oracle_operator(plan, N, inp.workload.lam), 65)
     plan.close()
+    # lambda read literally (1e-2 absolute, about 1e-9 of Ker(0) here): the system is singular to
+    # FP32 working precision and plain CG does not reach 1e-5 within 3000 iterations
+    lit = firm.Plan(N, inp.rotations, shifts=inp.shifts, ctf_group=inp.ctf_group, ctf_table=inp.ctf_table,
+                    precision=1, lambda_relative=0)
+    lit.kernel_precompute()
+    _, rep = lit.cg_solve(b, inp.workload.lam, TOL, 3000)
+    print(f"  literal lambda: status {rep['status']}, {rep['iters']} iterations, true rel res "
+          f"{rep['true_rel_res']:.2e}", flush=True)
+    assert rep["status"] == firm.FIRM_ERR_NOT_CONVERGED and rep["true_rel_res"] > TOL
+    lit.close()
 
 
 def test_uneven_workload_end_to_end_with_16bit_spectra(firm):
