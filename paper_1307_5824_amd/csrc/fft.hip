@@ -51,6 +51,24 @@ struct FftThr {
     static constexpr int value = (LS % 16 == 8) ? FftCfg<LS / 16, double2>::THREADS : FftCfg<LS / 16, float2>::THREADS;
 };
 
+// Pencils per workgroup of the row passes (contiguous rows; the exchange buffer is pencil-major,
+// so the pencil count changes no access pattern).  At L = 512 four pencils (256 threads, 26 KB of
+// LDS with the twiddle table) let six workgroups share a CU where sixteen allowed two: their load,
+// transform and store phases then overlap, and the two row passes of the N = 256 product run 7-8%
+// faster (44.1 -> 40.8 and 47.7 -> 43.8 us, bit-identical results); two pencils are slower again.
+#ifndef FIRM_ROWC512
+#define FIRM_ROWC512 4
+#endif
+template <int L, class V>
+struct RowCfg {
+    static constexpr int C = (L == 512 && sizeof(V) == 8) ? FIRM_ROWC512 : FftCfg<L, V>::C;
+    static constexpr int THREADS = C * L / 8;
+};
+template <int LS>
+struct RowThr {
+    static constexpr int value = (LS % 16 == 8) ? RowCfg<LS / 16, double2>::THREADS : RowCfg<LS / 16, float2>::THREADS;
+};
+
 // waves per SIMD that two workgroups of that size need (the VGPR budget of the middle pass)
 template <int LS>
 struct FftTwoBlocks {
@@ -140,13 +158,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // X_b(q) = (Z(q) - conj Z(L-q)) / 2i; modes q < n_keep are stored.
 // PRO: the rows are p = src + beta * pvec (CG direction update), written back to pvec.
 template <int L, bool PRO, class S, bool HIN>
-__global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
+__global__ void __launch_bounds__(RowThr<L * 16 + (int)sizeof(S)>::value)
 k_rows_r2c(const S* __restrict__ src, int nrows, int in_pitch, int n_in, typename VecOf<S>::V* __restrict__ dst,
            int out_pitch, int n_keep, S sg, const typename VecOf<S>::V* __restrict__ tw, S* pvec,
            const double* beta_dev, const int* active) {
     // HIN: rows zero-padded from L/2 (known at compile time: the first stage's zero inputs fold)
     using V = typename VecOf<S>::V;
-    constexpr int C = FftCfg<L, V>::C, T = L / 8;
+    constexpr int C = RowCfg<L, V>::C, T = L / 8;
     using P = Pen<L, C, true>;
     constexpr bool TWL = sizeof(S) == 4;
     __shared__ V lds[P::LDS];
@@ -219,12 +237,12 @@ struct CgStep {
 // y = scale * x + lam * xadd.  DOT: also a block partial of sum(xadd * y) in FP64.
 // STEP: y is the CG product q, consumed by the CG step (dst unused), partials of ||r||^2.
 template <int L, bool DOT, class S, bool HOUT, bool STEP = false>
-__global__ void __launch_bounds__(FftThr<L * 16 + (int)sizeof(S)>::value)
+__global__ void __launch_bounds__(RowThr<L * 16 + (int)sizeof(S)>::value)
 k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch, S* __restrict__ dst, int out_pitch,
            int n_out, S sg, S scale, S lam, const S* __restrict__ xadd, const typename VecOf<S>::V* __restrict__ tw,
            double* partials, const int* active, CgStep step) {
     using V = typename VecOf<S>::V;
-    constexpr int C = FftCfg<L, V>::C, T = L / 8, NT = FftCfg<L, V>::THREADS;
+    constexpr int C = RowCfg<L, V>::C, T = L / 8, NT = RowCfg<L, V>::THREADS;
     using P = Pen<L, C, true>;
     constexpr bool TWL = sizeof(S) == 4;
     static_assert(P::LDS * sizeof(V) >= (NT / 64) * sizeof(double), "reduction scratch");
@@ -729,7 +747,7 @@ template <int L, bool PRO, class S = float>
 hipError_t launch_r2c(hipStream_t st, const S* src, int nrows, int in_pitch, int n_in, typename VecOf<S>::V* dst,
                       int out_pitch, int n_keep, S sg, const typename VecOf<S>::V* tw, S* pvec = nullptr,
                       const double* beta = nullptr, const int* active = nullptr) {
-    using Cfg = FftCfg<L, typename VecOf<S>::V>;
+    using Cfg = RowCfg<L, typename VecOf<S>::V>;
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_in == L)
         hipLaunchKernelGGL((k_rows_r2c<L, PRO, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
@@ -744,7 +762,7 @@ template <int L, bool DOT, class S = float>
 hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows, int in_pitch, S* dst, int out_pitch,
                       int n_out, S sg, S scale, S lam, const S* xadd, const typename VecOf<S>::V* tw,
                       double* partials = nullptr, const int* active = nullptr) {
-    using Cfg = FftCfg<L, typename VecOf<S>::V>;
+    using Cfg = RowCfg<L, typename VecOf<S>::V>;
     if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_out == L)
@@ -760,7 +778,7 @@ hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows
 template <int L>
 hipError_t launch_c2r_step(hipStream_t st, const float2* src, int nrows, int in_pitch, int out_pitch, const float2* tw,
                            double* partials, const int* active, CgStep step) {
-    using Cfg = FftCfg<L, float2>;
+    using Cfg = RowCfg<L, float2>;
     if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     hipLaunchKernelGGL((k_rows_c2r<L, false, float, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
@@ -1108,7 +1126,7 @@ int fft_apply_cg_partials(firm_plan p) {
 
 namespace {
 template <int L>
-int c2r_blocks_t(int N) { return ceil_div(N * N / 2, FftCfg<L, float2>::C); }
+int c2r_blocks_t(int N) { return ceil_div(N * N / 2, RowCfg<L, float2>::C); }
 }  // namespace
 
 int fft_apply_cg_step_partials(firm_plan p) {
