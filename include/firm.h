@@ -78,6 +78,9 @@ typedef struct {
                              deviation), shell = rounded |q|; 2 = BF16 codes of K^ */
     double inner_tol;     /* precision 1: relative tolerance of each FP32 correction; 0 = 1e-3 */
     void* stream;         /* hipStream_t for all work; NULL = null stream */
+    int stagnation_iters; /* preconditioned solves: restart as plain CG from the current x when the
+                             residual norm has not halved in this many iterations (checked every
+                             check_every iterations); 0 = 300, < 0 = never */
 } firm_options;
 
 typedef struct {

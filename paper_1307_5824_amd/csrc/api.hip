@@ -213,6 +213,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     p->beta = M_PI * std::sqrt((o.kb_width / sig) * (o.kb_width / sig) * (sig - 0.5) * (sig - 0.5) - 0.8);
     p->refine_every = o.refine_every == 0 ? 50 : o.refine_every;
     p->check_every = o.check_every == 0 ? 10 : o.check_every;
+    p->stagnation_iters = o.stagnation_iters == 0 ? 300 : o.stagnation_iters;
     p->stream = (hipStream_t)o.stream;
     p->precision = o.precision;
     p->lambda_relative = o.lambda_relative;

@@ -226,6 +226,8 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
 
     int it_host = 0;
     firm_status result = FIRM_OK;
+    double stag_rr = INFINITY;  // squared residual norm at the last halving
+    int stag_it = 0;            // iteration of the last halving
     for (;;) {
         for (int i = 0; i < p->check_every; ++i) {
             const float* src = pc ? p->z : p->r;
@@ -249,18 +251,41 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
             }
         }
         CK(hipMemcpyAsync(p->host_flags, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        if (pc && p->stagnation_iters > 0)
+            CK(hipMemcpyAsync(p->host_scal, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
         CK(hipStreamSynchronize(st));
-        if (p->host_flags[F_ACTIVE]) continue;
+        // restart as plain CG from the current x (after a breakdown or a stagnation of the
+        // preconditioned recursion)
+        auto restart_plain = [&]() -> hipError_t {
+            pc = false;
+            fell_back = 1;
+            hipError_t e = fft_apply_AtA(p, x, p->tmp, (float)lam);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, nullptr);
+            hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RR, (int)S_RZ,
+                               nullptr);
+            hipLaunchKernelGGL(k_set_active, dim3(1), dim3(1), 0, st, flags, scal, 1);
+            return hipGetLastError();
+        };
+        if (p->host_flags[F_ACTIVE]) {
+            if (pc && p->stagnation_iters > 0) {
+                // stagnation: the residual norm has not halved (its square not quartered) within
+                // stagnation_iters iterations of the last halving
+                const double rr = p->host_scal[S_RR];
+                const int it = p->host_flags[F_ITER];
+                if (rr <= 0.25 * stag_rr) {
+                    stag_rr = rr;
+                    stag_it = it;
+                } else if (it - stag_it >= p->stagnation_iters) {
+                    CK(restart_plain());
+                }
+            }
+            continue;
+        }
         const int reason = p->host_flags[F_REASON];
         if (reason == R_BREAK) {
-            if (pc) {  // restart as plain CG from the current x
-                pc = false;
-                fell_back = 1;
-                CK(fft_apply_AtA(p, x, p->tmp, (float)lam));
-                hipLaunchKernelGGL(k_resid, dim3(VB), dim3(VT), 0, st, atb, p->tmp, p->r, n, p->partials3, nullptr);
-                hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_RR,
-                                   (int)S_RZ, nullptr);
-                hipLaunchKernelGGL(k_set_active, dim3(1), dim3(1), 0, st, flags, scal, 1);
+            if (pc) {
+                CK(restart_plain());
                 continue;
             }
             result = FIRM_ERR_BREAKDOWN;

@@ -17,6 +17,8 @@ struct firm_plan_s {
     int kbw = 7;
     double beta = 0.0;
     int refine_every = 50, check_every = 10;
+    int stagnation_iters = 300;  // preconditioned solves: plain-CG restart after this many iterations
+                                 // without a halving of the residual norm (<= 0: never)
     int precision = 0;          // 0 FP32 CG, 1 FP64 iterative refinement, 2 FP64 CG
     int lambda_relative = 0;    // lambda multiplies Ker(0)
     double inner_tol = 1e-3;    // relative tolerance of each FP32 correction (precision 1)

@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "FIRM_OK", 1: "FIRM_ERR_ARG", 2: "FIRM_ERR_ALLOC", 3: "FIRM_E
 class FirmOptions(ctypes.Structure):
     _fields_ = [("kb_width", ctypes.c_int), ("refine_every", ctypes.c_int), ("check_every", ctypes.c_int),
                 ("precision", ctypes.c_int), ("lambda_relative", ctypes.c_int), ("khat_bf16", ctypes.c_int),
-                ("inner_tol", ctypes.c_double), ("stream", ctypes.c_void_p)]
+                ("inner_tol", ctypes.c_double), ("stream", ctypes.c_void_p), ("stagnation_iters", ctypes.c_int)]
 
 
 class FirmCgReport(ctypes.Structure):
@@ -146,7 +146,7 @@ def _current_stream():
 
 def firm_plan_create(N, rotations, shifts=None, ctf_group=None, ctf_table=None, kb_width=0,
                      refine_every=0, check_every=0, stream=None, precision=0, lambda_relative=0, inner_tol=0.0,
-                     khat_bf16=0):
+                     khat_bf16=0, stagnation_iters=0):
     """Returns a raw plan handle (c_void_p); see Plan for the managed form."""
     rot, rotp = _host(np.asarray(rotations, dtype=np.float64).reshape(-1, 9), np.float64)
     M = rot.shape[0]
@@ -155,7 +155,7 @@ def firm_plan_create(N, rotations, shifts=None, ctf_group=None, ctf_table=None, 
     tab, tabp = _host(ctf_table, np.float32)
     G = 0 if tab is None else (tab.shape[0] if tab.ndim == 2 else 1)
     opt = FirmOptions(kb_width, refine_every, check_every, precision, lambda_relative, int(khat_bf16), inner_tol,
-                      stream)
+                      stream, int(stagnation_iters))
     h = ctypes.c_void_p()
     _check(lib.firm_plan_create(ctypes.byref(h), int(N), int(M), rotp, shp, grpp, int(G), tabp, ctypes.byref(opt)))
     return h
@@ -166,14 +166,14 @@ class Plan:
 
     def __init__(self, N, rotations, shifts=None, ctf_group=None, ctf_table=None, kb_width=0,
                  refine_every=0, check_every=0, stream=None, precision=0, lambda_relative=0, inner_tol=0.0,
-                 khat_bf16=0):
+                 khat_bf16=0, stagnation_iters=0):
         import torch
         self.N = int(N)
         self.M = int(np.asarray(rotations).reshape(-1, 9).shape[0])
         self.P = firm_slice_points(self.N)
         s = stream if stream is not None else _current_stream()
         self.h = firm_plan_create(N, rotations, shifts, ctf_group, ctf_table, kb_width, refine_every,
-                                  check_every, s, precision, lambda_relative, inner_tol, khat_bf16)
+                                  check_every, s, precision, lambda_relative, inner_tol, khat_bf16, stagnation_iters)
         self._torch = torch
 
     def close(self):

@@ -341,6 +341,32 @@ def test_pcg_breakdown_falls_back_to_cg(firm):
     assert np.linalg.norm(res) / np.linalg.norm(b) <= 1.5e-4
 
 
+def test_pcg_stagnation_falls_back_to_cg(firm):
+    """A preconditioner that makes progress too slowly (a random diagonal spanning seven decades)
+    trips the stagnation test (forced from the host with a 20-iteration window): the solver
+    restarts as plain CG from the current iterate and reaches the tolerance (oracle residual).
+    With the test switched off the same solve keeps the preconditioner to its iteration limit."""
+    N, M = 16, 30
+    R, _, _, _ = small_geometry(N, M, 76)
+    Ker = ofirm.kernel_direct(N, R).real
+    lam = 0.1 * float(Ker[N - 1, N - 1, N - 1])
+    rng = np.random.default_rng(13)
+    d = dev(10.0 ** rng.uniform(-7.0, 0.0, (N, N, N)))
+    b = rng.standard_normal((N, N, N))
+    plan = firm.Plan(N, R, stagnation_iters=20)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    x, rep = plan.cg_solve(dev(b), lam, 1e-4, 1000, precond=d)
+    print(f"stagnation fallback: {rep['iters']} iterations, fell_back {rep['fell_back']}", flush=True)
+    assert rep["status"] == 0 and rep["fell_back"] == 1
+    xr = host(x).astype(np.float64)
+    res = b - (ofirm.toeplitz_apply_fft(Ker, xr).real + lam * xr)
+    assert np.linalg.norm(res) / np.linalg.norm(b) <= 1.5e-4
+    off = firm.Plan(N, R, stagnation_iters=-1)
+    off.kernel_set(dev(ker_to_centred(Ker, N)))
+    _, rep2 = off.cg_solve(dev(b), lam, 1e-4, rep["iters"], precond=d)
+    assert rep2["fell_back"] == 0
+
+
 def test_pcg_iterates_match_oracle(firm):
     """PCG with a non-trivial even diagonal (the inverse of T. Chan's circulant) against the
     oracle's FP64 PCG, 10 steps, within the FP32 rounding envelope of that recursion."""
