@@ -160,10 +160,11 @@ firm_status firm_forward_project(firm_plan plan, const float* V_dev, void* b_dev
  * FIRM_ERR_STATE if no kernel exists; FIRM_ERR_ARG if lambda < 0. */
 firm_status firm_apply_AtA(firm_plan plan, const float* x_dev, float* y_dev, double lambda);
 
-/* Instrumented firm_apply_AtA: runs it reps times with HIP events between its five FFT
- * passes on the plan stream (rows along i3 with padding; columns along i2; the fused
- * multiply pass along i1; inverse along i2; inverse along i3 with crop and lambda x) and
- * writes their average durations in ms to pass_ms[5] (host).  Synchronises. */
+/* Instrumented firm_apply_AtA: runs it reps times on the plan stream, each of its five FFT
+ * passes (rows along i3 with padding; columns along i2; the fused multiply pass along i1;
+ * inverse along i2; inverse along i3 with crop and lambda x) launched with a pair of HIP
+ * events in its own dispatch (hipExtLaunchKernelGGL), and writes the passes' average kernel
+ * durations in ms to pass_ms[5] (host).  Synchronises after every product. */
 firm_status firm_apply_AtA_timed(firm_plan plan, const float* x_dev, float* y_dev, double lambda, int reps,
                                  float* pass_ms);
 

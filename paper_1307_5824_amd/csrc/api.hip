@@ -516,20 +516,20 @@ firm_status firm_apply_AtA_timed(firm_plan p, const float* x, float* y, double l
     if (reps < 1) return firm_fail(p, FIRM_ERR_ARG, "reps must be >= 1");
     if (!(lambda >= 0.0) || !std::isfinite(lambda)) return firm_fail(p, FIRM_ERR_ARG, "lambda must be finite and >= 0");
     if (!p->have_kernel) return firm_fail(p, FIRM_ERR_STATE, "no kernel: call firm_kernel_precompute or firm_kernel_set");
-    hipEvent_t ev[6];
-    for (int i = 0; i < 6; ++i) FIRM_HIP(p, hipEventCreate(&ev[i]));
+    hipEvent_t ev[10];
+    for (int i = 0; i < 10; ++i) FIRM_HIP(p, hipEventCreate(&ev[i]));
     double acc[5] = {0, 0, 0, 0, 0};
     hipError_t e = hipSuccess;
     for (int r = 0; r < reps && e == hipSuccess; ++r) {
         e = fft_apply_AtA_events(p, x, y, (float)lambda_eff(p, lambda), ev);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[9]);
         for (int i = 0; i < 5 && e == hipSuccess; ++i) {
             float ms = 0.f;
-            e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+            e = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
             acc[i] += ms;
         }
     }
-    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i < 10; ++i) (void)hipEventDestroy(ev[i]);
     if (e != hipSuccess) return firm_fail(p, FIRM_ERR_HIP, std::string("timed apply: ") + hipGetErrorString(e));
     for (int i = 0; i < 5; ++i) pass_ms[i] = (float)(acc[i] / reps);
     return FIRM_OK;

@@ -7,8 +7,9 @@
 //     accumulated in FP64 (per-block partials, then a one-block reduction) and
 //     the scalars alpha, beta and the residual norms live in FP64 on the device,
 //     so an iteration needs no host round trip.  The direction update
-//     p = z + beta p is fused into the first FFT pass of the product and <p, q>
-//     into its last pass.  Every refine_every iterations the recursive residual
+//     p = z + beta p is fused into the first FFT pass of the product, <p, q> into
+//     its middle pass (Parseval over the spectrum) and the step x += alpha p,
+//     r -= alpha q with ||r||^2 into its last pass.  Every refine_every iterations the recursive residual
 //     is replaced by the residual recomputed from the FP32 product.  The host
 //     reads a small flag block every check_every iterations; kernels enqueued
 //     after convergence see the flag and exit.
@@ -34,22 +35,30 @@ enum { R_RUN = 0, R_CONV = 1, R_MAXIT = 2, R_BREAK = 3 };
 
 constexpr int VB = 1024;  // blocks of the vector kernels
 constexpr int VT = 256;
+constexpr int RT = 1024;  // threads of the one-block sums that form alpha and beta
 
+// block sum of a double over NT threads; result valid in thread 0
+template <int NT = VT>
 __device__ __forceinline__ double block_reduce(double v) {
-    __shared__ double red[VT / 64];
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    __shared__ double red[NT / 64];
+    v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
     if (threadIdx.x == 0)
-        for (int i = 0; i < VT / 64; ++i) s += red[i];
+        for (int i = 0; i < NT / 64; ++i) s += red[i];
     return s;
 }
 
+// sum of n block partials by one block of NT threads; the unrolled loop has a thread's loads
+// in flight together (the partials were just written by the blocks of another kernel, so each
+// load waits on the memory behind L2)
+template <int NT = VT>
 __device__ __forceinline__ double sum_partials(const double* part, int n) {
     double a = 0.0;
-    for (int i = threadIdx.x; i < n; i += VT) a += part[i];
-    return block_reduce(a);
+#pragma unroll 8
+    for (int i = threadIdx.x; i < n; i += NT) a += part[i];
+    return block_reduce<NT>(a);
 }
 
 // r = atb - y in FP64, stored FP32; partial sums of r^2.
@@ -98,9 +107,9 @@ __global__ void k_init(double* scal, int* flags, double tol, int max_iter) {
     flags[F_REASON] = done ? (max_iter <= 0 && scal[S_RR] > scal[S_TOL2] ? R_MAXIT : R_CONV) : R_RUN;
 }
 
-__global__ void __launch_bounds__(VT) k_alpha(const double* part, int n, double* scal, int* flags) {
+__global__ void __launch_bounds__(RT) k_alpha(const double* part, int n, double* scal, int* flags) {
     if (flags[F_ACTIVE] == 0) return;
-    const double pq = sum_partials(part, n);
+    const double pq = sum_partials<RT>(part, n);
     if (threadIdx.x == 0) {
         scal[S_PQ] = pq;
         const double a = scal[S_RZ] / pq;
@@ -114,12 +123,12 @@ __global__ void __launch_bounds__(VT) k_alpha(const double* part, int n, double*
 }
 
 // rr = ||r||^2, rz = <r, z> (= rr without preconditioner), beta = rz_new / rz_old, stop tests.
-__global__ void __launch_bounds__(VT) k_beta(const double* part_rr, int n_rr, const double* part_rz, int n_rz,
+__global__ void __launch_bounds__(RT) k_beta(const double* part_rr, int n_rr, const double* part_rz, int n_rz,
                                              double* scal, int* flags) {
     if (flags[F_ACTIVE] == 0) return;
-    const double rr = sum_partials(part_rr, n_rr);
+    const double rr = sum_partials<RT>(part_rr, n_rr);
     __syncthreads();
-    const double rz = part_rz ? sum_partials(part_rz, n_rz) : rr;
+    const double rz = part_rz ? sum_partials<RT>(part_rz, n_rz) : rr;
     if (threadIdx.x == 0) {
         const double b = rz / scal[S_RZ];
         scal[S_RR] = rr;
@@ -234,10 +243,10 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
             // p = src + beta p and q = (A*A + lam) p, with alpha = rz / <p, q> formed between the
             // two halves of the product and the step x += alpha p, r -= alpha q in its last pass
             CK(fft_apply_cg_front(p, src, p->p, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
-            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(VT), 0, st, p->partials, nb_apply, scal, flags);
+            hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RT), 0, st, p->partials, nb_apply, scal, flags);
             CK(fft_apply_cg_step(p, x, p->p, p->r, scal + S_ALPHA, flags + F_ACTIVE, p->partials3));
             if (pc) CK(fft_precond(p, p->dhalf, p->r, p->z, flags + F_ACTIVE, p->partials2));
-            hipLaunchKernelGGL(k_beta, dim3(1), dim3(VT), 0, st, p->partials3, nb_step, pc ? p->partials2 : nullptr,
+            hipLaunchKernelGGL(k_beta, dim3(1), dim3(RT), 0, st, p->partials3, nb_step, pc ? p->partials2 : nullptr,
                                nb_prec, scal, flags);
             ++it_host;
             if (p->refine_every > 0 && it_host % p->refine_every == 0) {

@@ -6,12 +6,37 @@
 // straight from HBM and stores its 8 results straight back, so zero padding,
 // cropping, mode selection, the kernel multiply and the CG vector work sit in
 // the loads and stores.
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #include "fft_core.h"
 #include "firm_internal.h"
 
 namespace {
+
+// Kernel-attached timing of the product's passes: when the calling thread has armed a pair of
+// events, the next pass launch carries them in its dispatch (hipExtLaunchKernelGGL), so they
+// hold that kernel's own start and end, without the gaps between launches that events
+// recorded on the stream between passes would add.
+thread_local hipEvent_t tl_pass_ev[2] = {nullptr, nullptr};
+
+#define FIRM_PASS_LAUNCH(K, G, B, ST, ...)                                              \
+    do {                                                                                \
+        if (tl_pass_ev[0]) {                                                            \
+            hipExtLaunchKernelGGL(K, G, B, 0, ST, tl_pass_ev[0], tl_pass_ev[1], 0, __VA_ARGS__); \
+            tl_pass_ev[0] = tl_pass_ev[1] = nullptr;                                    \
+        } else {                                                                        \
+            hipLaunchKernelGGL(K, G, B, 0, ST, __VA_ARGS__);                            \
+        }                                                                               \
+    } while (0)
+
+// arm the timing events of the next pass launch (no-op for ev == nullptr)
+inline void arm_pass_events(hipEvent_t* ev, int pass) {
+    if (!ev) return;
+    tl_pass_ev[0] = ev[2 * pass];
+    tl_pass_ev[1] = ev[2 * pass + 1];
+}
 
 template <class S> struct VecOf;
 template <> struct VecOf<float> { using V = float2; };
@@ -142,7 +167,7 @@ __device__ __forceinline__ void st_nt(const T& v, T* p) {
 // Block sum of a double; result valid in thread 0.
 template <int THREADS>
 __device__ __forceinline__ double block_sum(double v, double* red) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    v = wave_sum(v);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0) red[w] = v;
     __syncthreads();
@@ -713,16 +738,20 @@ k_mid(typename VecOf<S>::V* __restrict__ data, const void* __restrict__ specv, c
     }
     if constexpr (DOT) {  // pencils that do not exist hold zeros
         double acc = (double)acc8 * ((col == 0 || col == ncols - 1) ? 1.0 : 2.0);
-        for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+        acc = wave_sum(acc);
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-        __syncthreads();
+    }
+    fft_reg<L, C, false>(v, lds, twp, (S)1);
+    if constexpr (DOT) {
+        // the inverse transform's LDS exchanges (lengths of 16 and more) put barriers between
+        // every wave's partial and this read, so the block sum needs no barrier of its own
+        if constexpr (L < 16) __syncthreads();
         if (threadIdx.x == 0) {
             double sum = 0.0;
             for (int w = 0; w < P::NT / 64; ++w) sum += red[w];
             dotp[blockIdx.x] = sum;
         }
     }
-    fft_reg<L, C, false>(v, lds, twp, (S)1);
     if (!valid) return;
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
@@ -750,10 +779,10 @@ hipError_t launch_r2c(hipStream_t st, const S* src, int nrows, int in_pitch, int
     using Cfg = RowCfg<L, typename VecOf<S>::V>;
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_in == L)
-        hipLaunchKernelGGL((k_rows_r2c<L, PRO, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
+        FIRM_PASS_LAUNCH((k_rows_r2c<L, PRO, S, true>), dim3(blocks), dim3(Cfg::THREADS), st, src, nrows, in_pitch,
                            n_in, dst, out_pitch, n_keep, sg, tw, pvec, beta, active);
     else
-        hipLaunchKernelGGL((k_rows_r2c<L, PRO, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+        FIRM_PASS_LAUNCH((k_rows_r2c<L, PRO, S, false>), dim3(blocks), dim3(Cfg::THREADS), st, src, nrows,
                            in_pitch, n_in, dst, out_pitch, n_keep, sg, tw, pvec, beta, active);
     return hipGetLastError();
 }
@@ -766,10 +795,10 @@ hipError_t launch_c2r(hipStream_t st, const typename VecOf<S>::V* src, int nrows
     if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
     if (2 * n_out == L)
-        hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows, in_pitch,
+        FIRM_PASS_LAUNCH((k_rows_c2r<L, DOT, S, true>), dim3(blocks), dim3(Cfg::THREADS), st, src, nrows, in_pitch,
                            dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active, CgStep{});
     else
-        hipLaunchKernelGGL((k_rows_c2r<L, DOT, S, false>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+        FIRM_PASS_LAUNCH((k_rows_c2r<L, DOT, S, false>), dim3(blocks), dim3(Cfg::THREADS), st, src, nrows,
                            in_pitch, dst, out_pitch, n_out, sg, scale, lam, xadd, tw, partials, active, CgStep{});
     return hipGetLastError();
 }
@@ -781,7 +810,7 @@ hipError_t launch_c2r_step(hipStream_t st, const float2* src, int nrows, int in_
     using Cfg = RowCfg<L, float2>;
     if (nrows < 2 || nrows % 2) return hipErrorInvalidValue;  // whole row pairs (the kernel loads the last one)
     const int blocks = ceil_div(nrows / 2, Cfg::C);
-    hipLaunchKernelGGL((k_rows_c2r<L, false, float, true, true>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, nrows,
+    FIRM_PASS_LAUNCH((k_rows_c2r<L, false, float, true, true>), dim3(blocks), dim3(Cfg::THREADS), st, src, nrows,
                        in_pitch, (float*)nullptr, out_pitch, L / 2, 1.f, 1.f, 0.f, (const float*)nullptr, tw, partials,
                        active, step);
     return hipGetLastError();
@@ -799,15 +828,15 @@ hipError_t launch_cols(hipStream_t st, const typename VecOf<S>::V* src, void* ds
     if (s_group < 0) s_group = (int64_t)Cfg::C * s_col;
     if (d_group < 0) d_group = (int64_t)Cfg::C * d_col;
     if (MAP == MAP_FIRST && EPI == EPI_STORE && 2 * n_in == L)
-        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 1>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+        FIRM_PASS_LAUNCH((k_cols<L, CONTIG, MAP, EPI, S, 1>), dim3(blocks), dim3(Cfg::THREADS), st, src, dst,
                            ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
                            tw, ep, active);
     else if (MAP == MAP_FIRST && EPI == EPI_STORE && 2 * n_out == L)
-        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 2>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+        FIRM_PASS_LAUNCH((k_cols<L, CONTIG, MAP, EPI, S, 2>), dim3(blocks), dim3(Cfg::THREADS), st, src, dst,
                            ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
                            tw, ep, active);
     else
-        hipLaunchKernelGGL((k_cols<L, CONTIG, MAP, EPI, S, 0>), dim3(blocks), dim3(Cfg::THREADS), 0, st, src, dst,
+        FIRM_PASS_LAUNCH((k_cols<L, CONTIG, MAP, EPI, S, 0>), dim3(blocks), dim3(Cfg::THREADS), st, src, dst,
                            ncols, s_outer, s_col, s_elem, d_outer, d_col, d_elem, s_group, d_group, n_in, n_out, sg,
                            tw, ep, active);
     return hipGetLastError();
@@ -828,7 +857,7 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
     if constexpr (sizeof(S) == 4) k16 = spec16 != nullptr;
     const bool half = 2 * n_in == L, dot = dotp != nullptr;
 #define FIRM_MID(H, K, D)                                                                                      \
-    hipLaunchKernelGGL((k_mid<L, S, H, K, D>), dim3(blocks), dim3(Cfg::THREADS), 0, st, data, sp, shtab, kadd, \
+    FIRM_PASS_LAUNCH((k_mid<L, S, H, K, D>), dim3(blocks), dim3(Cfg::THREADS), st, data, sp, shtab, kadd, \
                        nouter, ncols, s_outer, s_elem, s_group, n_in, tw, active, dotp)
     if (k16) {
         if constexpr (sizeof(S) == 4) {
@@ -868,28 +897,27 @@ hipError_t apply_front(firm_plan p, const float* src, float* pvec, float lam, co
                        double* dotp, hipEvent_t* ev) {
     const int N = L / 2, QP = p->QP;
     hipStream_t st = p->stream;
-    if (ev) RET_IF(hipEventRecord(ev[0], st));
     // A: rows along i3, N real -> padded 2N transform, modes 0..N kept
+    arm_pass_events(ev, 0);
     if (beta)
         RET_IF((launch_r2c<L, true>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw, pvec, beta, active)));
     else
         RET_IF((launch_r2c<L, false>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw)));
-    if (ev) RET_IF(hipEventRecord(ev[1], st));
     // T2 is blocked [q2][q3 group][i1][C] (C = the pencils per workgroup), so that every pencil
     // group of the middle pass is one contiguous block
     constexpr int C = FftCfg<L, float2>::C;
     const int64_t ng = (N + 1 + C - 1) / C, sg_ = (int64_t)N * C, se_ = ng * (int64_t)N * C;
     // B: along i2 for every (i1, q3): T1[i1][i2][q3] (N) -> T2[q2][g][i1][c] (2N)
+    arm_pass_events(ev, 1);
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T1, p->T2, N, N + 1, (int64_t)N * QP, 1, QP, C, 1,
                                                           se_, N, L, -1.f, p->tw, EpiArgs(), active, -1, sg_)));
-    if (ev) RET_IF(hipEventRecord(ev[2], st));
     // C: along i1 for every (q2, q3): forward, times K^ + lam / L^3, inverse, keep i1 < N.
     // With the unnormalised inverse the lam term adds exactly lam x to the cropped output, so
     // that pass E need not read x
     const float kadd = lam / ((float)L * L * L);
+    arm_pass_events(ev, 2);
     RET_IF((launch_mid<L>(st, p->T2, p->khat, L, N + 1, se_, C, N, p->tw, active, sg_, kadd,
                           p->khat_bf16 ? p->khat16 : nullptr, p->khat_bf16 == 1 ? p->shtab : nullptr, dotp)));
-    if (ev) RET_IF(hipEventRecord(ev[3], st));
     return hipSuccess;
 }
 
@@ -901,16 +929,16 @@ hipError_t apply_back(firm_plan p, float* y, const int* active, const CgStep* st
     constexpr int C = FftCfg<L, float2>::C;
     const int64_t ng = (N + 1 + C - 1) / C, sg_ = (int64_t)N * C, se_ = ng * (int64_t)N * C;
     // D: inverse along q2, keep i2 < N: T2[q2][g][i1][c] -> T1[i1][i2][q3]
+    arm_pass_events(ev, 3);
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->T2, p->T1, N, N + 1, C, 1, se_, (int64_t)N * QP, 1,
                                                           QP, L, N, 1.f, p->tw, EpiArgs(), active, sg_, -1)));
-    if (ev) RET_IF(hipEventRecord(ev[4], st));
     // E: inverse along q3 (half spectrum -> real), crop; CG form: the CG step instead of a store
+    arm_pass_events(ev, 4);
     if (step)
         RET_IF(launch_c2r_step<L>(st, p->T1, N * N, QP, N, p->tw, partials, active, *step));
     else
         RET_IF((launch_c2r<L, false>(st, p->T1, N * N, QP, y, N, N, 1.f, 1.f, 0.f, (const float*)nullptr, p->tw,
                                      nullptr, active)));
-    if (ev) RET_IF(hipEventRecord(ev[5], st));
     return hipSuccess;
 }
 
@@ -1159,9 +1187,17 @@ hipError_t fft_apply_AtA(firm_plan p, const float* x, float* y, float lam) {
     return hipErrorInvalidValue;
 }
 
-hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev) {
+namespace {
+hipError_t apply_events_dispatch(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev) {
     DISPATCH_L(2 * p->N, apply_passes, p, x, y, lam, ev);
     return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev) {
+    const hipError_t e = apply_events_dispatch(p, x, y, lam, ev);
+    tl_pass_ev[0] = tl_pass_ev[1] = nullptr;  // a pass that failed before its launch leaves none armed
+    return e;
 }
 
 hipError_t fft_apply_cg_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta_dev,

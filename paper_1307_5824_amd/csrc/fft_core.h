@@ -16,6 +16,28 @@
 #define FIRM_TWN 1024
 #endif
 
+// Sum of a double over the 64 lanes of a wavefront (all lanes active), returned in every
+// lane.  The lanes are combined with DPP moves, which run on the vector ALU, instead of LDS
+// permutes: pairs and quads by quad permutes, the four quads of each 16-lane row by two row
+// rotations (every lane then holds its row's sum), the four rows by reading one lane of each.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x124>(v);  // row_ror:4
+    v += dpp_f64<0x128>(v);  // row_ror:8
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 // complex helpers for float2 and double2
 template <class V> struct CxT;
 template <> struct CxT<float2> { using S = float; };

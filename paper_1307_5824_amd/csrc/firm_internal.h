@@ -115,6 +115,7 @@ hipError_t kernel_features(firm_plan p, float lam_rel, int res, float* feat);
 hipError_t probe_accumulate(firm_plan p, const float2* zh, const float2* uh, float* A, float* B, double* partials,
                             int nblocks);
 hipError_t synth_normals(firm_plan p, uint64_t seed, uint64_t offset, int64_t n, float* out);
+// ev: 10 events, a start/end pair per pass carried by that pass's own dispatch
 hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam, hipEvent_t* ev);
 hipError_t fft_khat_from_kerc(firm_plan p, float2* w1);        // kerc -> khat (w1: [2N][2N][QP])
 hipError_t fft_ker_grid(firm_plan p, const float* grid, float2* h1, float2* h2, float* chalf);
