@@ -123,18 +123,21 @@ def net_forward(f, params, emulate_bf16=False):
 
 def net_backward(do, params, cache, emulate_bf16=False):
     """Gradients of sum(do * o) with respect to the parameters (and the input features).
-    emulate_bf16: the data gradients through the C -> C layers use bfloat16 copies of the incoming
-    gradient and of the weights, as the GPU's matrix cores do; weight gradients stay full precision."""
+    emulate_bf16: the C -> C layers' gradients read bfloat16 operands, as the GPU's matrix cores
+    do: the data gradient bfloat16 copies of the incoming gradient and of the weights, the weight
+    and bias gradients bfloat16 copies of the incoming gradient and of the layer's input (the
+    sums themselves are exact here)."""
     grads = [None] * len(params)
     g = do[None]
     for i in range(len(params) - 1, -1, -1):
         h, z = cache[i]
         if i < len(params) - 1:
             g = g * (z > 0)
-        _, dw, db = conv3d_backward(h, params[i][0], g)
         if emulate_bf16 and i in MFMA_LAYERS:
+            _, dw, db = conv3d_backward(bf16(h), params[i][0], bf16(g))
             dx, _, _ = conv3d_backward(h, bf16(params[i][0]), bf16(g))
         else:
+            _, dw, db = conv3d_backward(h, params[i][0], g)
             dx, _, _ = conv3d_backward(h, params[i][0], g)
         grads[i] = (dw, db)
         g = dx

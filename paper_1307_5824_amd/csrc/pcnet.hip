@@ -10,8 +10,9 @@
 // Layers c2, c3 (C -> C) are implicit GEMMs on the matrix cores: one wavefront computes a
 // 32-voxel row segment x 32 output channels tile with v_mfma_f32_32x32x16_bf16 (BF16 operands, FP32
 // accumulation), K = 27 taps x C input channels; forward and backward-data share the kernel
-// (the backward uses the transposed weights and the mirrored taps).  c1, c4, the weight
-// gradients and Adam run on the vector ALUs in FP32.  Activations are channel-last
+// (the backward uses the transposed weights and the mirrored taps); their weight gradients are
+// GEMMs over the voxels on the same instruction.  c1, c4, their weight gradients and Adam run on
+// the vector ALUs in FP32.  Activations are channel-last
 // [batch][voxel][C], stored in FP32 and as BF16 copies for the matrix cores.
 #include <algorithm>
 #include <cmath>
@@ -206,6 +207,103 @@ __global__ void __launch_bounds__(CH * CI) k_wgrad(const float* __restrict__ gz,
     }
     unsafeAtomicAdd(&dw[(co * CI + ci) * 27 + tap], acc);
     if (tap == 0 && ci == 0) unsafeAtomicAdd(&db[co], accb);
+}
+
+// Weight gradients of the C -> C layers on the matrix cores: for every tap a GEMM over the voxels,
+//   dW[co][ci][tap] += sum_v gz[b][v][co] x[b][v + off(tap)][ci],   db[co] += sum_v gz[b][v][co],
+// with the BF16 copies of gz and x that the layers' MFMA passes use (FP32 accumulation).
+// Block: 9 wavefronts; wavefront w takes the neighbour row (da, db) = (w / 3 - 1, w % 3 - 1) and
+// its three taps 3 w + c (dc = c - 1), one 32 x 32 accumulator each (A[i][k] = gz[k][co = i],
+// B[k][j] = x[k + off][ci = j], K = voxels, 16 per instruction).  The block walks its rows
+// (b, v1, v2, 32-voxel segment); per row, gz's 32 voxels and each wavefront's neighbour row with
+// one voxel of halo at either end (periodic) are staged in LDS in their global [voxel][channel]
+// layout, and the operands gather 8 voxels of one channel.  The next row's global loads are
+// issued before the current row's products, so that their latency overlaps them.
+constexpr int WG_WAVES = 9;
+constexpr int WG_XCH = 34 * CH / 8;  // 16-byte chunks of a neighbour row with its halo
+
+__global__ void __launch_bounds__(64 * WG_WAVES) k_wgrad_mfma(const __bf16* __restrict__ gz,
+                                                             const __bf16* __restrict__ x, float* __restrict__ dw,
+                                                             float* __restrict__ db, int B, int g,
+                                                             int rows_per_block) {
+    __shared__ bf8_t gzs[32 * CH / 8];             // [voxel][channel], 2 KB
+    __shared__ bf8_t xs[WG_WAVES][WG_XCH];         // [wave][halo voxel p][channel], 19.1 KB
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int da = wave / 3 - 1, dbb = wave % 3 - 1;
+    const int segs = g / 32;
+    const int64_t rows = (int64_t)B * g * g * segs;
+    const int64_t GV = (int64_t)g * g * g;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+    // this thread's staging chunks of a row: gz chunk threadIdx.x (< 128), halo chunks l + 64 q
+    bf8_t pg = {}, px[3] = {};
+    auto fetch = [&](int64_t row) {
+        const int seg = (int)(row % segs);
+        const int64_t r2 = row / segs;
+        const int b = (int)(r2 / ((int64_t)g * g)), v1 = (int)((r2 / g) % g), v2 = (int)(r2 % g), s0 = 32 * seg;
+        const __bf16* xb = x + (int64_t)b * GV * CH;
+        if (threadIdx.x < 32 * CH / 8) {
+            const int v = threadIdx.x / (CH / 8), c8 = threadIdx.x % (CH / 8);
+            pg = *reinterpret_cast<const bf8_t*>(gz + ((int64_t)b * GV + ((int64_t)v1 * g + v2) * g + s0 + v) * CH +
+                                                 8 * c8);
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int c = l + 64 * q;
+            if (c < WG_XCH) {
+                const int p = c / (CH / 8), c8 = c % (CH / 8);
+                px[q] = *reinterpret_cast<const bf8_t*>(xb + (int64_t)vox(v1 + da, v2 + dbb, s0 - 1 + p, g) * CH +
+                                                        8 * c8);
+            }
+        }
+    };
+    f16_t acc0 = {}, acc1 = {}, acc2 = {};
+    float accb = 0.f;
+    const int i = l & 31, kb = l >> 5;
+    const __bf16* gzl = reinterpret_cast<const __bf16*>(gzs);
+    const __bf16* xl = reinterpret_cast<const __bf16*>(xs[wave]);
+    if (r0 < r1) fetch(r0);
+    for (int64_t row = r0; row < r1; ++row) {
+        __syncthreads();  // every wavefront has read the previous row's operands
+        if (threadIdx.x < 32 * CH / 8) gzs[threadIdx.x] = pg;
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+            if (l + 64 * q < WG_XCH) xs[wave][l + 64 * q] = px[q];
+        __syncthreads();
+        if (row + 1 < r1) fetch(row + 1);
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int k0 = 16 * kk + 8 * kb;
+            bf8_t a;
+            __bf16 xv[10];  // voxels k0 .. k0 + 9 of the halo row: the three taps' operands overlap
+#pragma unroll
+            for (int t = 0; t < 8; ++t) a[t] = gzl[(k0 + t) * CH + i];
+#pragma unroll
+            for (int t = 0; t < 10; ++t) xv[t] = xl[(k0 + t) * CH + i];
+            bf8_t b0, b1, b2;
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                b0[t] = xv[t];
+                b1[t] = xv[t + 1];
+                b2[t] = xv[t + 2];
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b1, acc1, 0, 0, 0);
+            acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b2, acc2, 0, 0, 0);
+        }
+        if (wave == 0 && l < CH)
+            for (int v = 0; v < 32; ++v) accb += (float)gzl[v * CH + l];
+    }
+    // D[i][j]: j = l % 32 (ci), i = 8 (t / 4) + 4 (l / 32) + t % 4 (co)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int co = 8 * (t / 4) + 4 * kb + (t % 4);
+        float* d = dw + (co * CH + i) * 27 + 3 * wave;
+        unsafeAtomicAdd(d, acc0[t]);
+        unsafeAtomicAdd(d + 1, acc1[t]);
+        unsafeAtomicAdd(d + 2, acc2[t]);
+    }
+    if (wave == 0 && l < CH) unsafeAtomicAdd(&db[l], accb);
 }
 
 // dW4[ci][tap] = sum go[b][v] h3[b][v + off][ci]; db4 = sum go.  Block: one tap, chunk; thread = ci.
@@ -656,13 +754,16 @@ firm_status firm_pcnet_loss_grad(firm_pcnet n, const float* feat, int res, int B
                        n->grad + OFF_B4, B, 256, g);
     hipLaunchKernelGGL(k_conv_last_bwd, dim3(nblk((int64_t)B * GV)), dim3(256), 0, st, n->go, n->prm + OFF_W4,
                        n->h3, n->gz, n->gzb, B, g);
-    hipLaunchKernelGGL((k_wgrad<CH>), dim3(chunks, 27), dim3(CH * CH), 0, st, n->gz, n->h2, n->grad + OFF_W3,
-                       n->grad + OFF_B3, B, 256, g);
     const int64_t rows = (int64_t)B * g * g * (g / 32);
+    // weight gradients of the C -> C layers: about 512 workgroups (two per CU), each over a run of rows
+    const int rpb = (int)((rows + 511) / 512);
+    const unsigned wblocks = (unsigned)((rows + rpb - 1) / rpb);
+    hipLaunchKernelGGL(k_wgrad_mfma, dim3(wblocks), dim3(64 * WG_WAVES), 0, st, n->gzb, n->h2b, n->grad + OFF_W3,
+                       n->grad + OFF_B3, B, g, rpb);
     hipLaunchKernelGGL((k_conv_mfma<false>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n->gzb, n->w3b,
                        nullptr, n->h2, n->gz2, n->gz2b, B, g);
-    hipLaunchKernelGGL((k_wgrad<CH>), dim3(chunks, 27), dim3(CH * CH), 0, st, n->gz2, n->h1, n->grad + OFF_W2,
-                       n->grad + OFF_B2, B, 256, g);
+    hipLaunchKernelGGL(k_wgrad_mfma, dim3(wblocks), dim3(64 * WG_WAVES), 0, st, n->gz2b, n->h1b, n->grad + OFF_W2,
+                       n->grad + OFF_B2, B, g, rpb);
     hipLaunchKernelGGL((k_conv_mfma<false>), dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, n->gz2b, n->w2b,
                        nullptr, n->h1, n->gz, n->gzb, B, g);
     hipLaunchKernelGGL((k_wgrad<1>), dim3(chunks, 27), dim3(CH), 0, st, n->gz, feat, n->grad + OFF_W1,

@@ -81,6 +81,52 @@ def test_vector_layer_indices(B, g):
     assert CH * CH <= 1024 and (CH * CH - 1) // CH < CH
 
 
+@pytest.mark.parametrize("B,g", SHAPES)
+def test_wgrad_mfma_indices(B, g):
+    """k_wgrad_mfma: 9 wavefronts per block, about 512 blocks over runs of rows (b, v1, v2, segment);
+    staging chunks of gz (threads < 128) and of each wavefront's neighbour row with its halo
+    (34 voxels, chunks l + 64 q < 136), operand gathers from LDS, atomics into dW and db."""
+    GV = g ** 3
+    segs = g // 32
+    rows = B * g * g * segs
+    rpb = (rows + 511) // 512
+    wblocks = (rows + rpb - 1) // rpb
+    assert wblocks <= 512 and wblocks * rpb >= rows and (wblocks - 1) * rpb < rows
+    row = np.arange(rows)                       # every row some block visits (r0 <= row < r1)
+    seg, r2 = row % segs, row // segs
+    b, v1, v2 = r2 // (g * g), (r2 // g) % g, r2 % g
+    s0 = 32 * seg
+    tid = np.arange(128)
+    v, c8 = tid // (CH // 8), tid % (CH // 8)
+    gzi = (b[:, None] * GV + (v1[:, None] * g + v2[:, None]) * g + s0[:, None] + v[None]) * CH + 8 * c8[None]
+    assert gzi.min() >= 0 and gzi.max() + 7 < B * GV * CH
+    assert tid.max() < 32 * CH // 8
+    lane = np.arange(64)
+    for wave in range(9):
+        da, db = wave // 3 - 1, wave % 3 - 1
+        for q in range(3):
+            c = lane + 64 * q
+            c = c[c < 34 * CH // 8]
+            p, cc = c // (CH // 8), c % (CH // 8)
+            src = vox(v1[:, None] + da, v2[:, None] + db, s0[:, None] - 1 + p[None], g)
+            xi = (b[:, None] * GV + src) * CH + 8 * cc[None]
+            assert xi.min() >= 0 and xi.max() + 7 < B * GV * CH
+            assert c.max() < 34 * CH // 8                       # xs[wave] chunk
+        i, kb = lane & 31, lane >> 5
+        for kk in range(2):
+            k0 = 16 * kk + 8 * kb
+            ga = (k0[:, None] + np.arange(8)[None]) * CH + i[:, None]
+            assert ga.min() >= 0 and ga.max() < 32 * CH         # gz row in LDS
+            xa = (k0[:, None] + np.arange(10)[None]) * CH + i[:, None]
+            assert xa.min() >= 0 and xa.max() < 34 * CH         # halo row in LDS
+        t = np.arange(16)
+        co = 8 * (t[None] // 4) + 4 * kb[:, None] + t[None] % 4
+        d = (co * CH + i[:, None]) * 27 + 3 * wave
+        assert d.min() >= 0 and d.max() + 2 < CH * CH * 27
+        # the three taps of the wave are the kernel's tap = 9 a + 3 b + c with (a, b) = (da, db) + 1
+        assert {3 * wave + c for c in range(3)} == {9 * (da + 1) + 3 * (db + 1) + c for c in range(3)}
+
+
 def _interp(i, N, g):
     u = np.float32(i - N // 2) * (np.float32(g) / np.float32(N))
     fl = np.floor(u)
