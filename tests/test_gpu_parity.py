@@ -68,6 +68,31 @@ def test_apply_matches_brute_force(firm):
     assert rel(y, ofirm.toeplitz_apply_brute(K, x).real) < TOL
 
 
+def test_timed_apply_matches_apply_and_times_every_pass(firm):
+    """firm_apply_AtA_timed launches the same five passes (each with a pair of events in its
+    dispatch): the product equals firm_apply_AtA's bit for bit, every pass has a positive
+    duration, and their sum is no more than the wall time of the products."""
+    import time
+    import torch
+    N = 64
+    rng = np.random.default_rng(12)
+    R, _, _, _ = small_geometry(N, 2, N)
+    plan = firm.Plan(N, R)
+    plan.kernel_set(dev(ker_to_centred(even_random_kernel(N, rng), N)))
+    x = dev(rng.standard_normal((N, N, N)))
+    y0 = host(plan.apply_AtA(x, 0.3))
+    y1 = torch.empty_like(x)
+    reps = 20
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = plan.apply_AtA_timed(x, 0.3, reps, y1)
+    wall_ms = (time.perf_counter() - t0) * 1e3 / reps
+    print(f"timed apply N={N}: passes {np.round(ms, 4)} ms, wall {wall_ms:.4f} ms per product", flush=True)
+    assert np.array_equal(host(y1), y0)
+    assert len(ms) == 5 and all(v > 0 for v in ms)
+    assert sum(ms) <= wall_ms
+
+
 def test_kernel_get_set_roundtrip(firm):
     N = 16
     rng = np.random.default_rng(9)
