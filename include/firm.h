@@ -76,7 +76,10 @@ typedef struct {
                              the FP32 kernel.  0 = FP32 K^; 1 = BF16 codes of (K^ - o_s) / s_s
                              with a per-shell offset o_s (shell mean) and scale s_s (largest
                              deviation), shell = rounded |q|; 2 = BF16 codes of K^ */
-    double inner_tol;     /* precision 1: relative tolerance of each FP32 correction; 0 = 1e-3 */
+    double inner_tol;     /* precision 1: relative tolerance of each FP32 correction (never tighter
+                             than half of what the remaining reduction to tol needs); 0 = the
+                             first correction to sqrt(tol) (within [1e-4, 1e-2]), later ones to
+                             half of the remaining reduction (at least 1e-4) */
     void* stream;         /* hipStream_t for all work; NULL = null stream */
     int stagnation_iters; /* preconditioned solves: restart as plain CG from the current x when the
                              residual norm has not halved in this many iterations (checked every

@@ -217,7 +217,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     p->stream = (hipStream_t)o.stream;
     p->precision = o.precision;
     p->lambda_relative = o.lambda_relative;
-    p->inner_tol = o.inner_tol > 0 ? o.inner_tol : 1e-3;
+    p->inner_tol = o.inner_tol;  // 0: chosen per solve from its tolerance
     p->khat_bf16 = o.khat_bf16;
 
     // geometry: columns 1 and 2 of R^{-1} = R^T are rows 1 and 2 of R; normal = c1 x c2

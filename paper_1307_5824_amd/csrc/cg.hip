@@ -483,7 +483,13 @@ static firm_status cg_refine64(firm_plan p, const double* atb, double* xw, doubl
         L1(k_f_from_d, p->rhs, p->r64, n);
         CK(fill_zero(p->dvec, n * sizeof(float), st));
         const double rel = std::sqrt(rr / bb);
-        const double inner = std::max(p->inner_tol, 0.5 * tol / rel);
+        // an explicit inner tolerance bounds every correction, which then goes to half of the
+        // reduction still needed; by default the first goes to sqrt(tol) and each later one to
+        // 0.8 of the reduction still needed (the FP64 residual is checked after every
+        // correction, so an overshoot below tol only costs iterations)
+        const double floor_tol = p->inner_tol > 0 ? p->inner_tol
+                                                  : (outer == 0 ? std::min(1e-2, std::max(1e-4, std::sqrt(tol))) : 1e-4);
+        const double inner = std::max(floor_tol, (p->inner_tol > 0 ? 0.5 : 0.8) * tol / rel);
         firm_cg_report ir{};
         firm_status is = cg_core32(p, p->rhs, p->dvec, lam, std::min(inner, 0.5), max_iter - total, d, &ir);
         if (is != FIRM_OK && is != FIRM_ERR_NOT_CONVERGED && is != FIRM_ERR_BREAKDOWN) return is;

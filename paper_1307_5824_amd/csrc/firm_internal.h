@@ -21,7 +21,7 @@ struct firm_plan_s {
                                  // without a halving of the residual norm (<= 0: never)
     int precision = 0;          // 0 FP32 CG, 1 FP64 iterative refinement, 2 FP64 CG
     int lambda_relative = 0;    // lambda multiplies Ker(0)
-    double inner_tol = 1e-3;    // relative tolerance of each FP32 correction (precision 1)
+    double inner_tol = 0.0;     // relative tolerance of each FP32 correction (precision 1; 0 = per solve)
     double ker0 = 0.0;          // Ker(0) of the current kernel
     int reg_order = 0;          // Fourier-space damping: order p of mu L_p (0 = none)
     double reg_mu = 0.0;        // its weight as given (times Ker(0) with lambda_relative)
