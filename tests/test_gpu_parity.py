@@ -350,7 +350,7 @@ def test_pcg_unit_diagonal_equals_cg(firm):
 def test_pcg_breakdown_falls_back_to_cg(firm):
     """An indefinite preconditioner (d = -1: <r, z> < 0 after the first step) is a breakdown;
     the solver restarts as plain CG from the current iterate and still reaches the tolerance,
-    judged by the oracle's residual of the returned x."""
+    checked by the oracle's residual of the returned x."""
     N, M = 16, 30
     R, _, _, _ = small_geometry(N, M, 75)
     Ker = ofirm.kernel_direct(N, R).real
