@@ -463,24 +463,36 @@ static firm_status cg_refine64(firm_plan p, const double* atb, double* xw, doubl
     hipStream_t st = p->stream;
     L1(k_dot64, atb, atb, n, p->partials3);
     R1(p->partials3, VB, p->scal, (int)S_BB, -1, nullptr);
+    // a zero initial guess (the usual case) has the residual atb itself: no first product
+    L1(k_dot64, xw, xw, n, p->partials3);
+    R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
     CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
     CK(hipStreamSynchronize(st));
-    const double bb = p->host_scal[S_BB] > 0 ? p->host_scal[S_BB] : 1.0;
+    const double bb0 = p->host_scal[S_BB];
+    const double bb = bb0 > 0 ? bb0 : 1.0;
+    bool xzero = p->host_scal[S_TRUE] == 0.0;
     int total = 0, outer = 0, fell_back = 0;
     double rr = 0.0;
     firm_status result = FIRM_OK;
     for (;;) {
-        CK(fft_apply_AtA64(p, xw, p->y64, lam));
-        L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
-        R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
-        CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-        CK(hipStreamSynchronize(st));
-        rr = p->host_scal[S_TRUE];
+        const double* res = p->r64;
+        if (xzero) {
+            rr = bb0;
+            res = atb;
+            xzero = false;
+        } else {
+            CK(fft_apply_AtA64(p, xw, p->y64, lam));
+            L1(k_resid64, atb, p->y64, p->r64, n, p->partials3);
+            R1(p->partials3, VB, p->scal, (int)S_TRUE, -1, nullptr);
+            CK(hipMemcpyAsync(p->host_scal, p->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
+            CK(hipStreamSynchronize(st));
+            rr = p->host_scal[S_TRUE];
+        }
         if (!std::isfinite(rr)) { result = FIRM_ERR_BREAKDOWN; break; }
         if (rr <= tol * tol * bb) break;
         if (total >= max_iter) { result = FIRM_ERR_NOT_CONVERGED; break; }
         // correction with the FP32 solver; the rhs is the FP64 residual rounded to FP32
-        L1(k_f_from_d, p->rhs, p->r64, n);
+        L1(k_f_from_d, p->rhs, res, n);
         CK(fill_zero(p->dvec, n * sizeof(float), st));
         const double rel = std::sqrt(rr / bb);
         // an explicit inner tolerance bounds every correction, which then goes to half of the
