@@ -285,6 +285,31 @@ def test_cg_small_workload_fp32_iterates(firm):
     assert err < max(TOL, 4 * env)
 
 
+@pytest.mark.parametrize("tol,f64", [(1e-3, False), (1e-5, False), (1e-8, True)])
+def test_refinement_reaches_tol_from_zero_and_nonzero_guesses(firm, tol, f64):
+    """Precision 1 (FP64 refinement, default inner tolerances) on an oracle kernel: from a zero
+    initial guess (whose first residual is atb itself, no product) and from a random one, the
+    solve stops at tol by the oracle's FP64 residual of the returned x (FP32 x for tol 1e-3 and
+    1e-5; the FP64 entry point for 1e-8, below what an FP32 x can represent at this condition)."""
+    N, M = 16, 40
+    R, _, _, _ = small_geometry(N, M, 43)
+    Ker = ofirm.kernel_direct(N, R).real
+    plan = firm.Plan(N, R, precision=1)
+    plan.kernel_set(dev(ker_to_centred(Ker, N)))
+    rng = np.random.default_rng(int(-np.log10(tol)))
+    atb = rng.standard_normal((N, N, N))
+    lam = 1e-1 * float(Ker[N - 1, N - 1, N - 1])
+    Ker = Ker.astype(np.float32).astype(np.float64)   # the operator the plan holds (FP32 kernel values)
+    dt = torch.float64 if f64 else torch.float32
+    for x0 in (None, torch.from_numpy(rng.standard_normal((N, N, N))).to("cuda", dt)):
+        x, rep = plan.cg_solve(torch.from_numpy(atb).to("cuda", dt), lam, tol, 2000, x0=x0)
+        xr = x.double().cpu().numpy()
+        tr = np.linalg.norm(atb - (ofirm.toeplitz_apply_fft(Ker, xr).real + lam * xr)) / np.linalg.norm(atb)
+        print(f"refinement tol {tol:g} x0 {'zero' if x0 is None else 'random'}: {rep['iters']} iterations, "
+              f"{rep['refinements']} corrections, oracle residual {tr:.3e}", flush=True)
+        assert rep["status"] == 0 and tr <= tol * 1.01
+
+
 def test_cg_converges_and_true_residual(firm):
     """CG to tol on a kernel from the oracle: the reported true residual is the oracle's."""
     N, M = 16, 40
