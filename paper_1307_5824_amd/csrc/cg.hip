@@ -217,10 +217,13 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
     hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials3, VB, scal, (int)S_BB, -1, nullptr);
     hipLaunchKernelGGL(k_init, dim3(1), dim3(1), 0, st, scal, flags, tol, max_iter);
     CK(fill_zero(p->p, n * sizeof(float), st));
+    // N > 64: z stays as its row half spectra in S1 and the product's first pass finishes the
+    // preconditioner (fft_apply_cg_front_pz), so that z is never written or read
+    auto fused = [&]() { return pc && N > 64; };
     auto set_rz = [&](bool guarded) -> hipError_t {
         const int* fl = guarded ? flags : nullptr;
         if (pc) {
-            hipError_t e = fft_precond(p, p->dhalf, p->r, p->z, fl, p->partials2);
+            hipError_t e = fft_precond(p, p->dhalf, p->r, fused() ? nullptr : p->z, fl, p->partials2);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_reduce_to, dim3(1), dim3(VT), 0, st, p->partials2, nb_prec, scal, (int)S_RZ, -1, fl);
         } else {
@@ -242,10 +245,13 @@ static firm_status cg_core32(firm_plan p, const float* atb, float* x, double lam
             const float* src = pc ? p->z : p->r;
             // p = src + beta p and q = (A*A + lam) p, with alpha = rz / <p, q> formed between the
             // two halves of the product and the step x += alpha p, r -= alpha q in its last pass
-            CK(fft_apply_cg_front(p, src, p->p, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
+            if (fused())
+                CK(fft_apply_cg_front_pz(p, p->p, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
+            else
+                CK(fft_apply_cg_front(p, src, p->p, (float)lam, scal + S_BETA, flags + F_ACTIVE, p->partials));
             hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RT), 0, st, p->partials, nb_apply, scal, flags);
             CK(fft_apply_cg_step(p, x, p->p, p->r, scal + S_ALPHA, flags + F_ACTIVE, p->partials3));
-            if (pc) CK(fft_precond(p, p->dhalf, p->r, p->z, flags + F_ACTIVE, p->partials2));
+            if (pc) CK(fft_precond(p, p->dhalf, p->r, fused() ? nullptr : p->z, flags + F_ACTIVE, p->partials2));
             hipLaunchKernelGGL(k_beta, dim3(1), dim3(RT), 0, st, p->partials3, nb_step, pc ? p->partials2 : nullptr,
                                nb_prec, scal, flags);
             ++it_host;

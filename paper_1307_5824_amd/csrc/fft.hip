@@ -335,6 +335,82 @@ k_rows_c2r(const typename VecOf<S>::V* __restrict__ src, int nrows, int in_pitch
 }
 
 
+// First pass of a preconditioned CG iteration with the preconditioner's last pass fused in.
+// In: the half spectra of z = F^{-1}(d . F r) along i3 (the preconditioner's output before its
+// inverse row transform, S1 [row][q3 <= N/2], pitch qpn).  Per pencil (rows 2 pr and 2 pr + 1 of
+// the N^2 rows along i3, packed as one complex sequence): the N-point inverse transform gives z;
+// then p = z + beta p (stored); then the 2N-point forward transform of p's rows zero-padded from N,
+// as two N-point transforms: its even outputs X(2m) are the N-point DFT of p, its odd outputs
+// X(2m+1) that of p(e) exp(-2 pi i e / 2N); their half spectra go to dst (pitch out_pitch, modes
+// 0..N), as the product's first pass writes them.  z is never stored.
+constexpr int PZC = 8;  // pencils per workgroup
+template <int N>
+__global__ void __launch_bounds__(PZC * N / 8) k_rows_pz(const float2* __restrict__ S1, int qpn, float* pvec,
+                                                      const double* __restrict__ beta_dev, float2* __restrict__ dst,
+                                                      int out_pitch, const float2* __restrict__ tw, const int* active) {
+    using V = float2;
+    constexpr int C = PZC, T = N / 8, NT = C * T, L = 2 * N;
+    using P = Pen<N, C, true>;
+    static_assert(FIRM_TWN % L == 0, "twist from the twiddle table");
+    __shared__ V lds[2 * P::LDS];  // the transforms' exchange buffer (first half), then both spectra
+    __shared__ V twl[FIRM_TWN];
+    if (cg_inactive(active)) return;
+    TwCopy<NT, V> twc;
+    twc.fetch(tw);
+    const int c = P::c(), j = P::j();
+    const int pr = blockIdx.x * C + c;  // the grid covers the N^2 / 2 pencils exactly
+    const float beta = (float)(*beta_dev);
+    V v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = j + t * T;
+        const int m = e <= N / 2 ? e : N - e;
+        const V Ya = S1[(int64_t)(2 * pr) * qpn + m];
+        const V Yb = S1[(int64_t)(2 * pr + 1) * qpn + m];
+        v[t] = e <= N / 2 ? mkv<V>(Ya.x - Yb.y, Ya.y + Yb.x)    // Ya + i Yb
+                          : mkv<V>(Ya.x + Yb.y, Yb.x - Ya.y);   // conj Ya + i conj Yb
+    }
+    twc.store(twl);
+    __syncthreads();  // the twiddle table is in place
+    fft_reg<N, C, true>(v, lds, twl, 1.f);  // z of row 2 pr (real part) and 2 pr + 1 (imaginary part)
+    V w[8], u[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int e = j + t * T;
+        const int64_t g = (int64_t)(2 * pr) * N + e;
+        const float a = v[t].x + beta * pvec[g], b = v[t].y + beta * pvec[g + N];
+        pvec[g] = a;
+        pvec[g + N] = b;
+        w[t] = mkv<V>(a, b);
+        u[t] = c_mul(w[t], twl[e * (FIRM_TWN / L)]);  // times exp(-2 pi i e / 2N)
+    }
+    fft_reg<N, C, true>(w, lds, twl, -1.f);  // X(2m), m = j + T t
+    fft_reg<N, C, true>(u, lds, twl, -1.f);  // X(2m + 1)
+    __syncthreads();  // every wavefront has read the exchange buffer
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int m = j + t * T;
+        lds[P::idx(m, c)] = w[t];
+        lds[P::LDS + P::idx(m, c)] = u[t];
+    }
+    __syncthreads();
+    // half spectra of the two rows, modes q in [0, N]: from X(q) and X(2N - q), both of q's parity
+#pragma unroll
+    for (int t = 0; t <= 8; ++t) {
+        const int q = j + t * T;
+        if (q <= N) {
+            const int h = q & 1;
+            const int mq = q >> 1, mm = (N - ((q + h) >> 1)) & (N - 1);
+            const V Z = lds[h * P::LDS + P::idx(mq, c)];
+            const V Zm = lds[h * P::LDS + P::idx(mm, c)];
+            const V D = mkv<V>(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));  // (Z - conj Zm) / 2
+            // plain stores, as the product's first pass: the next pass finds them in the memory-side cache
+            dst[(int64_t)(2 * pr) * out_pitch + q] = mkv<V>(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+            dst[(int64_t)(2 * pr + 1) * out_pitch + q] = mkv<V>(D.y, -D.x);  // D / i
+        }
+    }
+}
+
 // The Fourier-diagonal preconditioner's outer passes for N <= 64, one workgroup per i1 slab
 // (the N x N slab and its N x (N/2 + 1) half spectrum fit LDS).  FWD: rows along i3 real to
 // half spectrum (two real rows per complex pencil, as k_rows_r2c), then columns along i2
@@ -893,6 +969,9 @@ hipError_t launch_mid(hipStream_t st, typename VecOf<S>::V* data, const S* spec,
 // takes the CG step with the alpha formed from them in between (fft_apply_cg_step_partials
 // partials of ||r||^2).
 template <int L>
+hipError_t apply_front_bc(firm_plan p, float lam, const int* active, double* dotp, hipEvent_t* ev);
+
+template <int L>
 hipError_t apply_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta, const int* active,
                        double* dotp, hipEvent_t* ev) {
     const int N = L / 2, QP = p->QP;
@@ -903,6 +982,28 @@ hipError_t apply_front(firm_plan p, const float* src, float* pvec, float lam, co
         RET_IF((launch_r2c<L, true>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw, pvec, beta, active)));
     else
         RET_IF((launch_r2c<L, false>(st, src, N * N, N, N, p->T1, QP, N + 1, -1.f, p->tw)));
+    return apply_front_bc<L>(p, lam, active, dotp, ev);
+}
+
+// the front of the preconditioned CG product with the preconditioner's last pass fused into its
+// first (k_rows_pz): z's half spectra in S1 -> p = z + beta p -> T1
+template <int L>
+hipError_t apply_front_pz(firm_plan p, float* pvec, float lam, const double* beta, const int* active, double* dotp) {
+    if constexpr (L >= 256 && L <= 1024) {
+        constexpr int N = L / 2;
+        hipLaunchKernelGGL((k_rows_pz<N>), dim3(N * N / 2 / PZC), dim3(PZC * N / 8), 0, p->stream, p->S1, p->QPn,
+                           pvec, beta, p->T1, p->QP, p->tw, active);
+        RET_IF(hipGetLastError());
+        return apply_front_bc<L>(p, lam, active, dotp, nullptr);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int L>
+hipError_t apply_front_bc(firm_plan p, float lam, const int* active, double* dotp, hipEvent_t* ev) {
+    const int N = L / 2, QP = p->QP;
+    hipStream_t st = p->stream;
     // T2 is blocked [q2][q3 group][i1][C] (C = the pencils per workgroup), so that every pencil
     // group of the middle pass is one contiguous block
     constexpr int C = FftCfg<L, float2>::C;
@@ -1035,6 +1136,7 @@ hipError_t precond_passes(firm_plan p, const float* dhalf, const float* r, float
     const int N = L, H = N / 2 + 1, QPn = p->QPn;
     hipStream_t st = p->stream;
     if constexpr (L <= 64) {  // slab kernels around the middle pass: 3 launches instead of 5
+        if (!z) return hipErrorInvalidValue;
         constexpr int NT = FftCfg<L, float2>::THREADS;
         hipLaunchKernelGGL((k_precond_slab<L, true>), dim3(N), dim3(NT), 0, st, r, p->S1, (float*)nullptr, QPn,
                            p->tw, active);
@@ -1056,6 +1158,7 @@ hipError_t precond_passes(firm_plan p, const float* dhalf, const float* r, float
     RET_IF((launch_cols<L, false, MAP_FIRST, EPI_STORE>(st, p->S1, p->S1, N, H, (int64_t)N * QPn, 1, QPn,
                                                           (int64_t)N * QPn, 1, QPn, N, N, 1.f, p->tw, EpiArgs(),
                                                           active)));
+    if (!z) return hipSuccess;  // the row half spectra of z stay in S1 (for k_rows_pz)
     return launch_c2r<L, false, float>(st, p->S1, N * N, QPn, z, N, N, 1.f, 1.f, 0.f, nullptr, p->tw, nullptr, active);
 }
 
@@ -1203,6 +1306,12 @@ hipError_t fft_apply_AtA_events(firm_plan p, const float* x, float* y, float lam
 hipError_t fft_apply_cg_front(firm_plan p, const float* src, float* pvec, float lam, const double* beta_dev,
                               const int* active, double* dotp) {
     DISPATCH_L(2 * p->N, apply_front, p, src, pvec, lam, beta_dev, active, dotp, nullptr);
+    return hipErrorInvalidValue;
+}
+
+hipError_t fft_apply_cg_front_pz(firm_plan p, float* pvec, float lam, const double* beta_dev, const int* active,
+                                 double* dotp) {
+    DISPATCH_L(2 * p->N, apply_front_pz, p, pvec, lam, beta_dev, active, dotp);
     return hipErrorInvalidValue;
 }
 

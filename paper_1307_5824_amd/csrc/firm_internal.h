@@ -123,7 +123,9 @@ hipError_t fft_atb_grid(firm_plan p, const float2* grid, float2* j1, float2* j2,
                         const double* k0term);
 hipError_t fft_project_grid(firm_plan p, const float* u, float2* t1, float2* w, float2* X);  // L x L x QP
 hipError_t fft_images_r2c(firm_plan p, const float* img, int G, float2* out);  // G x N x QPn half spectra
-// z = IFFT_N(dhalf . FFT_N(r)); partials: also fft_precond_partials(p) block partials of <r, z>
+// z = IFFT_N(dhalf . FFT_N(r)); partials: also fft_precond_partials(p) block partials of <r, z>.
+// z == nullptr (N > 64 only): z is left as its half spectra along i3 in S1, for
+// fft_apply_cg_front_pz
 hipError_t fft_precond(firm_plan p, const float* dhalf, const float* r, float* z, const int* active = nullptr,
                        double* partials = nullptr);
 int fft_precond_partials(firm_plan p);
@@ -139,6 +141,10 @@ hipError_t fft_apply_cg_front(firm_plan p, const float* src, float* pvec, float 
                               const int* active, double* dotp);
 hipError_t fft_apply_cg_step(firm_plan p, float* x, const float* pvec, float* r, const double* alpha_dev,
                              const int* active, double* partials);
+// the front with z taken from the preconditioner's half spectra in S1 (N = 128, 256; see
+// fft_precond with z == nullptr): p = z + beta p, z itself is never stored
+hipError_t fft_apply_cg_front_pz(firm_plan p, float* pvec, float lam, const double* beta_dev, const int* active,
+                                 double* dotp);
 int fft_apply_cg_step_partials(firm_plan p);
 int fft_apply_cg_partials(firm_plan p);
 
