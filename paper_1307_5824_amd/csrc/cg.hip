@@ -9,10 +9,12 @@
 //     so an iteration needs no host round trip.  The direction update
 //     p = z + beta p is fused into the first FFT pass of the product, <p, q> into
 //     its middle pass (Parseval over the spectrum) and the step x += alpha p,
-//     r -= alpha q with ||r||^2 into its last pass.  Every refine_every iterations the recursive residual
-//     is replaced by the residual recomputed from the FP32 product.  The host
-//     reads a small flag block every check_every iterations; kernels enqueued
-//     after convergence see the flag and exit.
+//     r -= alpha q with ||r||^2 into its last pass; for N > 64 the
+//     preconditioner's last pass is fused into the product's first as well.
+//     Every refine_every iterations the recursive residual is replaced by the
+//     residual recomputed from the FP32 product.  The host reads a small flag
+//     block every check_every iterations; kernels enqueued after convergence
+//     see the flag and exit.
 //  1  FP64 iterative refinement: the residual, the product that forms it and the
 //     solution are FP64; each correction is an FP32 (P)CG solve of the residual
 //     equation to a relative tolerance.  Reaches residuals below the FP32
