@@ -40,12 +40,12 @@ def even_random_kernel(N, rng):
     return 0.5 * (K + K[::-1, ::-1, ::-1])
 
 
-def gaussian_kernel(N, width):
-    """Real, even, smooth kernel exp(-|n|^2 / (2 w^2)) + 0.1 cos(pi n1 / N) on offsets (-N, N)^3."""
+def gaussian_kernel(N, width, cos_amp=0.1):
+    """Real, even, smooth kernel exp(-|n|^2 / (2 w^2)) + cos_amp cos(pi n1 / N) on offsets (-N, N)^3."""
     n = np.arange(-N + 1, N, dtype=np.float64)
     g = np.exp(-n * n / (2 * width * width))
     K = g[:, None, None] * g[None, :, None] * g[None, None, :]
-    K += 0.1 * np.cos(np.pi * n / N)[:, None, None] * np.ones((1, 2 * N - 1, 2 * N - 1))
+    K += cos_amp * np.cos(np.pi * n / N)[:, None, None] * np.ones((1, 2 * N - 1, 2 * N - 1))
     return K
 
 
