@@ -254,6 +254,27 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     }
     std::vector<float> poly, dker, datb;
     kb_tables(p, poly, dker, datb);
+    {
+        // fixed-point unit of the kernel gridding: every term 2 h^2 w1 w2 w3 stays below 2^31 units
+        double wmax = 0.0;
+        for (int j = 0; j < p->kbw; ++j)
+            for (int i = 0; i <= 4000; ++i) {
+                const double x = -1.0 + i / 2000.0;
+                double v = 0.0;
+                for (int k = KB_DEG; k >= 0; --k) v = v * x + (double)poly[j * (KB_DEG + 1) + k];
+                wmax = std::max(wmax, std::fabs(v));
+            }
+        double hmax = ctf_table ? 0.0 : 1.0;
+        if (ctf_table)
+            for (int64_t i = 0; i < (int64_t)Geff * Q; ++i) hmax = std::max(hmax, std::fabs((double)ctf_table[i]));
+        // A*b: a term is w1 w2 w3 h e^{i theta} (b(k) + conj b(-k)) per component, at most
+        // 2 sqrt(2) hmax bmax wmax^3 in magnitude; the unit is fixed per call from bmax
+        p->fx_atb_coef = (float)std::min(1e30, 2147483648.0 / (2.0 * std::sqrt(2.0) * std::max(hmax, 1e-30) * wmax * wmax * wmax * 1.05));
+        const double bound = 2.0 * hmax * hmax * wmax * wmax * wmax * 1.05;
+        int e = bound > 0.0 ? (int)std::floor(std::log2(2147483648.0 / bound)) : 0;
+        e = std::min(std::max(e, -100), 100);
+        p->fx_ker = std::ldexp(1.0f, e);
+    }
     std::vector<int> wk = spread_worklist(4 * N, spread_tile_real(), M, 4.0);
     std::vector<int> wa = spread_worklist(2 * N, spread_tile_cplx(), M, 2.0);
     p->ntiles_ker = (int)(wk.size() / 4);
@@ -293,6 +314,7 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->dhalf, blocked_spectrum_elems(N, N, N / 2 + 1, false)));
     chk(dalloc(&p->S1, (size_t)((int64_t)N * N * p->QPn)));
     chk(dalloc(&p->dscal, 8));
+    p->fx_bmax = reinterpret_cast<unsigned*>(p->dscal + 1);
     chk(dalloc(&p->rowstart, (size_t)(N + 1)));
     chk(dalloc(&p->tiles_ker, wk.size()));
     chk(dalloc(&p->tiles_atb, wa.size()));

@@ -39,6 +39,9 @@ struct firm_plan_s {
 
     // Kaiser-Bessel window (device)
     float* kb_poly = nullptr;  // w x (KB_DEG+1) polynomial coefficients on f in [0, 1]
+    float fx_ker = 1.f;        // kernel gridding: integer units per unit (power of 2, terms < 2^31)
+    float fx_atb_coef = 0.f;   // A*b gridding: units per unit times the largest |b component| may reach
+    unsigned* fx_bmax = nullptr;  // device word: bits of the largest |b component| (inside dscal)
     float* deconv_ker = nullptr;  // 2N: 1/phihat at circulant position p (L = 4N)
     float* deconv_atb = nullptr;  // N: 1/phihat at centred index i (L = 2N)
 

@@ -14,13 +14,20 @@
 // tile is then added to the global grid with one atomic per cell.  Each point is
 // spread exactly once.
 //
-// The LDS accumulation uses no atomics (LDS float atomics run at a fraction of
-// the plain read/write rate on this chip).  Each wavefront owns a slab of rows
-// (first tile axis) of the padded tile.  The per-point window weights are
-// computed once, one thread per point and axis, and staged in LDS ranked by the
-// window's first row; then every wavefront walks the staged points whose W rows
-// meet its slab, with its lanes on the W x W footprint of the other two axes:
-// all rows of the slab are read, updated and written back.  Within one
+// LDS float atomics run at a small fraction of the plain read/write rate on this
+// chip, 64-bit integer atomics at about the plain rate.  The kernel's tile (Ker)
+// is therefore accumulated in fixed point: 64-bit integer cells, each term the
+// FP32 product rounded to an integer in units of 1/fxs (|term| < 2^31), added
+// with one integer atomic per cell.  Integer sums are exact and independent of
+// the order of the adds, so every wavefront takes any staged point.  The per-point
+// window weights are computed once, one thread per point and axis, and staged in
+// LDS; the lanes of a wavefront sit on the W x W footprint of the last two axes
+// and add the point's W rows.
+//
+// The A*b tile keeps FP32 cells without atomics.  Each wavefront owns a slab of
+// rows (first tile axis) of the padded tile; the staged points are ranked by the
+// window's first row, and every wavefront walks the points whose W rows meet its
+// slab: all rows of the slab are read, updated and written back.  Within one
 // instruction the lanes' cells are distinct and no two wavefronts write the same
 // row, so the plain read-modify-write is race-free.  Only the half disk (k1 > 0, or k1 = 0 and
 // k2 > 0) is spread: its partner -k is folded in (Ker is real and even; for A*b
@@ -52,6 +59,12 @@ struct SpreadArgs {
     const double* shifts;
     const int* rowstart;  // index of (k1, 0) shifted: idx(k1, k2) = rowstart[k1 + N/2] + k2
     int P;
+    float fxs;      // fixed-point accumulation: integer units per unit of grid value (a power of 2)
+    double fx_inv;  // 1 / fxs
+    // when set, fxs is the largest power of 2 not above fx_coef / bmax, bmax the float whose bits
+    // are at fx_bmax (the largest |component| of the data), found on the device before the launch
+    const unsigned* fx_bmax;
+    float fx_coef;
 };
 
 template <int W>
@@ -117,31 +130,34 @@ __device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, do
     return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
 }
 
-// Two workgroups per CU, except the W = 8 complex tile (85 KB of LDS), which fits one.
-template <int T, int W, bool CPLX, int NTH>
-__global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128)) k_spread(SpreadArgs a) {
+// Two workgroups per CU, except the W = 8 complex and fixed-point tiles, which fit one.
+template <int T, int W, bool CPLX, int NTH, bool FX>
+__global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX)) ? NTH / 256 : NTH / 128)) k_spread(SpreadArgs a) {
     constexpr int SP_THREADS = NTH, SP_WAVES = NTH / 64;
     constexpr int PT = T + W;
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;
     constexpr int H = (PT + SP_WAVES - 1) / SP_WAVES;  // rows per wavefront slab
-    // the real tile holds floats; the complex tile holds (re, im) pairs, one 8-byte access per cell
-    constexpr int G = CPLX ? 4 : 2;                    // lane groups of one LDS access
+    // FP32 slabs: the real tile holds floats; the complex tile holds (re, im) pairs, one 8-byte
+    // access per cell.  Fixed point (FX): 64-bit integer cells, one plane per component.
+    constexpr int G = (CPLX || FX) ? 4 : 2;            // lane groups of one LDS access
     constexpr int RP = row_pitch(PT, W, G);            // LDS pitch of a tile row, in cells (conflict-free)
     constexpr int GROUPS = row_groups(RP, W, G);       // lane group of every footprint row
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
-    constexpr int NR = SP_WAVES * H;                   // planes, padded to whole slabs
-    constexpr int NV = CPLX ? 2 : 1;                   // floats per cell
-    // staged point: the weights of the NR tile rows (0 outside the window), then the window
-    // weights of axes 1 and 2; stride in floats
-    constexpr int PSTR = ((NR + 2 * W) + 3) / 4 * 4;
+    constexpr int NR = FX ? PT : SP_WAVES * H;         // planes (slabs: padded to whole slabs)
+    constexpr int NV = CPLX ? 2 : 1;                   // components per cell
+    // staged point.  Slabs: the weights of the NR tile rows (0 outside the window), then the
+    // window weights of axes 1 and 2.  FX: the W weights of axes 0, 1, 2 at 0, 8, 16.  Stride in
+    // floats.
+    constexpr int PSTR = FX ? 24 : ((NR + 2 * W) + 3) / 4 * 4;
     static_assert(W <= 8, "window width");
     constexpr int SP_PB = 96;                          // points staged per batch (two tiles per CU)
     constexpr int NK = PT - W + 1;                     // possible first rows of a window
     static_assert(NK <= 64, "first-row buckets");
-    static_assert(NR % 4 == 0 && PSTR % 4 == 0, "row weights zeroed as float4");
+    static_assert(FX || (NR % 4 == 0 && PSTR % 4 == 0), "row weights zeroed as float4");
     constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
-    __shared__ __align__(16) float tile[NV * NR * PP];  // complex: (re, im) per cell
+    __shared__ __align__(16) float tile[FX ? 1 : NV * NR * PP];  // complex: (re, im) per cell
+    __shared__ __align__(16) unsigned long long tile64[FX ? NV * PT * PP : 1];  // re plane, im plane
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
     __shared__ int pt_lo[SP_PB];                       // window starts of axes 1, 2 in bytes 1, 2
     __shared__ float2 pt_v[CPLX ? SP_PB : 1];
@@ -153,12 +169,25 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
 
     const int tid = threadIdx.x;
     const int4 wk = a.work[blockIdx.x];
+    float fxs = a.fxs;
+    double fx_inv = a.fx_inv;
+    if (FX && a.fx_bmax) {
+        const float bm = __uint_as_float(*a.fx_bmax);
+        int e = 0;
+        if (bm > 0.f) e = (int)fmin(fmax(floor(log2((double)a.fx_coef / (double)bm)), -100.0), 100.0);
+        fxs = ldexpf(1.f, e);
+        fx_inv = ldexp(1.0, -e);
+    }
     const int nt = a.nt;
     const int tt0 = wk.x / (nt * nt), tt1 = (wk.x / nt) % nt, tt2 = wk.x % nt;
     const int L = a.L, N = a.N;
     const double halfL = 0.5 * L;
 
-    for (int i = tid; i < NV * NR * PP; i += SP_THREADS) tile[i] = 0.f;
+    if constexpr (FX) {
+        for (int i = tid; i < NV * PT * PP; i += SP_THREADS) tile64[i] = 0ull;
+    } else {
+        for (int i = tid; i < NV * NR * PP; i += SP_THREADS) tile[i] = 0.f;
+    }
     for (int i = tid; i < NK; i += SP_THREADS) bcnt[i] = 0;
     if (tid == 0) { any = 0; nimg = 0; qn = 0; qfail = SP_QCAP; }
 
@@ -217,8 +246,9 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
                         const int g = a.group ? a.group[m] : 0;
                         const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
                         if constexpr (!CPLX) {
-                            scale = 2.f * h * h;
+                            scale = 2.f * h * h * (FX ? fxs : 1.f);
                         } else {
+                            if constexpr (FX) scale = fxs;
                             // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
                             const int idx = a.rowstart[k1 + N / 2] + k2;
                             const float2 bp = a.b[(int64_t)m * a.P + idx];
@@ -233,29 +263,41 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
                             }
                             pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
                         }
-                        st_kr[p] = lod[it] | (atomicAdd(&bcnt[lod[it]], 1) << 8);
+                        if constexpr (!FX) st_kr[p] = lod[it] | (atomicAdd(&bcnt[lod[it]], 1) << 8);
                     }
                 }
             }
-            __syncthreads();
-            if (tid < 64) {  // exclusive scan of the bucket counts; the counts restart at zero
-                const int v = tid < NK ? bcnt[tid] : 0;
-                int incl = v;
+            if constexpr (!FX) {
+                __syncthreads();
+                if (tid < 64) {  // exclusive scan of the bucket counts; the counts restart at zero
+                    const int v = tid < NK ? bcnt[tid] : 0;
+                    int incl = v;
 #pragma unroll
-                for (int o = 1; o < 64; o <<= 1) {
-                    const int t = __shfl_up(incl, o, 64);
-                    if (tid >= o) incl += t;
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const int t = __shfl_up(incl, o, 64);
+                        if (tid >= o) incl += t;
+                    }
+                    if (tid < NK) {
+                        bstart[tid] = incl - v;
+                        bcnt[tid] = 0;
+                    }
                 }
-                if (tid < NK) {
-                    bstart[tid] = incl - v;
-                    bcnt[tid] = 0;
-                }
+                __syncthreads();
             }
-            __syncthreads();
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int d = dd[it];
                 if (d < 0) continue;
+                if constexpr (FX) {
+                    // the point keeps its batch position: weights of axis d at 8 d, window starts
+                    // in the bytes of pt_lo
+                    float* q = pt_w + pp[it] * PSTR + 8 * d;
+#pragma unroll
+                    for (int j = 0; j < W; ++j) q[j] = d == 0 ? scale * ph[it][j] : ph[it][j];
+                    reinterpret_cast<unsigned char*>(pt_lo)[4 * pp[it] + d] = (unsigned char)lod[it];
+                    if (CPLX && d == 0) pt_v[pp[it]] = pval;
+                    continue;
+                }
                 const int kr = st_kr[pp[it]];
                 const int slot = bstart[kr & 255] + (kr >> 8);
                 float* q = pt_w + slot * PSTR;
@@ -303,6 +345,81 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
                 const int jl = act ? lane : 0;
                 j2 = jl / W;
                 j3 = jl - j2 * W;
+            }
+            if constexpr (FX) {
+                // fixed point: the wavefronts take the batch's points in turn, the lanes on the
+                // W x W footprint of axes 1 and 2, one 64-bit integer atomic add per cell and
+                // window row.  Integer addition is associative, so the tile is exact and
+                // independent of the order of the adds; each term is the FP32 product
+                // rounded to an integer (|term| < 2^31 by the choice of fxs).
+                // A wavefront takes FQ of its points at a time.  Their window words, axis-0
+                // weights and values (the same for every lane) arrive in one LDS read spread over
+                // the lanes and are then broadcast from registers (readlane); each footprint lane
+                // reads its own axis-1 and axis-2 weights.  All reads of the FQ points come before
+                // their adds, so the wavefront waits once per FQ points (LDS completes in order,
+                // so a read issued after adds waits for them).  The lanes off the footprint take
+                // part in the reads only.
+                constexpr int FQ = 4;  // the register list of the asm statement below names 4
+                static_assert(FQ * 8 + FQ * (CPLX ? 3 : 1) <= 64, "one read for the uniform data");
+                const int wvu = __builtin_amdgcn_readfirstlane(wv);
+                // lane roles of the uniform read: 8 q + k -> weight k of point q (k < 8); 32 + q ->
+                // window word of point q; 32 + FQ + 2 q + c -> component c of the value of point q
+                const int uq = lane < 32 ? (lane >> 3) : (lane < 32 + FQ ? lane - 32 : ((lane - 32 - FQ) >> 1) % FQ);
+                for (int p0 = wvu; p0 < nb; p0 += FQ * SP_WAVES) {
+                    int pq[FQ];
+#pragma unroll
+                    for (int q = 0; q < FQ; ++q) pq[q] = min(p0 + q * SP_WAVES, nb - 1);
+                    int pl = pq[0];
+#pragma unroll
+                    for (int q = 1; q < FQ; ++q) pl = uq == q ? pq[q] : pl;
+                    const float* src = lane < 32 ? pt_w + pl * PSTR + (lane & 7)
+                                     : (lane < 32 + FQ || !CPLX) ? reinterpret_cast<const float*>(pt_lo + pl)
+                                                                 : reinterpret_cast<const float*>(pt_v + pl) + (lane & 1);
+                    float w2[FQ], w3[FQ];
+#pragma unroll
+                    for (int q = 0; q < FQ; ++q) {
+                        w2[q] = pt_w[pq[q] * PSTR + 8 + j2];
+                        w3[q] = pt_w[pq[q] * PSTR + 16 + j3];
+                    }
+                    float u = *src;
+                    // all the reads are issued here, before any register of theirs is used
+                    asm volatile("" : "+v"(u), "+v"(w2[0]), "+v"(w3[0]), "+v"(w2[1]), "+v"(w3[1]),
+                                 "+v"(w2[2]), "+v"(w3[2]), "+v"(w2[3]), "+v"(w3[3]));
+                    float w23[FQ];
+#pragma unroll
+                    for (int q = 0; q < FQ; ++q) w23[q] = w2[q] * w3[q];
+                    if (!act) continue;
+#pragma unroll
+                    for (int q = 0; q < FQ; ++q) {
+                        if (p0 + q * SP_WAVES >= nb) break;
+                        const int lw = __builtin_amdgcn_readlane(__float_as_int(u), 32 + q);
+                        const int cb = (lw & 255) * PP + (((lw >> 8) & 255) + j2) * RP + ((lw >> 16) & 255) + j3;
+                        if constexpr (!CPLX) {
+#pragma unroll
+                            for (int r = 0; r < W; ++r) {
+                                const float wxr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 8 * q + r));
+                                __hip_atomic_fetch_add(&tile64[cb + r * PP],
+                                                       (unsigned long long)(unsigned)fmaf(wxr, w23[q], 0.5f),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                        } else {
+                            const float vx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 32 + FQ + 2 * q));
+                            const float vy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 33 + FQ + 2 * q));
+                            const float ar = w23[q] * vx, ai = w23[q] * vy;
+#pragma unroll
+                            for (int r = 0; r < W; ++r) {
+                                const float wxr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 8 * q + r));
+                                const long long qr = (int)rintf(wxr * ar), qi = (int)rintf(wxr * ai);
+                                __hip_atomic_fetch_add(&tile64[cb + r * PP], (unsigned long long)qr,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_add(&tile64[PT * PP + cb + r * PP], (unsigned long long)qi,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                continue;
             }
             struct Pt {
                 int cb, l1, l2;
@@ -399,7 +516,7 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
     // queued points name their view by slot, and the slots are reused only after the queue has
     // been processed.  A chunk is VPT views per thread (the fixed cost of a chunk, barriers and
     // the latency of the view data, is paid once for all of them).
-    constexpr int VPT = 4;
+    constexpr int VPT = 8;
     int base = 0;  // first slot whose rows are not yet enumerated
     for (int mb = wk.y; mb < wk.z; mb += VPT * SP_THREADS) {
         unsigned pendv = 0u;  // this thread's views of the chunk that meet the tile, not yet in a slot
@@ -523,7 +640,17 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
         const int g1 = ((o1 + l1 - L / 2) % L + L) % L;
         const int g2 = ((o2 + l2 - L / 2) % L + L) % L;
         const int64_t gi = ((int64_t)g0 * L + g1) * L + g2;
-        if (!CPLX) {
+        if constexpr (FX) {
+            if constexpr (!CPLX) {
+                const unsigned long long v = tile64[li];
+                if (v) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, (float)((double)v * fx_inv));
+            } else {
+                const long long vr = (long long)tile64[li], vi = (long long)tile64[PT * PP + li];
+                float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
+                if (vr) unsafeAtomicAdd(gp, (float)((double)vr * fx_inv));
+                if (vi) unsafeAtomicAdd(gp + 1, (float)((double)vi * fx_inv));
+            }
+        } else if (!CPLX) {
             const float v = tile[li];
             if (v != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, v);
         } else {
@@ -534,6 +661,22 @@ __global__ void __launch_bounds__(NTH, (CPLX && W >= 8 ? NTH / 256 : NTH / 128))
         }
     }
 }
+
+// bits of the largest |component| of n complex values (atomic max on the bits of non-negative
+// floats, which order like the floats); *out starts at 0
+__global__ void k_absmax(const float4* __restrict__ b, int64_t n2, const float2* __restrict__ tail, int ntail,
+                         unsigned* out) {
+    float m = 0.f;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n2; i += (int64_t)gridDim.x * blockDim.x) {
+        const float4 v = b[i];
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) m = fmaxf(m, fmaxf(fabsf(tail[threadIdx.x].x), fabsf(tail[threadIdx.x].y)));
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));
+}
+
+__global__ void k_set_u32(unsigned* p, unsigned v) { *p = v; }
 
 __global__ void k_fill_zero(float4* p, size_t n4) {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
@@ -598,23 +741,27 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ o, int64
 
 int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
 
-// Ker (real tile): 8 wavefronts with 3-row slabs; A*b (two tiles, re and im): 4 with 5-row slabs,
-// so that two workgroups fit the LDS of a compute unit in both cases.
-template <int T, bool CPLX, int NTH = CPLX ? 256 : 512>
-hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* grid, const float2* b) {
+// Ker: fixed-point tile (64-bit cells), 8 wavefronts taking the points in turn.  A*b (two FP32
+// tiles, re and im): 4 wavefronts with 5-row slabs.  Two workgroups fit the LDS of a compute unit
+// in both cases.
+template <int T, bool CPLX, bool FX, int NTH = (CPLX && !FX) ? 256 : 512>
+hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* grid, const float2* b, float fxs,
+                         const unsigned* fx_bmax = nullptr, float fx_coef = 0.f) {
     SpreadArgs a;
     a.N = p->N; a.M = p->M; a.L = L; a.nt = (L + T - 1) / T;
     a.s = (double)L / p->N;
     a.c12 = p->c12; a.nrm = p->nrm; a.group = p->group; a.table = p->table; a.Q = p->Q;
     a.poly = p->kb_poly; a.work = reinterpret_cast<const int4*>(work); a.grid = grid;
     a.b = b; a.shifts = p->shifts; a.rowstart = p->rowstart; a.P = p->P;
+    a.fxs = fxs; a.fx_inv = 1.0 / (double)fxs;
+    a.fx_bmax = fx_bmax; a.fx_coef = fx_coef;
     if (nwork == 0) return hipSuccess;
     switch (p->kbw) {
-        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -622,7 +769,7 @@ hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* g
 
 }  // namespace
 
-#define SP_TILE_REAL 16
+#define SP_TILE_REAL 13
 #define SP_TILE_CPLX 12
 
 // Host work list: tiles of an L^3 grid that can hold points (|centre| - R <= L/2), each
@@ -673,11 +820,19 @@ hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t s) {
 }
 
 hipError_t spread_ker(firm_plan p, float* grid) {
-    return launch_spread<SP_TILE_REAL, false>(p, 4 * p->N, p->tiles_ker, p->ntiles_ker, grid, nullptr);
+    return launch_spread<SP_TILE_REAL, false, true>(p, 4 * p->N, p->tiles_ker, p->ntiles_ker, grid, nullptr, p->fx_ker);
 }
 
 hipError_t spread_atb(firm_plan p, const float2* b, float2* grid) {
-    return launch_spread<SP_TILE_CPLX, true>(p, 2 * p->N, p->tiles_atb, p->ntiles_atb, grid, b);
+    // the fixed-point unit follows from the largest |component| of b, found first
+    const int64_t n = (int64_t)p->M * p->P;
+    hipLaunchKernelGGL(k_set_u32, dim3(1), dim3(1), 0, p->stream, p->fx_bmax, 0u);
+    hipLaunchKernelGGL(k_absmax, dim3(grid_blocks(n / 2)), dim3(256), 0, p->stream,
+                       reinterpret_cast<const float4*>(b), n / 2, b + (n / 2) * 2, (int)(n % 2), p->fx_bmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_spread<SP_TILE_CPLX, true, true>(p, 2 * p->N, p->tiles_atb, p->ntiles_atb, grid, b, 1.f,
+                                                  p->fx_bmax, p->fx_atb_coef);
 }
 
 hipError_t atb_k0_term(firm_plan p, const float2* b, double* out) {

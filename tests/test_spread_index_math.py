@@ -1,0 +1,161 @@
+"""Host-side emulation of the index arithmetic of the fixed-point gridding accumulation
+(paper_1307_5824_amd/csrc/spread.hip, k_spread with FX): the footprint lane map (rows split
+among the 16-lane groups of an 8-byte LDS access), the 64-bit tile indices of every add, the
+staged-point record, and the lane roles of the one read that carries the FQ points' window
+words, axis-0 weights and values to the readlane broadcasts.  Computed the way the kernel
+computes them and checked against the sizes of what they index, for every tile and window
+width the library launches (kernel tile 13, A*b tile 12, widths 4..8).  Runs on the CPU; no
+kernel is launched."""
+import itertools
+
+import numpy as np
+import pytest
+
+SP_PB, PSTR, FQ, NTH = 96, 24, 4, 512
+LDS_CU = 160 * 1024
+
+
+def place_rows(r, W, rp, G, grp):
+    if r == W:
+        return True
+    cap = 64 // G
+    for g in range(G):
+        n = sum(1 for q in range(r) if grp[q] == g)
+        if (n + 1) * W > cap:
+            continue
+        ok = all((q * rp + i) % cap != (r * rp + j) % cap
+                 for q in range(r) if grp[q] == g for i in range(W) for j in range(W))
+        if not ok:
+            continue
+        grp[r] = g
+        if place_rows(r + 1, W, rp, G, grp):
+            return True
+    return False
+
+
+def row_groups(rp, W, G):
+    grp = [0] * 8
+    if not place_rows(0, W, rp, G, grp):
+        return -1
+    return sum(grp[r] << (2 * r) for r in range(W))
+
+
+def row_pitch(PT, W, G):
+    for rp in range(PT, PT + 32):
+        if row_groups(rp, W, G) >= 0:
+            return rp
+    return PT
+
+
+def lane_map(W, groups, G=4):
+    """(j2, j3, act) of every lane, as the kernel derives them."""
+    out = []
+    for lane in range(64):
+        j2 = j3 = 0
+        act = False
+        if groups >= 0:
+            g, idx = lane // (64 // G), lane % (64 // G)
+            rank = idx // W
+            seen = 0
+            for r in range(W):
+                if (groups >> (2 * r)) & 3 != g:
+                    continue
+                if seen == rank:
+                    j2, j3, act = r, idx - rank * W, True
+                seen += 1
+        else:
+            act = lane < W * W
+            jl = lane if act else 0
+            j2, j3 = jl // W, jl - (jl // W) * W
+        out.append((j2, j3, act))
+    return out
+
+
+CASES = [(13, W, False) for W in range(4, 9)] + [(12, W, True) for W in range(4, 9)]
+
+
+@pytest.mark.parametrize("T,W,cplx", CASES)
+def test_footprint_lanes_and_tile_indices(T, W, cplx):
+    PT = T + W
+    RP = row_pitch(PT, W, 4)
+    PP = PT * RP
+    NV = 2 if cplx else 1
+    groups = row_groups(RP, W, 4)
+    lanes = lane_map(W, groups)
+    cells = [(j2, j3) for j2, j3, act in lanes if act]
+    # every footprint cell has exactly one lane
+    assert sorted(cells) == [(a, b) for a in range(W) for b in range(W)]
+    if groups >= 0:
+        # within each group of 16 lanes the active cells fall in distinct 8-byte banks
+        for g in range(4):
+            offs = [(j2 * RP + j3) % 16 for j2, j3, act in lanes[16 * g:16 * g + 16] if act]
+            assert len(offs) == len(set(offs))
+    # every add of every point lands in the tile: window starts are clamped to [0, PT - W]
+    size = NV * PT * PP
+    for l0, l1, l2 in itertools.product((0, 1, PT - W - 1, PT - W), repeat=3):
+        for j2, j3, act in lanes:
+            if not act:
+                continue
+            cb = l0 * PP + (l1 + j2) * RP + l2 + j3
+            for r in range(W):
+                idx = cb + r * PP + (PT * PP if cplx else 0)
+                assert 0 <= cb + r * PP and idx < size
+    # the tile's flush visits each cell once: li = l0 PP + l1 RP + l2 over PT^3 cells, distinct
+    li = {(a * PP + b * RP + c) for a in range(PT) for b in range(PT) for c in range(PT)}
+    assert len(li) == PT ** 3 and max(li) < PT * PP
+
+
+@pytest.mark.parametrize("T,W,cplx", CASES)
+def test_staged_record_and_uniform_read(T, W, cplx):
+    PT = T + W
+    RP = row_pitch(PT, W, 4)
+    NV = 2 if cplx else 1
+    # staging: item (point p, axis d) writes weights at p PSTR + 8 d + j and byte d of pt_lo[p]
+    for p, d, j in itertools.product(range(SP_PB), range(3), range(W)):
+        assert p * PSTR + 8 * d + j < SP_PB * PSTR and 8 * d + j < PSTR
+        assert 4 * p + d < 4 * SP_PB
+    # the uniform read: roles of the lanes and the lanes the readlanes take
+    assert FQ * 8 + FQ * (3 if cplx else 1) <= 64
+    for nb in (1, 2, 7, 8, 9, 33, 95, 96):
+        for wv in range(NTH // 64):
+            for p0 in range(wv, nb, FQ * (NTH // 64)):
+                pq = [min(p0 + q * (NTH // 64), nb - 1) for q in range(FQ)]
+                for lane in range(64):
+                    if lane < 32:
+                        uq = lane >> 3
+                    elif lane < 32 + FQ:
+                        uq = lane - 32
+                    else:
+                        uq = ((lane - 32 - FQ) >> 1) % FQ
+                    pl = pq[uq]
+                    assert 0 <= pl < nb
+                    if lane < 32:
+                        assert pl * PSTR + (lane & 7) < SP_PB * PSTR
+                    elif lane < 32 + FQ or not cplx:
+                        assert pl < SP_PB
+                    else:
+                        assert 2 * pl + (lane & 1) < 2 * SP_PB
+                # readlane sources: weight r of point q, window word of q, value components of q
+                for q in range(FQ):
+                    for r in range(W):
+                        assert (8 * q + r) >> 3 == q and (8 * q + r) & 7 == r
+                    assert 32 + q - 32 == q
+                    if cplx:
+                        for c in range(2):
+                            ln = 32 + FQ + 2 * q + c
+                            assert ln < 64 and ((ln - 32 - FQ) >> 1) % FQ == q and (ln & 1) == c
+    # LDS of one workgroup: the 64-bit tile, the staged points and the queue of the kernel
+    lds = NV * PT * PT * RP * 8 + SP_PB * PSTR * 4 + SP_PB * 4 + (SP_PB * 8 if cplx else 0) + 1024 * 4 + NTH * 4
+    wgs = 1 if (cplx or W >= 8) else 2
+    assert wgs * lds <= LDS_CU
+
+
+def test_fixed_point_sums_are_exact_and_order_free():
+    """The tile adds integer terms below 2^31 in 64-bit cells: any order gives the same sum, and
+    up to 2^32 terms cannot overflow, so the flush sees the exact sum of the rounded terms."""
+    rng = np.random.default_rng(5)
+    terms = rng.integers(-(2 ** 31) + 1, 2 ** 31, 10000, dtype=np.int64)
+    s1 = int(np.sum(terms))
+    s2 = int(np.sum(rng.permutation(terms)))
+    assert s1 == s2 == sum(int(t) for t in terms)
+    assert (2 ** 31) * (2 ** 32) <= 2 ** 63
