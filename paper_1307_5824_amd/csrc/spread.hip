@@ -15,21 +15,16 @@
 // spread exactly once.
 //
 // LDS float atomics run at a small fraction of the plain read/write rate on this
-// chip, 64-bit integer atomics at about the plain rate.  The kernel's tile (Ker)
-// is therefore accumulated in fixed point: 64-bit integer cells, each term the
-// FP32 product rounded to an integer in units of 1/fxs (|term| < 2^31), added
-// with one integer atomic per cell.  Integer sums are exact and independent of
-// the order of the adds, so every wavefront takes any staged point.  The per-point
-// window weights are computed once, one thread per point and axis, and staged in
-// LDS; the lanes of a wavefront sit on the W x W footprint of the last two axes
-// and add the point's W rows.
-//
-// The A*b tile keeps FP32 cells without atomics.  Each wavefront owns a slab of
-// rows (first tile axis) of the padded tile; the staged points are ranked by the
-// window's first row, and every wavefront walks the points whose W rows meet its
-// slab: all rows of the slab are read, updated and written back.  Within one
-// instruction the lanes' cells are distinct and no two wavefronts write the same
-// row, so the plain read-modify-write is race-free.  Only the half disk (k1 > 0, or k1 = 0 and
+// chip, 64-bit integer atomics at about the plain rate.  The tile is therefore
+// accumulated in fixed point: 64-bit integer cells, each term the FP32 product
+// rounded to an integer in units of 1/fxs (a power of 2 with |term| < 2^31),
+// added with one integer atomic per cell.  Integer sums are exact and independent
+// of the order of the adds, so every wavefront takes any staged point.  The
+// per-point window weights are computed once, one thread per point and axis, and
+// staged in LDS; the lanes of a wavefront sit on the W x W footprint of the last
+// two axes and add the point's W rows.  Ker's terms are non-negative; A*b is
+// spread one component (re, then im) per launch, with signed terms and a unit
+// that follows from the largest |component| of the data.  Only the half disk (k1 > 0, or k1 = 0 and
 // k2 > 0) is spread: its partner -k is folded in (Ker is real and even; for A*b
 // the pair (k, -k) gives the real part exactly), and k = 0 is added afterwards
 // in closed form.
@@ -65,6 +60,7 @@ struct SpreadArgs {
     // are at fx_bmax (the largest |component| of the data), found on the device before the launch
     const unsigned* fx_bmax;
     float fx_coef;
+    int comp;  // complex data spread one component at a time: the component (0 re, 1 im)
 };
 
 template <int W>
@@ -130,40 +126,30 @@ __device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, do
     return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
 }
 
-// Two workgroups per CU, except the W = 8 complex and fixed-point tiles, which fit one.
-template <int T, int W, bool CPLX, int NTH, bool FX>
-__global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX)) ? NTH / 256 : NTH / 128)) k_spread(SpreadArgs a) {
+// One tile plane of 64-bit integer cells.  Complex data (A*b) is spread one component per
+// launch (a.comp), so that its tile is as small as the kernel's: two workgroups per CU up to
+// W = 7, one for W = 8.
+template <int T, int W, bool CPLX, int NTH>
+__global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_spread(SpreadArgs a) {
     constexpr int SP_THREADS = NTH, SP_WAVES = NTH / 64;
     constexpr int PT = T + W;
     constexpr int PADLO = (W + 1) / 2 - 1;
     constexpr int NCELL = PT * PT * PT;
-    constexpr int H = (PT + SP_WAVES - 1) / SP_WAVES;  // rows per wavefront slab
-    // FP32 slabs: the real tile holds floats; the complex tile holds (re, im) pairs, one 8-byte
-    // access per cell.  Fixed point (FX): 64-bit integer cells, one plane per component.
-    constexpr int G = (CPLX || FX) ? 4 : 2;            // lane groups of one LDS access
+    constexpr int G = 4;                               // lane groups of an 8-byte LDS access
     constexpr int RP = row_pitch(PT, W, G);            // LDS pitch of a tile row, in cells (conflict-free)
     constexpr int GROUPS = row_groups(RP, W, G);       // lane group of every footprint row
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
-    constexpr int NR = FX ? PT : SP_WAVES * H;         // planes (slabs: padded to whole slabs)
-    constexpr int NV = CPLX ? 2 : 1;                   // components per cell
-    // staged point.  Slabs: the weights of the NR tile rows (0 outside the window), then the
-    // window weights of axes 1 and 2.  FX: the W weights of axes 0, 1, 2 at 0, 8, 16.  Stride in
-    // floats.
-    constexpr int PSTR = FX ? 24 : ((NR + 2 * W) + 3) / 4 * 4;
+    // staged point: the W window weights of axes 0, 1, 2 at 0, 8, 16 (axis 0 times the point's
+    // value in fixed-point units); stride in floats
+    constexpr int PSTR = 24;
     static_assert(W <= 8, "window width");
-    constexpr int SP_PB = 96;                          // points staged per batch (two tiles per CU)
-    constexpr int NK = PT - W + 1;                     // possible first rows of a window
-    static_assert(NK <= 64, "first-row buckets");
-    static_assert(FX || (NR % 4 == 0 && PSTR % 4 == 0), "row weights zeroed as float4");
+    constexpr int SP_PB = 96;                          // points staged per batch
     constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
-    __shared__ __align__(16) float tile[FX ? 1 : NV * NR * PP];  // complex: (re, im) per cell
-    __shared__ __align__(16) unsigned long long tile64[FX ? NV * PT * PP : 1];  // re plane, im plane
+    __shared__ __align__(16) unsigned long long tile64[PT * PP];
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
-    __shared__ int pt_lo[SP_PB];                       // window starts of axes 1, 2 in bytes 1, 2
-    __shared__ float2 pt_v[CPLX ? SP_PB : 1];
-    __shared__ int st_kr[SP_PB];                       // batch position -> first row | rank << 8
-    __shared__ int bcnt[NK], bstart[NK];
+    __shared__ int pt_lo[SP_PB];                       // window starts of axes 0, 1, 2 in bytes 0, 1, 2
     __shared__ int img_m[SP_THREADS];
+    __shared__ int rs_l[CPLX ? 264 : 1];              // row starts of the disk order (N <= 256)
     __shared__ int queue[SP_QCAP];
     __shared__ int nimg, qn, qfail, any;
 
@@ -171,7 +157,7 @@ __global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX))
     const int4 wk = a.work[blockIdx.x];
     float fxs = a.fxs;
     double fx_inv = a.fx_inv;
-    if (FX && a.fx_bmax) {
+    if (a.fx_bmax) {
         const float bm = __uint_as_float(*a.fx_bmax);
         int e = 0;
         if (bm > 0.f) e = (int)fmin(fmax(floor(log2((double)a.fx_coef / (double)bm)), -100.0), 100.0);
@@ -183,13 +169,10 @@ __global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX))
     const int L = a.L, N = a.N;
     const double halfL = 0.5 * L;
 
-    if constexpr (FX) {
-        for (int i = tid; i < NV * PT * PP; i += SP_THREADS) tile64[i] = 0ull;
-    } else {
-        for (int i = tid; i < NV * NR * PP; i += SP_THREADS) tile[i] = 0.f;
-    }
-    for (int i = tid; i < NK; i += SP_THREADS) bcnt[i] = 0;
+    for (int i = tid; i < PT * PP; i += SP_THREADS) tile64[i] = 0ull;
     if (tid == 0) { any = 0; nimg = 0; qn = 0; qfail = SP_QCAP; }
+    if constexpr (CPLX)
+        for (int i = tid; i <= a.N; i += SP_THREADS) rs_l[i] = a.rowstart[i];
 
     const double tc0 = tt0 * T + 0.5 * T - halfL, tc1 = tt1 * T + 0.5 * T - halfL, tc2 = tt2 * T + 0.5 * T - halfL;
     const double Rt = T * 0.8660254037844386 + 1e-3;
@@ -204,19 +187,38 @@ __global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX))
         // select between addresses, which puts them in scratch memory
         const int tv0 = tt0, tv1 = tt1, tv2 = tt2;
         const int wv = tid >> 6, lane = tid & 63;
-        const int r0 = wv * H;                                   // this wave's rows [r0, r0 + H)
+        // footprint cell (j2, j3) of this lane: lane group g holds the rows assigned to it, W
+        // lanes per row
+        int j2 = 0, j3 = 0;
+        bool act = false;
+        if constexpr (GROUPS >= 0) {
+            const int g = lane / (64 / G), idx = lane % (64 / G), rank = idx / W;
+            int seen = 0;
+#pragma unroll
+            for (int r = 0; r < W; ++r) {
+                if (((GROUPS >> (2 * r)) & 3) != g) continue;
+                if (seen == rank) {
+                    j2 = r;
+                    j3 = idx - rank * W;
+                    act = true;
+                }
+                ++seen;
+            }
+        } else {
+            act = lane < W * W;
+            const int jl = act ? lane : 0;
+            j2 = jl / W;
+            j3 = jl - j2 * W;
+        }
         for (int pb = 0; pb < nq; pb += SP_PB) {
             const int nb = min(SP_PB, nq - pb);
-            // stage the batch in three steps.  (1) One item per (point, axis), spread over all
-            // threads: the window start and weights along that axis; the axis-0 item also
-            // computes the point's value and ranks the point among those with the same first
-            // row (bucket counts in LDS).  (2) One wave turns the counts into bucket starts.
-            // (3) Every item writes its weights to the point's slot, bucket start + rank, so
-            // that the points meeting a wavefront's slab form one contiguous range.
+            // stage the batch: one item per (point, axis), spread over all threads, computes the
+            // window start and weights along that axis; the axis-0 item also computes the point's
+            // value and folds it, in fixed-point units, into its weights.  The point keeps its
+            // batch position.
             float ph[NIT][W];
             int lod[NIT], pp[NIT], dd[NIT];
             float scale = 1.f;
-            float2 pval = make_float2(0.f, 0.f);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int i = tid + it * SP_THREADS;
@@ -246,243 +248,85 @@ __global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX))
                         const int g = a.group ? a.group[m] : 0;
                         const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
                         if constexpr (!CPLX) {
-                            scale = 2.f * h * h * (FX ? fxs : 1.f);
+                            scale = 2.f * h * h * fxs;
                         } else {
-                            if constexpr (FX) scale = fxs;
                             // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
-                            const int idx = a.rowstart[k1 + N / 2] + k2;
+                            const int idx = rs_l[k1 + N / 2] + k2;
                             const float2 bp = a.b[(int64_t)m * a.P + idx];
                             const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
                             const float sr = bp.x + bm.x, si = bp.y - bm.y;
                             float cs = 1.f, sn = 0.f;
                             if (a.shifts) {
-                                const double th = 6.283185307179586 * (k1 * a.shifts[2 * (int64_t)m] +
-                                                                      k2 * a.shifts[2 * (int64_t)m + 1]) / N;
-                                cs = (float)cos(th);
-                                sn = (float)sin(th);
+                                // theta / 2 pi reduced to [-1/2, 1/2] in FP64, then the FP32 sine and
+                                // cosine of pi times twice that
+                                const double f = (k1 * a.shifts[2 * (int64_t)m] + k2 * a.shifts[2 * (int64_t)m + 1]) / N;
+                                sincospif((float)(2.0 * (f - rint(f))), &sn, &cs);
                             }
-                            pval = make_float2(h * (cs * sr - sn * si), h * (cs * si + sn * sr));
+                            scale = fxs * h * (a.comp ? cs * si + sn * sr : cs * sr - sn * si);
                         }
-                        if constexpr (!FX) st_kr[p] = lod[it] | (atomicAdd(&bcnt[lod[it]], 1) << 8);
                     }
                 }
-            }
-            if constexpr (!FX) {
-                __syncthreads();
-                if (tid < 64) {  // exclusive scan of the bucket counts; the counts restart at zero
-                    const int v = tid < NK ? bcnt[tid] : 0;
-                    int incl = v;
-#pragma unroll
-                    for (int o = 1; o < 64; o <<= 1) {
-                        const int t = __shfl_up(incl, o, 64);
-                        if (tid >= o) incl += t;
-                    }
-                    if (tid < NK) {
-                        bstart[tid] = incl - v;
-                        bcnt[tid] = 0;
-                    }
-                }
-                __syncthreads();
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int d = dd[it];
                 if (d < 0) continue;
-                if constexpr (FX) {
-                    // the point keeps its batch position: weights of axis d at 8 d, window starts
-                    // in the bytes of pt_lo
-                    float* q = pt_w + pp[it] * PSTR + 8 * d;
+                // weights of axis d at 8 d, window starts in the bytes of pt_lo
+                float* q = pt_w + pp[it] * PSTR + 8 * d;
 #pragma unroll
-                    for (int j = 0; j < W; ++j) q[j] = d == 0 ? scale * ph[it][j] : ph[it][j];
-                    reinterpret_cast<unsigned char*>(pt_lo)[4 * pp[it] + d] = (unsigned char)lod[it];
-                    if (CPLX && d == 0) pt_v[pp[it]] = pval;
-                    continue;
-                }
-                const int kr = st_kr[pp[it]];
-                const int slot = bstart[kr & 255] + (kr >> 8);
-                float* q = pt_w + slot * PSTR;
-                if (d == 0) {
-                    // rows of the padded tile: zero, then the window's W rows
-#pragma unroll
-                    for (int r = 0; r < NR; r += 4) *reinterpret_cast<float4*>(q + r) = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-                    for (int j = 0; j < W; ++j) q[lod[it] + j] = scale * ph[it][j];
-                    if constexpr (CPLX) pt_v[slot] = pval;
-                } else {
-                    const int off = d == 1 ? NR : NR + W;
-#pragma unroll
-                    for (int j = 0; j < W; ++j) q[off + j] = ph[it][j];
-                    reinterpret_cast<unsigned char*>(pt_lo)[4 * slot + d] = (unsigned char)lod[it];
-                }
+                for (int j = 0; j < W; ++j) q[j] = d == 0 ? scale * ph[it][j] : ph[it][j];
+                reinterpret_cast<unsigned char*>(pt_lo)[4 * pp[it] + d] = (unsigned char)lod[it];
             }
             __syncthreads();
-            // this wavefront's points: first row in [r0 - W + 1, r0 + H - 1], taken two at a time;
-            // when the two footprints are disjoint both points' rows are read before either is
-            // written back (two independent read-modify-write chains in flight)
-            const int vlo = max(0, r0 - W + 1), vhi = min(NK - 1, r0 + H - 1);
-            const int pbeg = vlo <= vhi ? bstart[vlo] : 0;
-            const int pend = vlo <= vhi ? (vhi + 1 < NK ? bstart[vhi + 1] : nb) : 0;
-            constexpr int A2 = NR, A3 = NR + W;
-            // footprint cell (j2, j3) of this lane: lane group g holds the rows assigned to it,
-            // W lanes per row
-            int j2 = 0, j3 = 0;
-            bool act = false;
-            if constexpr (GROUPS >= 0) {
-                const int g = lane / (64 / G), idx = lane % (64 / G), rank = idx / W;
-                int seen = 0;
+            // The wavefronts take the batch's points in turn, the lanes on the W x W footprint of
+            // axes 1 and 2, one 64-bit integer atomic add per cell and window row.  Integer
+            // addition is associative, so the tile is exact and independent of the order of the
+            // adds; each term is the FP32 product rounded to an integer (|term| < 2^31 by the
+            // choice of fxs).  A wavefront takes FQ of its points at a time: their window words and
+            // axis-0 weights (the same for every lane) arrive in one LDS read spread over the
+            // lanes and are then broadcast from registers (readlane); each footprint lane reads
+            // its own axis-1 and axis-2 weights.  All reads of the FQ points come before their
+            // adds, so the wavefront waits once per FQ points (LDS completes in order, so a read
+            // issued after adds waits for them).  The lanes off the footprint take part in the
+            // reads only.
+            constexpr int FQ = 4;  // the register list of the asm statement below names 4
+            static_assert(FQ * 8 + FQ <= 64, "one read for the uniform data");
+            const int wvu = __builtin_amdgcn_readfirstlane(wv);
+            // lane roles of the uniform read: 8 q + k -> weight k of point q (k < 8); 32 + q -> window
+            // word of point q; the other lanes repeat point q's window word
+            const int uq = lane < 32 ? (lane >> 3) : (lane - 32) % FQ;
+            for (int p0 = wvu; p0 < nb; p0 += FQ * SP_WAVES) {
+                int pq[FQ];
 #pragma unroll
-                for (int r = 0; r < W; ++r) {
-                    if (((GROUPS >> (2 * r)) & 3) != g) continue;
-                    if (seen == rank) {
-                        j2 = r;
-                        j3 = idx - rank * W;
-                        act = true;
-                    }
-                    ++seen;
+                for (int q = 0; q < FQ; ++q) pq[q] = min(p0 + q * SP_WAVES, nb - 1);
+                int pl = pq[0];
+#pragma unroll
+                for (int q = 1; q < FQ; ++q) pl = uq == q ? pq[q] : pl;
+                const float* src = lane < 32 ? pt_w + pl * PSTR + (lane & 7) : reinterpret_cast<const float*>(pt_lo + pl);
+                float w2[FQ], w3[FQ];
+#pragma unroll
+                for (int q = 0; q < FQ; ++q) {
+                    w2[q] = pt_w[pq[q] * PSTR + 8 + j2];
+                    w3[q] = pt_w[pq[q] * PSTR + 16 + j3];
                 }
-            } else {
-                act = lane < W * W;
-                const int jl = act ? lane : 0;
-                j2 = jl / W;
-                j3 = jl - j2 * W;
-            }
-            if constexpr (FX) {
-                // fixed point: the wavefronts take the batch's points in turn, the lanes on the
-                // W x W footprint of axes 1 and 2, one 64-bit integer atomic add per cell and
-                // window row.  Integer addition is associative, so the tile is exact and
-                // independent of the order of the adds; each term is the FP32 product
-                // rounded to an integer (|term| < 2^31 by the choice of fxs).
-                // A wavefront takes FQ of its points at a time.  Their window words, axis-0
-                // weights and values (the same for every lane) arrive in one LDS read spread over
-                // the lanes and are then broadcast from registers (readlane); each footprint lane
-                // reads its own axis-1 and axis-2 weights.  All reads of the FQ points come before
-                // their adds, so the wavefront waits once per FQ points (LDS completes in order,
-                // so a read issued after adds waits for them).  The lanes off the footprint take
-                // part in the reads only.
-                constexpr int FQ = 4;  // the register list of the asm statement below names 4
-                static_assert(FQ * 8 + FQ * (CPLX ? 3 : 1) <= 64, "one read for the uniform data");
-                const int wvu = __builtin_amdgcn_readfirstlane(wv);
-                // lane roles of the uniform read: 8 q + k -> weight k of point q (k < 8); 32 + q ->
-                // window word of point q; 32 + FQ + 2 q + c -> component c of the value of point q
-                const int uq = lane < 32 ? (lane >> 3) : (lane < 32 + FQ ? lane - 32 : ((lane - 32 - FQ) >> 1) % FQ);
-                for (int p0 = wvu; p0 < nb; p0 += FQ * SP_WAVES) {
-                    int pq[FQ];
+                float u = *src;
+                // all the reads are issued here, before any register of theirs is used
+                asm volatile("" : "+v"(u), "+v"(w2[0]), "+v"(w3[0]), "+v"(w2[1]), "+v"(w3[1]),
+                             "+v"(w2[2]), "+v"(w3[2]), "+v"(w2[3]), "+v"(w3[3]));
+                if (!act) continue;
 #pragma unroll
-                    for (int q = 0; q < FQ; ++q) pq[q] = min(p0 + q * SP_WAVES, nb - 1);
-                    int pl = pq[0];
+                for (int q = 0; q < FQ; ++q) {
+                    if (p0 + q * SP_WAVES >= nb) break;
+                    const float w23 = w2[q] * w3[q];
+                    const int lw = __builtin_amdgcn_readlane(__float_as_int(u), 32 + q);
+                    const int cb = (lw & 255) * PP + (((lw >> 8) & 255) + j2) * RP + ((lw >> 16) & 255) + j3;
 #pragma unroll
-                    for (int q = 1; q < FQ; ++q) pl = uq == q ? pq[q] : pl;
-                    const float* src = lane < 32 ? pt_w + pl * PSTR + (lane & 7)
-                                     : (lane < 32 + FQ || !CPLX) ? reinterpret_cast<const float*>(pt_lo + pl)
-                                                                 : reinterpret_cast<const float*>(pt_v + pl) + (lane & 1);
-                    float w2[FQ], w3[FQ];
-#pragma unroll
-                    for (int q = 0; q < FQ; ++q) {
-                        w2[q] = pt_w[pq[q] * PSTR + 8 + j2];
-                        w3[q] = pt_w[pq[q] * PSTR + 16 + j3];
-                    }
-                    float u = *src;
-                    // all the reads are issued here, before any register of theirs is used
-                    asm volatile("" : "+v"(u), "+v"(w2[0]), "+v"(w3[0]), "+v"(w2[1]), "+v"(w3[1]),
-                                 "+v"(w2[2]), "+v"(w3[2]), "+v"(w2[3]), "+v"(w3[3]));
-                    float w23[FQ];
-#pragma unroll
-                    for (int q = 0; q < FQ; ++q) w23[q] = w2[q] * w3[q];
-                    if (!act) continue;
-#pragma unroll
-                    for (int q = 0; q < FQ; ++q) {
-                        if (p0 + q * SP_WAVES >= nb) break;
-                        const int lw = __builtin_amdgcn_readlane(__float_as_int(u), 32 + q);
-                        const int cb = (lw & 255) * PP + (((lw >> 8) & 255) + j2) * RP + ((lw >> 16) & 255) + j3;
-                        if constexpr (!CPLX) {
-#pragma unroll
-                            for (int r = 0; r < W; ++r) {
-                                const float wxr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 8 * q + r));
-                                __hip_atomic_fetch_add(&tile64[cb + r * PP],
-                                                       (unsigned long long)(unsigned)fmaf(wxr, w23[q], 0.5f),
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            }
-                        } else {
-                            const float vx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 32 + FQ + 2 * q));
-                            const float vy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 33 + FQ + 2 * q));
-                            const float ar = w23[q] * vx, ai = w23[q] * vy;
-#pragma unroll
-                            for (int r = 0; r < W; ++r) {
-                                const float wxr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 8 * q + r));
-                                const long long qr = (int)rintf(wxr * ar), qi = (int)rintf(wxr * ai);
-                                __hip_atomic_fetch_add(&tile64[cb + r * PP], (unsigned long long)qr,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                                __hip_atomic_fetch_add(&tile64[PT * PP + cb + r * PP], (unsigned long long)qi,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            }
-                        }
-                    }
-                }
-                __syncthreads();
-                continue;
-            }
-            struct Pt {
-                int cb, l1, l2;
-                float rw[H];
-                float w23;
-                float2 v;
-            };
-            auto load = [&](int pi, Pt& q) {
-                const float* w = pt_w + pi * PSTR;
-                const int lw = pt_lo[pi];
-                q.l1 = (lw >> 8) & 255;
-                q.l2 = (lw >> 16) & 255;
-                q.cb = r0 * PP + (q.l1 + j2) * RP + q.l2 + j3;
-#pragma unroll
-                for (int k = 0; k < H; ++k) q.rw[k] = w[r0 + k];
-                q.w23 = w[A2 + j2] * w[A3 + j3];
-                q.v = CPLX ? pt_v[pi] : make_float2(0.f, 0.f);
-            };
-            // rows of the slab: read, then add weight * value (weight 0 outside the window)
-            auto rd = [&](const Pt& q, float (&vr)[H], float (&vi)[H]) {
-#pragma unroll
-                for (int k = 0; k < H; ++k) {
-                    if constexpr (CPLX) {
-                        const float2 t = reinterpret_cast<const float2*>(tile)[q.cb + k * PP];
-                        vr[k] = t.x;
-                        vi[k] = t.y;
-                    } else {
-                        vr[k] = tile[q.cb + k * PP];
-                    }
-                }
-            };
-            auto wr = [&](const Pt& q, const float (&vr)[H], const float (&vi)[H]) {
-                if constexpr (!CPLX) {
-#pragma unroll
-                    for (int k = 0; k < H; ++k) tile[q.cb + k * PP] = fmaf(q.rw[k], q.w23, vr[k]);
-                } else {
-                    const float sr = q.w23 * q.v.x, si = q.w23 * q.v.y;
-#pragma unroll
-                    for (int k = 0; k < H; ++k)
-                        reinterpret_cast<float2*>(tile)[q.cb + k * PP] =
-                            make_float2(fmaf(q.rw[k], sr, vr[k]), fmaf(q.rw[k], si, vi[k]));
-                }
-            };
-            for (int pi = pbeg; pi < pend; pi += 2) {
-                const bool two = pi + 1 < pend;
-                Pt a, b;
-                load(pi, a);
-                load(two ? pi + 1 : pi, b);
-                const bool apart = two && (abs(a.l1 - b.l1) >= W || abs(a.l2 - b.l2) >= W);
-                float ar[H], ai[H], br[H], bi[H];
-                if (act) {
-                    if (apart) {
-                        rd(a, ar, ai);
-                        rd(b, br, bi);
-                        wr(a, ar, ai);
-                        wr(b, br, bi);
-                    } else {
-                        rd(a, ar, ai);
-                        wr(a, ar, ai);
-                        if (two) {
-                            rd(b, br, bi);
-                            wr(b, br, bi);
-                        }
+                    for (int r = 0; r < W; ++r) {
+                        const float wxr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(u), 8 * q + r));
+                        // Ker: non-negative terms; a component of complex data: signed terms
+                        const unsigned long long t = CPLX ? (unsigned long long)(long long)(int)rintf(wxr * w23)
+                                                          : (unsigned long long)(unsigned)fmaf(wxr, w23, 0.5f);
+                        __hip_atomic_fetch_add(&tile64[cb + r * PP], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                 }
             }
@@ -640,24 +484,13 @@ __global__ void __launch_bounds__(NTH, ((CPLX && FX) || (W >= 8 && (CPLX || FX))
         const int g1 = ((o1 + l1 - L / 2) % L + L) % L;
         const int g2 = ((o2 + l2 - L / 2) % L + L) % L;
         const int64_t gi = ((int64_t)g0 * L + g1) * L + g2;
-        if constexpr (FX) {
-            if constexpr (!CPLX) {
-                const unsigned long long v = tile64[li];
-                if (v) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, (float)((double)v * fx_inv));
-            } else {
-                const long long vr = (long long)tile64[li], vi = (long long)tile64[PT * PP + li];
-                float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
-                if (vr) unsafeAtomicAdd(gp, (float)((double)vr * fx_inv));
-                if (vi) unsafeAtomicAdd(gp + 1, (float)((double)vi * fx_inv));
-            }
-        } else if (!CPLX) {
-            const float v = tile[li];
-            if (v != 0.f) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, v);
+        // the exact integer sum, rounded once to FP32; complex data: component a.comp
+        if constexpr (!CPLX) {
+            const unsigned long long v = tile64[li];
+            if (v) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + gi, (float)((double)v * fx_inv));
         } else {
-            const float2 v = reinterpret_cast<const float2*>(tile)[li];
-            float* gp = reinterpret_cast<float*>(a.grid) + 2 * gi;
-            if (v.x != 0.f) unsafeAtomicAdd(gp, v.x);
-            if (v.y != 0.f) unsafeAtomicAdd(gp + 1, v.y);
+            const long long v = (long long)tile64[li];
+            if (v) unsafeAtomicAdd(reinterpret_cast<float*>(a.grid) + 2 * gi + a.comp, (float)((double)v * fx_inv));
         }
     }
 }
@@ -741,12 +574,11 @@ __global__ void k_f2d(const float* __restrict__ a, double* __restrict__ o, int64
 
 int grid_blocks(int64_t n) { return (int)std::min<int64_t>((n + 255) / 256, 65536); }
 
-// Ker: fixed-point tile (64-bit cells), 8 wavefronts taking the points in turn.  A*b (two FP32
-// tiles, re and im): 4 wavefronts with 5-row slabs.  Two workgroups fit the LDS of a compute unit
-// in both cases.
-template <int T, bool CPLX, bool FX, int NTH = (CPLX && !FX) ? 256 : 512>
+// 8 wavefronts per workgroup; the tile and the staging fit two workgroups in the LDS of a compute
+// unit (one for W = 8).
+template <int T, bool CPLX, int NTH = 512>
 hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* grid, const float2* b, float fxs,
-                         const unsigned* fx_bmax = nullptr, float fx_coef = 0.f) {
+                         const unsigned* fx_bmax = nullptr, float fx_coef = 0.f, int comp = 0) {
     SpreadArgs a;
     a.N = p->N; a.M = p->M; a.L = L; a.nt = (L + T - 1) / T;
     a.s = (double)L / p->N;
@@ -754,14 +586,14 @@ hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* g
     a.poly = p->kb_poly; a.work = reinterpret_cast<const int4*>(work); a.grid = grid;
     a.b = b; a.shifts = p->shifts; a.rowstart = p->rowstart; a.P = p->P;
     a.fxs = fxs; a.fx_inv = 1.0 / (double)fxs;
-    a.fx_bmax = fx_bmax; a.fx_coef = fx_coef;
+    a.fx_bmax = fx_bmax; a.fx_coef = fx_coef; a.comp = comp;
     if (nwork == 0) return hipSuccess;
     switch (p->kbw) {
-        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
-        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX, NTH, FX>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 4: hipLaunchKernelGGL((k_spread<T, 4, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 5: hipLaunchKernelGGL((k_spread<T, 5, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 6: hipLaunchKernelGGL((k_spread<T, 6, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 7: hipLaunchKernelGGL((k_spread<T, 7, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
+        case 8: hipLaunchKernelGGL((k_spread<T, 8, CPLX, NTH>), dim3(nwork), dim3(NTH), 0, p->stream, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -820,7 +652,7 @@ hipError_t fill_zero(void* ptr, size_t bytes, hipStream_t s) {
 }
 
 hipError_t spread_ker(firm_plan p, float* grid) {
-    return launch_spread<SP_TILE_REAL, false, true>(p, 4 * p->N, p->tiles_ker, p->ntiles_ker, grid, nullptr, p->fx_ker);
+    return launch_spread<SP_TILE_REAL, false>(p, 4 * p->N, p->tiles_ker, p->ntiles_ker, grid, nullptr, p->fx_ker);
 }
 
 hipError_t spread_atb(firm_plan p, const float2* b, float2* grid) {
@@ -831,8 +663,13 @@ hipError_t spread_atb(firm_plan p, const float2* b, float2* grid) {
                        reinterpret_cast<const float4*>(b), n / 2, b + (n / 2) * 2, (int)(n % 2), p->fx_bmax);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return launch_spread<SP_TILE_CPLX, true, true>(p, 2 * p->N, p->tiles_atb, p->ntiles_atb, grid, b, 1.f,
-                                                  p->fx_bmax, p->fx_atb_coef);
+    // one component per launch: a one-plane tile leaves room for two workgroups per CU
+    for (int comp = 0; comp < 2; ++comp) {
+        e = launch_spread<SP_TILE_CPLX, true>(p, 2 * p->N, p->tiles_atb, p->ntiles_atb, grid, b, 1.f,
+                                                         p->fx_bmax, p->fx_atb_coef, comp);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t atb_k0_term(firm_plan p, const float2* b, double* out) {

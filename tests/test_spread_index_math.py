@@ -2,10 +2,10 @@
 (paper_1307_5824_amd/csrc/spread.hip, k_spread with FX): the footprint lane map (rows split
 among the 16-lane groups of an 8-byte LDS access), the 64-bit tile indices of every add, the
 staged-point record, and the lane roles of the one read that carries the FQ points' window
-words, axis-0 weights and values to the readlane broadcasts.  Computed the way the kernel
-computes them and checked against the sizes of what they index, for every tile and window
-width the library launches (kernel tile 13, A*b tile 12, widths 4..8).  Runs on the CPU; no
-kernel is launched."""
+words and axis-0 weights to the readlane broadcasts.  Computed the way the kernel computes them
+and checked against the sizes of what they index, for every tile and window width the library
+launches: the kernel's tile 13 and the A*b tile 12, one component per launch (a one-plane tile),
+widths 4..8.  Runs on the CPU; no kernel is launched."""
 import itertools
 
 import numpy as np
@@ -71,6 +71,8 @@ def lane_map(W, groups, G=4):
     return out
 
 
+# (tile, width, complex data): the complex data is spread one component per launch into a
+# one-plane tile of signed terms, so both cases index one plane
 CASES = [(13, W, False) for W in range(4, 9)] + [(12, W, True) for W in range(4, 9)]
 
 
@@ -79,7 +81,7 @@ def test_footprint_lanes_and_tile_indices(T, W, cplx):
     PT = T + W
     RP = row_pitch(PT, W, 4)
     PP = PT * RP
-    NV = 2 if cplx else 1
+    NV = 1
     groups = row_groups(RP, W, 4)
     lanes = lane_map(W, groups)
     cells = [(j2, j3) for j2, j3, act in lanes if act]
@@ -98,8 +100,8 @@ def test_footprint_lanes_and_tile_indices(T, W, cplx):
                 continue
             cb = l0 * PP + (l1 + j2) * RP + l2 + j3
             for r in range(W):
-                idx = cb + r * PP + (PT * PP if cplx else 0)
-                assert 0 <= cb + r * PP and idx < size
+                idx = cb + r * PP
+                assert 0 <= idx < size
     # the tile's flush visits each cell once: li = l0 PP + l1 RP + l2 over PT^3 cells, distinct
     li = {(a * PP + b * RP + c) for a in range(PT) for b in range(PT) for c in range(PT)}
     assert len(li) == PT ** 3 and max(li) < PT * PP
@@ -109,13 +111,12 @@ def test_footprint_lanes_and_tile_indices(T, W, cplx):
 def test_staged_record_and_uniform_read(T, W, cplx):
     PT = T + W
     RP = row_pitch(PT, W, 4)
-    NV = 2 if cplx else 1
     # staging: item (point p, axis d) writes weights at p PSTR + 8 d + j and byte d of pt_lo[p]
     for p, d, j in itertools.product(range(SP_PB), range(3), range(W)):
         assert p * PSTR + 8 * d + j < SP_PB * PSTR and 8 * d + j < PSTR
         assert 4 * p + d < 4 * SP_PB
     # the uniform read: roles of the lanes and the lanes the readlanes take
-    assert FQ * 8 + FQ * (3 if cplx else 1) <= 64
+    assert FQ * 8 + FQ <= 64
     for nb in (1, 2, 7, 8, 9, 33, 95, 96):
         for wv in range(NTH // 64):
             for p0 in range(wv, nb, FQ * (NTH // 64)):
@@ -131,22 +132,23 @@ def test_staged_record_and_uniform_read(T, W, cplx):
                     assert 0 <= pl < nb
                     if lane < 32:
                         assert pl * PSTR + (lane & 7) < SP_PB * PSTR
-                    elif lane < 32 + FQ or not cplx:
-                        assert pl < SP_PB
                     else:
-                        assert 2 * pl + (lane & 1) < 2 * SP_PB
-                # readlane sources: weight r of point q, window word of q, value components of q
+                        assert pl < SP_PB
+                # readlane sources: weight r of point q, window word of q
                 for q in range(FQ):
                     for r in range(W):
                         assert (8 * q + r) >> 3 == q and (8 * q + r) & 7 == r
                     assert 32 + q - 32 == q
-                    if cplx:
-                        for c in range(2):
-                            ln = 32 + FQ + 2 * q + c
-                            assert ln < 64 and ((ln - 32 - FQ) >> 1) % FQ == q and (ln & 1) == c
-    # LDS of one workgroup: the 64-bit tile, the staged points and the queue of the kernel
-    lds = NV * PT * PT * RP * 8 + SP_PB * PSTR * 4 + SP_PB * 4 + (SP_PB * 8 if cplx else 0) + 1024 * 4 + NTH * 4
-    wgs = 1 if (cplx or W >= 8) else 2
+    # the A*b staging reads the disk's row starts from LDS (N + 1 entries loaded, 264 declared)
+    # at k1 + N/2 for the half disk's rows 0 <= k1 <= N/2
+    for N in (8, 16, 32, 64, 128, 256):
+        assert max(k1 + N // 2 for k1 in range(N // 2 + 1)) <= N < 264
+    # LDS of one workgroup: the 64-bit tile, the staged points, the queue, the view slots (and the
+    # row starts for complex data); two workgroups share a CU up to width 7
+    lds = PT * PT * RP * 8 + SP_PB * PSTR * 4 + SP_PB * 4 + 1024 * 4 + NTH * 4
+    if cplx:
+        lds += 264 * 4
+    wgs = 1 if W >= 8 else 2
     assert wgs * lds <= LDS_CU
 
 
