@@ -142,8 +142,10 @@ firm_status firm_kernel_set(firm_plan plan, const float* ker_dev);
 firm_status firm_set_regularizer(firm_plan plan, int order, double mu);
 
 /* Step 2 (section 3.4): atb_dev (N^3 floats) = Re A*(re-centred b) (eq. backprojection)
- * for slices b_dev (device, M x P complex64).  Exact real part for any b: the
- * spread uses the pair (k, -k) as b(k) + conj(b(-k)). */
+ * for slices b_dev (device, M x P complex64, finite values).  Exact real part for any b: the
+ * spread uses the pair (k, -k) as b(k) + conj(b(-k)).  The gridding accumulates exact
+ * fixed-point sums whose unit follows the largest |component| of b (found on the device first),
+ * so the result's accuracy is that of FP32 terms for any overall scale of b. */
 firm_status firm_backproject(firm_plan plan, const void* b_dev, float* atb_dev);
 
 /* The forward projector (eq. forward-projector) with the imaging model of section 3.1:
