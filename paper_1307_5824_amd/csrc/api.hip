@@ -145,7 +145,8 @@ void firm_plan_destroy(firm_plan p) {
                    p->partials2, p->partials3, p->scal, p->dhalf, p->S1, p->grid, p->ws1, p->ws2,
                    p->tiles_ker, p->tiles_atb, p->dscal, p->rowstart, p->flags, p->khat64, p->T1d,
                    p->T2d, p->tw64, p->x64, p->r64, p->p64, p->q64, p->y64, p->atb64, p->rhs, p->dvec,
-                   p->img_ws, p->khat16, p->shtab, p->uws, p->usc};
+                   p->img_ws, p->khat16, p->shtab, p->uws, p->usc, p->c12s, p->nrms, p->groups, p->shiftss,
+                   p->vorder, p->vbox};
     for (void* d : dev)
         if (d) (void)hipFree(d);
     if (p->host_scal) (void)hipHostFree(p->host_scal);
@@ -236,6 +237,59 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
         k0 += h0 * h0;
     }
     p->ker_k0 = k0;
+    // The gridding visits the views in the order of their planes' normals: each normal folded to
+    // the hemisphere where its largest component is positive, keyed by that axis and a Morton
+    // code of the other two components over it, so that a block of SP_VBLK consecutive views
+    // spans a small cone and the box of its normals lets a tile skip the whole block.
+    std::vector<int32_t> vord(M);
+    std::vector<double> c12s((size_t)M * 6);
+    std::vector<float> nrms((size_t)M * 4);
+    std::vector<int32_t> grps(M);
+    std::vector<double> shs(shifts ? (size_t)M * 2 : 0);
+    const int nvblk = (M + SP_VBLK - 1) / SP_VBLK;
+    std::vector<float4> vbox((size_t)nvblk * 2);
+    {
+        std::vector<std::pair<uint64_t, int32_t>> key(M);
+        for (int m = 0; m < M; ++m) {
+            const float* n = &nrm[4 * (size_t)m];
+            int ax = 0;
+            for (int d = 1; d < 3; ++d)
+                if (std::fabs(n[d]) > std::fabs(n[ax])) ax = d;
+            const double inv = 1.0 / (double)n[ax];  // |n[ax]| >= 1/sqrt(3)
+            const double u = n[(ax + 1) % 3] * inv, v = n[(ax + 2) % 3] * inv;  // in [-1, 1]
+            const uint32_t qu = (uint32_t)std::min(1023.0, std::max(0.0, (u + 1.0) * 511.5));
+            const uint32_t qv = (uint32_t)std::min(1023.0, std::max(0.0, (v + 1.0) * 511.5));
+            uint64_t mort = 0;
+            for (int b = 0; b < 10; ++b) mort |= (uint64_t)((qu >> b) & 1u) << (2 * b) | (uint64_t)((qv >> b) & 1u) << (2 * b + 1);
+            key[m] = {((uint64_t)ax << 20) | mort, m};
+        }
+        std::stable_sort(key.begin(), key.end());
+        for (int j = 0; j < M; ++j) {
+            const int m = key[j].second;
+            vord[j] = m;
+            for (int d = 0; d < 6; ++d) c12s[6 * (size_t)j + d] = c12[6 * (size_t)m + d];
+            const float* n = &nrm[4 * (size_t)m];
+            int ax = 0;
+            for (int d = 1; d < 3; ++d)
+                if (std::fabs(n[d]) > std::fabs(n[ax])) ax = d;
+            const float sg = n[ax] < 0.f ? -1.f : 1.f;  // the same plane; the tests use |n . x|
+            for (int d = 0; d < 3; ++d) nrms[4 * (size_t)j + d] = sg * n[d];
+            nrms[4 * (size_t)j + 3] = 0.f;
+            grps[j] = grp[m];
+            if (shifts) { shs[2 * (size_t)j] = shifts[2 * (size_t)m]; shs[2 * (size_t)j + 1] = shifts[2 * (size_t)m + 1]; }
+        }
+        for (int bk = 0; bk < nvblk; ++bk) {
+            float lo[3] = {1e30f, 1e30f, 1e30f}, hi[3] = {-1e30f, -1e30f, -1e30f};
+            double l1 = 0.0;
+            for (int j = bk * SP_VBLK; j < std::min(M, (bk + 1) * SP_VBLK); ++j) {
+                const float* n = &nrms[4 * (size_t)j];
+                for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], n[d]); hi[d] = std::max(hi[d], n[d]); }
+                l1 = std::max(l1, (double)std::fabs(n[0]) + std::fabs(n[1]) + std::fabs(n[2]));
+            }
+            vbox[2 * (size_t)bk] = make_float4(lo[0], lo[1], lo[2], (float)(l1 * (1.0 + 1e-6)));
+            vbox[2 * (size_t)bk + 1] = make_float4(hi[0], hi[1], hi[2], 0.f);
+        }
+    }
     std::vector<int> rowstart(N + 1);
     {
         int off = 0;
@@ -289,6 +343,12 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     chk(dalloc(&p->group, (size_t)M));
     if (ctf_table) chk(dalloc(&p->table, (size_t)G * Q));
     if (shifts) chk(dalloc(&p->shifts, (size_t)M * 2));
+    chk(dalloc(&p->c12s, c12s.size()));
+    chk(dalloc(&p->nrms, nrms.size()));
+    chk(dalloc(&p->groups, (size_t)M));
+    if (shifts) chk(dalloc(&p->shiftss, (size_t)M * 2));
+    chk(dalloc(&p->vorder, (size_t)M));
+    chk(dalloc(&p->vbox, vbox.size()));
     chk(dalloc(&p->kb_poly, poly.size()));
     chk(dalloc(&p->deconv_ker, dker.size()));
     chk(dalloc(&p->deconv_atb, datb.size()));
@@ -333,6 +393,12 @@ firm_status firm_plan_create(firm_plan* out, int N, int M, const double* rot, co
     up(p->group, grp.data(), grp.size() * sizeof(int32_t));
     if (ctf_table) up(p->table, ctf_table, (size_t)G * Q * sizeof(float));
     if (shifts) up(p->shifts, shifts, (size_t)M * 2 * sizeof(double));
+    up(p->c12s, c12s.data(), c12s.size() * sizeof(double));
+    up(p->nrms, nrms.data(), nrms.size() * sizeof(float));
+    up(p->groups, grps.data(), grps.size() * sizeof(int32_t));
+    if (shifts) up(p->shiftss, shs.data(), shs.size() * sizeof(double));
+    up(p->vorder, vord.data(), vord.size() * sizeof(int32_t));
+    up(p->vbox, vbox.data(), vbox.size() * sizeof(float4));
     up(p->kb_poly, poly.data(), poly.size() * sizeof(float));
     up(p->deconv_ker, dker.data(), dker.size() * sizeof(float));
     up(p->deconv_atb, datb.data(), datb.size() * sizeof(float));

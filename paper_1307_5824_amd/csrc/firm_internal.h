@@ -35,6 +35,15 @@ struct firm_plan_s {
     int32_t* group = nullptr;  // M
     float* table = nullptr;    // G x Q (h), or null
     double* shifts = nullptr;  // M x 2 or null
+    // the same per-view arrays in the gridding's view order (normals folded to one hemisphere and
+    // sorted along a space-filling curve of their direction), its map to the caller's order, and
+    // per block of SP_VBLK views the box of the normals and the largest |n|_1
+    double* c12s = nullptr;
+    float* nrms = nullptr;
+    int32_t* groups = nullptr;
+    double* shiftss = nullptr;
+    int32_t* vorder = nullptr;  // gridding position -> view index
+    float4* vbox = nullptr;     // 2 per block: (min n, max |n|_1), (max n, 0)
     double ker_k0 = 0.0;       // sum_m h_m(0)^2: the k = 0 term of Ker
 
     // Kaiser-Bessel window (device)
@@ -201,6 +210,7 @@ hipError_t precond_set(firm_plan p, const float* d_centred);
 std::vector<int> spread_worklist(int L, int T, int M, double s);
 int spread_tile_real();
 int spread_tile_cplx();
+constexpr int SP_VBLK = 512;  // views per block of the gridding's view order (its workgroup size)
 void kb_tables(firm_plan p, std::vector<float>& poly, std::vector<float>& dker, std::vector<float>& datb);
 
 // block count helper

@@ -61,6 +61,10 @@ struct SpreadArgs {
     const unsigned* fx_bmax;
     float fx_coef;
     int comp;  // complex data spread one component at a time: the component (0 re, 1 im)
+    // the per-view arrays above are in the gridding's view order; vorder maps a position to the
+    // caller's view index (for b), vbox holds per block of SP_VBLK views the box of the normals
+    const int* vorder;
+    const float4* vbox;
 };
 
 template <int W>
@@ -252,8 +256,9 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                         } else {
                             // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
                             const int idx = rs_l[k1 + N / 2] + k2;
-                            const float2 bp = a.b[(int64_t)m * a.P + idx];
-                            const float2 bm = a.b[(int64_t)m * a.P + (a.P - 1 - idx)];
+                            const int64_t mo = a.vorder[m];  // the caller's view index
+                            const float2 bp = a.b[mo * a.P + idx];
+                            const float2 bm = a.b[mo * a.P + (a.P - 1 - idx)];
                             const float sr = bp.x + bm.x, si = bp.y - bm.y;
                             float cs = 1.f, sn = 0.f;
                             if (a.shifts) {
@@ -365,18 +370,32 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     for (int mb = wk.y; mb < wk.z; mb += VPT * SP_THREADS) {
         unsigned pendv = 0u;  // this thread's views of the chunk that meet the tile, not yet in a slot
         {
+            // a block of SP_VBLK views whose box of normals n gives no |n . c| within the bound
+            // below for the tile's centre c holds no view that meets the tile: skipped whole
             float4 nv[VPT];
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
-                const int m = mb + v * SP_THREADS + tid;
-                nv[v] = m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                const int m0 = mb + v * SP_THREADS, m = m0 + tid;
+                bool live = m0 < wk.z;
+                if (live) {
+                    const float4 lo = a.vbox[2 * (m0 / SP_THREADS)], hi = a.vbox[2 * (m0 / SP_THREADS) + 1];
+                    const double p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
+                    const double p2 = tc2 * lo.z, q2 = tc2 * hi.z;
+                    const double dmin = fmin(p0, q0) + fmin(p1, q1) + fmin(p2, q2);
+                    const double dmax = fmax(p0, q0) + fmax(p1, q1) + fmax(p2, q2);
+                    const double lim = 0.5 * T * lo.w + 3e-3;
+                    live = dmin <= lim && dmax >= -lim;
+                }
+                nv[v] = live && m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+                if (!live) nv[v].w = 1.f;  // marks the view as skipped
             }
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
                 // the plane meets the tile's cube: distance of the centre at most the cube's half
                 // extent along the normal
                 const int m = mb + v * SP_THREADS + tid;
-                if (m < wk.z && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
+                if (m < wk.z && nv[v].w == 0.f && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
                                     0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3)
                     pendv |= 1u << v;
             }
@@ -582,9 +601,11 @@ hipError_t launch_spread(firm_plan p, int L, const int* work, int nwork, void* g
     SpreadArgs a;
     a.N = p->N; a.M = p->M; a.L = L; a.nt = (L + T - 1) / T;
     a.s = (double)L / p->N;
-    a.c12 = p->c12; a.nrm = p->nrm; a.group = p->group; a.table = p->table; a.Q = p->Q;
+    a.c12 = p->c12s; a.nrm = p->nrms; a.group = p->groups; a.table = p->table; a.Q = p->Q;
     a.poly = p->kb_poly; a.work = reinterpret_cast<const int4*>(work); a.grid = grid;
-    a.b = b; a.shifts = p->shifts; a.rowstart = p->rowstart; a.P = p->P;
+    a.b = b; a.shifts = p->shiftss; a.rowstart = p->rowstart; a.P = p->P;
+    a.vorder = p->vorder; a.vbox = p->vbox;
+    static_assert(NTH == SP_VBLK, "a culling round's view blocks are the host's normal-box blocks");
     a.fxs = fxs; a.fx_inv = 1.0 / (double)fxs;
     a.fx_bmax = fx_bmax; a.fx_coef = fx_coef; a.comp = comp;
     if (nwork == 0) return hipSuccess;
@@ -623,7 +644,9 @@ std::vector<int> spread_worklist(int L, int T, int M, double s) {
                 const double frac = rho <= Rt ? 1.0 : Rt / rho;
                 const double expect = frac * M;
                 const int nch = std::max(1, (int)std::ceil(expect / chunk));
-                const int per = (M + nch - 1) / nch;
+                // ranges start on multiples of SP_VBLK: the spread's culling rounds read the normal
+                // boxes of whole blocks
+                const int per = ((M + nch - 1) / nch + SP_VBLK - 1) / SP_VBLK * SP_VBLK;
                 for (int k = 0; k < nch; ++k) {
                     const int m0 = k * per, m1 = std::min(M, m0 + per);
                     if (m0 < m1) items.push_back({expect / nch, (a * nt + b) * nt + c, m0, m1});

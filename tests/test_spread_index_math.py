@@ -161,3 +161,44 @@ def test_fixed_point_sums_are_exact_and_order_free():
     s2 = int(np.sum(rng.permutation(terms)))
     assert s1 == s2 == sum(int(t) for t in terms)
     assert (2 ** 31) * (2 ** 32) <= 2 ** 63
+
+
+def test_normal_box_culling_never_drops_a_view():
+    """The spread skips a block of 512 views when the box of their (hemisphere-folded) normals
+    gives no |n . c| within 0.5 T max|n|_1 + 3e-3 of the tile's centre c.  Emulated with the
+    kernel's expressions (FP32 normals, FP64 products): whenever some view of a block passes the
+    per-view plane test, the block test passes too; and the test does prune."""
+    rng = np.random.default_rng(11)
+    M, T, L = 4096, 13, 1024
+    # a concentrated cluster and uniform directions, as the workloads' view distributions
+    n = rng.standard_normal((M, 3))
+    n[: M // 2] = n[: M // 2] * 0.2 + np.array([0.3, 0.5, 0.8])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    n = n.astype(np.float32)
+    ax = np.argmax(np.abs(n), axis=1)
+    sg = np.where(n[np.arange(M), ax] < 0, -1.0, 1.0).astype(np.float32)
+    nf = n * sg[:, None]
+    u = n[np.arange(M), (ax + 1) % 3] / n[np.arange(M), ax]
+    v = n[np.arange(M), (ax + 2) % 3] / n[np.arange(M), ax]
+    qu = np.clip((u + 1.0) * 511.5, 0, 1023).astype(np.int64)
+    qv = np.clip((v + 1.0) * 511.5, 0, 1023).astype(np.int64)
+    mort = np.zeros(M, dtype=np.int64)
+    for b in range(10):
+        mort |= ((qu >> b) & 1) << (2 * b) | ((qv >> b) & 1) << (2 * b + 1)
+    order = np.argsort((ax.astype(np.int64) << 20) | mort, kind="stable")
+    ns = nf[order]
+    skipped = 0
+    for t in range(200):
+        tc = (rng.integers(0, L // T, 3) * T + 0.5 * T - 0.5 * L).astype(np.float64)
+        for bk in range(M // 512):
+            blk = ns[bk * 512:(bk + 1) * 512].astype(np.float64)
+            per_view = np.abs(blk @ tc) <= 0.5 * T * np.abs(blk).sum(axis=1) + 2e-3
+            lo, hi = blk.min(axis=0).astype(np.float32), blk.max(axis=0).astype(np.float32)
+            l1 = np.float32(np.abs(blk).sum(axis=1).max() * (1 + 1e-6))
+            p, q = tc * lo.astype(np.float64), tc * hi.astype(np.float64)
+            dmin, dmax = np.minimum(p, q).sum(), np.maximum(p, q).sum()
+            lim = 0.5 * T * float(l1) + 3e-3
+            live = dmin <= lim and dmax >= -lim
+            assert live or not per_view.any()
+            skipped += not live
+    assert skipped > 0
