@@ -373,6 +373,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             // a block of SP_VBLK views whose box of normals n gives no |n . c| within the bound
             // below for the tile's centre c holds no view that meets the tile: skipped whole
             float4 nv[VPT];
+            unsigned livev = 0u;
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
                 const int m0 = mb + v * SP_THREADS, m = m0 + tid;
@@ -386,17 +387,16 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     const double lim = 0.5 * T * lo.w + 3e-3;
                     live = dmin <= lim && dmax >= -lim;
                 }
-                nv[v] = live && m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m)
-                                         : make_float4(0.f, 0.f, 0.f, 0.f);
-                if (!live) nv[v].w = 1.f;  // marks the view as skipped
+                live = live && m < wk.z;
+                nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                livev |= (unsigned)live << v;
             }
 #pragma unroll
             for (int v = 0; v < VPT; ++v) {
                 // the plane meets the tile's cube: distance of the centre at most the cube's half
                 // extent along the normal
-                const int m = mb + v * SP_THREADS + tid;
-                if (m < wk.z && nv[v].w == 0.f && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
-                                    0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3)
+                if (((livev >> v) & 1u) && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
+                                                0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3)
                     pendv |= 1u << v;
             }
         }
