@@ -178,10 +178,11 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     if constexpr (CPLX)
         for (int i = tid; i <= a.N; i += SP_THREADS) rs_l[i] = a.rowstart[i];
 
-    const double tc0 = tt0 * T + 0.5 * T - halfL, tc1 = tt1 * T + 0.5 * T - halfL, tc2 = tt2 * T + 0.5 * T - halfL;
-    const double Rt = T * 0.8660254037844386 + 1e-3;
-    const double rk = Rt / a.s;
-    const int S = (int)floor(2.0 * rk) + 3;
+    // the tile's centre (relative to the grid's centre) in FP32: the plane tests carry margins of
+    // 2e-3 and more against its rounding (< 3e-5 at |c| <= 512), and the candidate rows one row
+    const float tc0 = tt0 * T + 0.5f * T - 0.5f * L, tc1 = tt1 * T + 0.5f * T - 0.5f * L, tc2 = tt2 * T + 0.5f * T - 0.5f * L;
+    const float rk = (T * 0.8660254f + 1e-3f) / (float)a.s, inv_s = 1.f / (float)a.s;
+    const int S = (int)floorf(2.f * rk) + 3;
     const int N2 = N * N;
 
     // points of the queue [0, nq) staged and accumulated in batches of SP_PB
@@ -380,11 +381,11 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                 bool live = m0 < wk.z;
                 if (live) {
                     const float4 lo = a.vbox[2 * (m0 / SP_THREADS)], hi = a.vbox[2 * (m0 / SP_THREADS) + 1];
-                    const double p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
-                    const double p2 = tc2 * lo.z, q2 = tc2 * hi.z;
-                    const double dmin = fmin(p0, q0) + fmin(p1, q1) + fmin(p2, q2);
-                    const double dmax = fmax(p0, q0) + fmax(p1, q1) + fmax(p2, q2);
-                    const double lim = 0.5 * T * lo.w + 3e-3;
+                    const float p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
+                    const float p2 = tc2 * lo.z, q2 = tc2 * hi.z;
+                    const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
+                    const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
+                    const float lim = 0.5f * T * lo.w + 3e-3f;
                     live = dmin <= lim && dmax >= -lim;
                 }
                 live = live && m < wk.z;
@@ -395,8 +396,8 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             for (int v = 0; v < VPT; ++v) {
                 // the plane meets the tile's cube: distance of the centre at most the cube's half
                 // extent along the normal
-                if (((livev >> v) & 1u) && fabs(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
-                                                0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3)
+                if (((livev >> v) & 1u) && fabsf(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
+                                                0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f)
                     pendv |= 1u << v;
             }
         }
@@ -426,8 +427,8 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     const int v = u / S;
                     sl = base + v;
                     const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const double u1 = (tc0 * c[0] + tc1 * c[1] + tc2 * c[2]) / a.s;
-                    k1 = (int)ceil(u1 - rk) - 1 + (u - v * S);
+                    const float u1 = (tc0 * (float)c[0] + tc1 * (float)c[1] + tc2 * (float)c[2]) * inv_s;
+                    k1 = (int)ceilf(u1 - rk) - 1 + (u - v * S);
                     if (k1 >= 0 && 4 * k1 * k1 <= N2) {
                         const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
                         float lo = (float)-kd, hi = (float)kd;
