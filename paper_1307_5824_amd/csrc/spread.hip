@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     __shared__ int rs_l[CPLX ? 264 : 1];              // row starts of the disk order (N <= 256)
     __shared__ int queue[SP_QCAP];
     __shared__ int nimg, qn, qfail, any;
+    __shared__ float geo[12];  // the tile's constants (see below)
 
     const int tid = threadIdx.x;
     const int4 wk = a.work[blockIdx.x];
@@ -179,10 +180,26 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
         for (int i = tid; i <= a.N; i += SP_THREADS) rs_l[i] = a.rowstart[i];
 
     // the tile's centre (relative to the grid's centre) in FP32: the plane tests carry margins of
-    // 2e-3 and more against its rounding (< 3e-5 at |c| <= 512), and the candidate rows one row
-    const float tc0 = tt0 * T + 0.5f * T - 0.5f * L, tc1 = tt1 * T + 0.5f * T - 0.5f * L, tc2 = tt2 * T + 0.5f * T - 0.5f * L;
-    const float rk = (T * 0.8660254f + 1e-3f) / (float)a.s, inv_s = 1.f / (float)a.s;
-    const int S = (int)floorf(2.f * rk) + 3;
+    // 2e-3 and more against its rounding (< 3e-5 at |c| <= 512), and the candidate rows one row.
+    // These tile constants are the same in every lane; they are kept in LDS (geo) and read where
+    // they are used, since vector registers holding them across the loops below would spill.
+    enum { G_TC0, G_TC1, G_TC2, G_BLO0, G_BLO1, G_BLO2, G_BHI0, G_BHI1, G_BHI2, G_RK, G_INVS, G_N };
+    const int S = (int)floorf(2.f * ((T * 0.8660254f + 1e-3f) / (float)a.s)) + 3;
+    if (tid == 0) {
+        // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
+        // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
+        // grid.  Each interval is then trimmed to the exact one with the FP64 cell test.
+        constexpr float MARGIN = 1e-2f, FAR = 1e30f;
+        const int tt[3] = {tt0, tt1, tt2};
+        for (int d = 0; d < 3; ++d) {
+            geo[G_TC0 + d] = tt[d] * T + 0.5f * T - 0.5f * L;
+            geo[G_BLO0 + d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
+            geo[G_BHI0 + d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
+        }
+        geo[G_RK] = (T * 0.8660254f + 1e-3f) / (float)a.s;
+        geo[G_INVS] = 1.f / (float)a.s;
+    }
+    __syncthreads();  // the counters, the tile constants and the row starts are in place
     const int N2 = N * N;
 
     // points of the queue [0, nq) staged and accumulated in batches of SP_PB
@@ -340,13 +357,6 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
         }
     };
 
-    // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
-    // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
-    // grid.  Each interval is then trimmed to the exact one with the FP64 cell test.
-    constexpr float MARGIN = 1e-2f, FAR = 1e30f;
-    const float blo0 = tt0 == 0 ? -FAR : tt0 * T - MARGIN, bhi0 = (tt0 + 1) * T >= L ? FAR : (tt0 + 1) * T + MARGIN;
-    const float blo1 = tt1 == 0 ? -FAR : tt1 * T - MARGIN, bhi1 = (tt1 + 1) * T >= L ? FAR : (tt1 + 1) * T + MARGIN;
-    const float blo2 = tt2 == 0 ? -FAR : tt2 * T - MARGIN, bhi2 = (tt2 + 1) * T >= L ? FAR : (tt2 + 1) * T + MARGIN;
 
     // the point (k1, k2) of the view with columns c lies in the tile (the test that decides
     // which tile spreads a point): inside the disk and its clamped cell in the tile per axis
@@ -379,6 +389,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             for (int v = 0; v < VPT; ++v) {
                 const int m0 = mb + v * SP_THREADS, m = m0 + tid;
                 bool live = m0 < wk.z;
+                const float tc0 = geo[G_TC0], tc1 = geo[G_TC1], tc2 = geo[G_TC2];
                 if (live) {
                     const float4 lo = a.vbox[2 * (m0 / SP_THREADS)], hi = a.vbox[2 * (m0 / SP_THREADS) + 1];
                     const float p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
@@ -396,7 +407,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             for (int v = 0; v < VPT; ++v) {
                 // the plane meets the tile's cube: distance of the centre at most the cube's half
                 // extent along the normal
-                if (((livev >> v) & 1u) && fabsf(tc0 * nv[v].x + tc1 * nv[v].y + tc2 * nv[v].z) <=
+                if (((livev >> v) & 1u) && fabsf(geo[G_TC0] * nv[v].x + geo[G_TC1] * nv[v].y + geo[G_TC2] * nv[v].z) <=
                                                 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f)
                     pendv |= 1u << v;
             }
@@ -427,16 +438,16 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     const int v = u / S;
                     sl = base + v;
                     const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const float u1 = (tc0 * (float)c[0] + tc1 * (float)c[1] + tc2 * (float)c[2]) * inv_s;
-                    k1 = (int)ceilf(u1 - rk) - 1 + (u - v * S);
+                    const float u1 = (geo[G_TC0] * (float)c[0] + geo[G_TC1] * (float)c[1] + geo[G_TC2] * (float)c[2]) *
+                                     geo[G_INVS];
+                    k1 = (int)ceilf(u1 - geo[G_RK]) - 1 + (u - v * S);
                     if (k1 >= 0 && 4 * k1 * k1 <= N2) {
                         const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
                         float lo = (float)-kd, hi = (float)kd;
                         bool ok = true;
 #pragma unroll
                         for (int d = 0; d < 3; ++d) {
-                            const float bl = d == 0 ? blo0 : (d == 1 ? blo1 : blo2);
-                            const float bh = d == 0 ? bhi0 : (d == 1 ? bhi1 : bhi2);
+                            const float bl = geo[G_BLO0 + d], bh = geo[G_BHI0 + d];
                             const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
                             if (fabsf(be) < 1e-6f) {
                                 ok = ok && al >= bl && al <= bh;
