@@ -184,7 +184,10 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     // These tile constants are the same in every lane; they are kept in LDS (geo) and read where
     // they are used, since vector registers holding them across the loops below would spill.
     enum { G_TC0, G_TC1, G_TC2, G_BLO0, G_BLO1, G_BLO2, G_BHI0, G_BHI1, G_BHI2, G_RK, G_INVS, G_N };
-    const int S = (int)floorf(2.f * ((T * 0.8660254f + 1e-3f) / (float)a.s)) + 3;
+    // candidate rows of a view: the k1 within rk of the projection u1 of the tile's centre onto the
+    // plane (rk: the circumscribed sphere's radius in lattice units), widened by 1e-3 for the
+    // rounding of u1: S = floor(2 rk + 2e-3) + 2 rows from ceil(u1 - rk - 1e-3)
+    const int S = (int)floorf(2.f * ((T * 0.8660254f + 1e-3f) / (float)a.s) + 2e-3f) + 2;
     if (tid == 0) {
         // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
         // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
@@ -440,7 +443,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     const double* c = a.c12 + 6 * (int64_t)img_m[sl];
                     const float u1 = (geo[G_TC0] * (float)c[0] + geo[G_TC1] * (float)c[1] + geo[G_TC2] * (float)c[2]) *
                                      geo[G_INVS];
-                    k1 = (int)ceilf(u1 - geo[G_RK]) - 1 + (u - v * S);
+                    k1 = (int)ceilf(u1 - geo[G_RK] - 1e-3f) + (u - v * S);
                     if (k1 >= 0 && 4 * k1 * k1 <= N2) {
                         const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
                         float lo = (float)-kd, hi = (float)kd;
