@@ -157,6 +157,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     __shared__ int queue[SP_QCAP];
     __shared__ int nimg, qn, qfail, any;
     __shared__ float geo[12];  // the tile's constants (see below)
+    __shared__ unsigned short lmap[64];  // footprint cell of each lane (see below)
 
     const int tid = threadIdx.x;
     const int4 wk = a.work[blockIdx.x];
@@ -202,18 +203,11 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
         geo[G_RK] = (T * 0.8660254f + 1e-3f) / (float)a.s;
         geo[G_INVS] = 1.f / (float)a.s;
     }
-    __syncthreads();  // the counters, the tile constants and the row starts are in place
-    const int N2 = N * N;
-
-    // points of the queue [0, nq) staged and accumulated in batches of SP_PB
-    auto process = [&](int nq) {
-        if (tid == 0 && nq > 0) any = 1;
-        // tile coordinates as values: a select between the captured references would be a
-        // select between addresses, which puts them in scratch memory
-        const int tv0 = tt0, tv1 = tt1, tv2 = tt2;
-        const int wv = tid >> 6, lane = tid & 63;
-        // footprint cell (j2, j3) of this lane: lane group g holds the rows assigned to it, W
-        // lanes per row
+    if (tid < 64) {
+        // footprint cell (j2, j3) of each lane: lane group g holds the rows assigned to it, W lanes
+        // per row; kept in LDS and read where the adds need it (registers holding it across the
+        // staging would spill)
+        const int lane = tid;
         int j2 = 0, j3 = 0;
         bool act = false;
         if constexpr (GROUPS >= 0) {
@@ -235,6 +229,18 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             j2 = jl / W;
             j3 = jl - j2 * W;
         }
+        lmap[lane] = (unsigned short)(j2 | (j3 << 4) | ((int)act << 8));
+    }
+    __syncthreads();  // the counters, the tile constants, the lane map and the row starts are in place
+    const int N2 = N * N;
+
+    // points of the queue [0, nq) staged and accumulated in batches of SP_PB
+    auto process = [&](int nq) {
+        if (tid == 0 && nq > 0) any = 1;
+        // tile coordinates as values: a select between the captured references would be a
+        // select between addresses, which puts them in scratch memory
+        const int tv0 = tt0, tv1 = tt1, tv2 = tt2;
+        const int wv = tid >> 6, lane = tid & 63;
         for (int pb = 0; pb < nq; pb += SP_PB) {
             const int nb = min(SP_PB, nq - pb);
             // stage the batch: one item per (point, axis), spread over all threads, computes the
@@ -315,6 +321,9 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             // adds, so the wavefront waits once per FQ points (LDS completes in order, so a read
             // issued after adds waits for them).  The lanes off the footprint take part in the
             // reads only.
+            const int lm = lmap[lane];
+            const int j2 = lm & 15, j3 = (lm >> 4) & 15;
+            const bool act = (lm >> 8) != 0;
             constexpr int FQ = 4;  // the register list of the asm statement below names 4
             static_assert(FQ * 8 + FQ <= 64, "one read for the uniform data");
             const int wvu = __builtin_amdgcn_readfirstlane(wv);
