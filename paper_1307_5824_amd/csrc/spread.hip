@@ -153,6 +153,8 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
     __shared__ int pt_lo[SP_PB];                       // window starts of axes 0, 1, 2 in bytes 0, 1, 2
     __shared__ int img_m[SP_THREADS];
+    __shared__ int img_o[CPLX ? SP_THREADS : 1];  // complex data: the slot's view in the caller's order
+    __shared__ int img_g[CPLX ? SP_THREADS : 1];  // complex data: the slot's CTF group
     __shared__ int rs_l[CPLX ? 264 : 1];              // row starts of the disk order (N <= 256)
     __shared__ int queue[SP_QCAP];
     __shared__ int nimg, qn, qfail, any;
@@ -276,14 +278,14 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     // also keeps the LDS accesses inside the tile should rounding ever differ
                     lod[it] = min(max(b0 - (ttd * T - PADLO), 0), PT - W);
                     if (d == 0) {
-                        const int g = a.group ? a.group[m] : 0;
+                        const int g = CPLX ? img_g[sl] : a.group[m];
                         const float h = a.table ? a.table[(int64_t)g * a.Q + k1 * k1 + k2 * k2] : 1.f;
                         if constexpr (!CPLX) {
                             scale = 2.f * h * h * fxs;
                         } else {
                             // h exp(i theta) (b(k) + conj b(-k)), theta = 2 pi <k, s_m> / N (re-centring)
                             const int idx = rs_l[k1 + N / 2] + k2;
-                            const int64_t mo = a.vorder[m];  // the caller's view index
+                            const int64_t mo = img_o[sl];  // the caller's view index
                             const float2 bp = a.b[mo * a.P + idx];
                             const float2 bm = a.b[mo * a.P + (a.P - 1 - idx)];
                             const float sr = bp.x + bm.x, si = bp.y - bm.y;
@@ -436,6 +438,16 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             }
             __syncthreads();
             const int top = min(nimg, SP_THREADS);
+            if constexpr (CPLX) {
+                // the new slots' CTF groups and views in the caller's order, read once per slot
+                // here (in parallel) rather than by the staging of every point
+                if (tid >= base && tid < top) {
+                    const int m = img_m[tid];
+                    img_o[tid] = a.vorder[m];
+                    img_g[tid] = a.group[m];
+                }
+                __syncthreads();
+            }
             // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
             // plus the disk and half-disk bounds), trimmed to the exact test at both ends (the cell
             // along a row is monotone in k2, so the points that pass form an interval), then the
