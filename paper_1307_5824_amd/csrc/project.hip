@@ -215,23 +215,27 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
         const int q0 = ((o0 + l0) % L + L) % L, q1 = ((o1 + l1) % L + L) % L, q2 = ((o2 + l2) % L + L) % L;
         tile[i] = grid_value(a.X, L, N, a.QP, q0, q1, q2);
     }
-    if (tid == 0) { qn = 0; nimg = 0; }
-
-    const double tc[3] = {tt[0] * T + 0.5 * T - halfL, tt[1] * T + 0.5 * T - halfL, tt[2] * T + 0.5 * T - halfL};
-    const double Rt = T * 0.8660254037844386 + 1e-3;
-    const double rk = Rt / a.s;
-    const int S = (int)floor(2.0 * rk) + 3;  // candidate rows per view
-    const int N2 = N * N;
-    // positions tau whose (clamped) cell lies in the tile, widened by a margin far above the
-    // rounding of the FP32 row intervals; the edge tiles also own the clamped cells beyond the
-    // grid.  Each interval is then trimmed to the exact one with the FP64 cell test.
-    constexpr float MARGIN = 1e-2f, FAR = 1e30f;
-    float blo[3], bhi[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
-        bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
+    // The tile's constants, the same in every lane, kept in LDS and read where they are used
+    // (vector registers holding them across the loops below would spill): its centre relative to
+    // the grid's centre in FP32 (the plane test's margin of 2e-3 and the candidate rows' slack
+    // of one row are far above its rounding), the row radius rk, and the slab bounds: positions
+    // tau whose (clamped) cell lies in the tile, widened by a margin far above the rounding of the
+    // FP32 row intervals; the edge tiles also own the clamped cells beyond the grid.  Each
+    // interval is then trimmed to the exact one with the FP64 cell test.
+    __shared__ float tcl[3], blo[3], bhi[3], rkl;
+    if (tid == 0) {
+        qn = 0;
+        nimg = 0;
+        constexpr float MARGIN = 1e-2f, FAR = 1e30f;
+        for (int d = 0; d < 3; ++d) {
+            tcl[d] = tt[d] * T + 0.5f * T - 0.5f * L;
+            blo[d] = tt[d] == 0 ? -FAR : tt[d] * T - MARGIN;
+            bhi[d] = (tt[d] + 1) * T >= L ? FAR : (tt[d] + 1) * T + MARGIN;
+        }
+        rkl = (T * 0.8660254f + 1e-3f) / (float)a.s;
     }
+    const int S = (int)floorf(2.f * ((T * 0.8660254f + 1e-3f) / (float)a.s)) + 3;  // candidate rows per view
+    const int N2 = N * N;
     // the point (k1, k2) of the view with columns c lies in the tile: inside the disk and its
     // clamped cell in the tile per axis
     auto in_tile = [&](const double* c, int k1, int k2) {
@@ -273,13 +277,13 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
                 const int m = m0 + v * NTH + tid;
                 // the plane meets the tile's cube: distance of the centre at most the cube's
                 // half extent along the normal
-                const double dist = fabs(tc[0] * nv[v].x + tc[1] * nv[v].y + tc[2] * nv[v].z);
-                if (m < wk.z && dist <= 0.5 * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3) {
+                const float dist = fabsf(tcl[0] * nv[v].x + tcl[1] * nv[v].y + tcl[2] * nv[v].z);
+                if (m < wk.z && dist <= 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f) {
                     const double* c = a.c12 + 6 * (int64_t)m;
-                    const double u1 = (tc[0] * c[0] + tc[1] * c[1] + tc[2] * c[2]) / a.s;
+                    const float u1 = (tcl[0] * (float)c[0] + tcl[1] * (float)c[1] + tcl[2] * (float)c[2]) / (float)a.s;
                     const int sl = atomicAdd(&nimg, 1);
                     img_m[sl] = m;
-                    img_r[sl] = (int)ceil(u1 - rk) - 1;
+                    img_r[sl] = (int)ceilf(u1 - rkl) - 1;
                 }
             }
             m0 += PJ_VPT * NTH;
