@@ -5,7 +5,9 @@ staged-point record, and the lane roles of the one read that carries the FQ poin
 words and axis-0 weights to the readlane broadcasts.  Computed the way the kernel computes them
 and checked against the sizes of what they index, for every tile and window width the library
 launches: the kernel's tile 13 and the A*b tile 12, one component per launch (a one-plane tile),
-widths 4..8.  Runs on the CPU; no kernel is launched."""
+widths 4..8; and the FP32 plane test and candidate rows of both gridding kernels (spread and
+forward projector) against every point of random views at N = 256.  Runs on the CPU; no kernel
+is launched."""
 import itertools
 
 import numpy as np
@@ -202,3 +204,50 @@ def test_normal_box_culling_never_drops_a_view():
             assert live or not per_view.any()
             skipped += not live
     assert skipped > 0
+
+
+def _rotation(rng):
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    return q * np.sign(np.diag(r))[None, :]
+
+
+@pytest.mark.parametrize("T,kind", [(13, "spread"), (12, "spread"), (12, "project")])
+def test_plane_test_and_candidate_rows_cover_every_point(T, kind):
+    """Both gridding kernels keep a view for a tile when the FP32 plane test passes, and then
+    enumerate S candidate rows k1 from a start computed in FP32 from the tile's centre c:
+    u1 = <c, c1> / s, the spread from ceil(u1 - rk - 1e-3) with S = floor(2 rk + 2e-3) + 2, the
+    forward projector from ceil(u1 - rk) - 1 with S = floor(2 rk) + 3, rk = (0.866 T + 1e-3) / s.
+    Every half-disk point (|k| <= N/2) of a view at N = 256 (grid 2N, s = 2) must have its
+    clamped cell's tile pass the plane test and its k1 among that tile's candidate rows."""
+    rng = np.random.default_rng(17 + T)
+    N = 256
+    L, s = 2 * N, 2.0
+    f32 = np.float32
+    kk = np.arange(-N // 2, N // 2 + 1)
+    k1, k2 = np.meshgrid(kk, kk, indexing="ij")
+    disk = 4 * (k1 * k1 + k2 * k2) <= N * N
+    k1, k2 = k1[disk], k2[disk]
+    rk = (f32(T) * f32(0.8660254) + f32(1e-3)) / f32(s)
+    if kind == "spread":
+        S = int(np.floor(f32(2) * rk + f32(2e-3))) + 2
+    else:
+        S = int(np.floor(f32(2) * rk)) + 3
+    for _ in range(24):
+        R = _rotation(rng)
+        c1, c2 = R[:, 0], R[:, 1]
+        nv = np.cross(c1, c2).astype(f32)
+        tau = s * (k2[:, None] * c2[None, :] + k1[:, None] * c1[None, :]) + 0.5 * L
+        tt = np.clip(np.floor(tau), 0, L - 1).astype(np.int64) // T
+        tc = (tt.astype(f32) * f32(T) + f32(0.5 * T) - f32(0.5 * L)).astype(f32)
+        dist = np.abs(tc[:, 0] * nv[0] + tc[:, 1] * nv[1] + tc[:, 2] * nv[2])
+        lim = f32(0.5) * f32(T) * (np.abs(nv[0]) + np.abs(nv[1]) + np.abs(nv[2])) + f32(2e-3)
+        assert np.all(dist <= lim)
+        c1f = c1.astype(f32)
+        dot = tc[:, 0] * c1f[0] + tc[:, 1] * c1f[1] + tc[:, 2] * c1f[2]
+        if kind == "spread":
+            u1 = dot * (f32(1) / f32(s))
+            start = np.ceil(u1 - rk - f32(1e-3)).astype(np.int64)
+        else:
+            u1 = dot / f32(s)
+            start = np.ceil(u1 - rk).astype(np.int64) - 1
+        assert np.all(k1 >= start) and np.all(k1 < start + S)
