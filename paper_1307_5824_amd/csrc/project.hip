@@ -314,7 +314,9 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
                         if (fabsf(be) < 1e-6f) {
                             ok = ok && al >= blo[d] && al <= bhi[d];
                         } else {
-                            const float t1 = (blo[d] - al) / be, t2 = (bhi[d] - al) / be;
+                            // reciprocal to about 1 ulp: far inside the bounds' margin
+                            const float rb = __builtin_amdgcn_rcpf(be);
+                            const float t1 = (blo[d] - al) * rb, t2 = (bhi[d] - al) * rb;
                             lo = fmaxf(lo, fminf(t1, t2));
                             hi = fminf(hi, fmaxf(t1, t2));
                         }

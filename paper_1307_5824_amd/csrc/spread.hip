@@ -476,7 +476,9 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                             if (fabsf(be) < 1e-6f) {
                                 ok = ok && al >= bl && al <= bh;
                             } else {
-                                const float t1 = (bl - al) / be, t2 = (bh - al) / be;
+                                // reciprocal to about 1 ulp: far inside the bounds' margin
+                                const float rb = __builtin_amdgcn_rcpf(be);
+                                const float t1 = (bl - al) * rb, t2 = (bh - al) * rb;
                                 lo = fmaxf(lo, fminf(t1, t2));
                                 hi = fminf(hi, fmaxf(t1, t2));
                             }
