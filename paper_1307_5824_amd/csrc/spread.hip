@@ -130,6 +130,14 @@ __device__ __forceinline__ double tau_of(double s, int k1, int k2, double cd, do
     return fma(s, fma((double)k2, c3d, (double)k1 * cd), halfL);
 }
 
+// Points staged per batch: the most, in whole rounds (a round gives every wavefront FQ points),
+// that keep one staging item (point, axis) per thread and the workgroup's LDS within its budget.
+constexpr int sp_batch(int nth, int fixed_bytes, int per_point, int budget, int round) {
+    int pb = nth / 3 / round * round;
+    while (pb > round && fixed_bytes + pb * per_point > budget) pb -= round;
+    return pb;
+}
+
 // One tile plane of 64-bit integer cells.  Complex data (A*b) is spread one component per
 // launch (a.comp), so that its tile is as small as the kernel's: two workgroups per CU up to
 // W = 7, one for W = 8.
@@ -143,11 +151,18 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     constexpr int RP = row_pitch(PT, W, G);            // LDS pitch of a tile row, in cells (conflict-free)
     constexpr int GROUPS = row_groups(RP, W, G);       // lane group of every footprint row
     constexpr int PP = PT * RP;                        // LDS pitch of a tile plane
-    // staged point: the W window weights of axes 0, 1, 2 at 0, 8, 16 (axis 0 times the point's
+    // staged point: the W window weights of axes 0, 1, 2 at 0, W, 2W (axis 0 times the point's
     // value in fixed-point units); stride in floats
-    constexpr int PSTR = 24;
-    static_assert(W <= 8, "window width");
-    constexpr int SP_PB = 96;                          // points staged per batch
+    constexpr int PSTR = 3 * W;
+    static_assert(W >= 3 && W <= 8, "window width");
+    constexpr int FQ = 4;  // points a wavefront accumulates at a time (see the accumulation)
+    // LDS besides the staged points: the tile, the view slots (and for complex data their views,
+    // groups and the disk's row starts), the queue, and 512 bytes for the counters, the tile
+    // constants, the lane map, the flush's partial sums and alignment.  The batch is as large as
+    // the rest allows: two workgroups share a CU up to W = 7 (80 KB each), one at W = 8.
+    constexpr int LDS_FIXED = PT * PP * 8 + NTH * 4 * (CPLX ? 3 : 1) + (CPLX ? 264 * 4 : 0) + SP_QCAP * 4 + 512;
+    constexpr int SP_PB = sp_batch(NTH, LDS_FIXED, PSTR * 4 + 4, W >= 8 ? 160 * 1024 : 80 * 1024, FQ * SP_WAVES);
+    static_assert(SP_PB >= FQ * SP_WAVES && 3 * SP_PB <= NTH, "staging batch");
     constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
     __shared__ __align__(16) unsigned long long tile64[PT * PP];
     __shared__ __align__(16) float pt_w[SP_PB * PSTR];
@@ -305,8 +320,8 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             for (int it = 0; it < NIT; ++it) {
                 const int d = dd[it];
                 if (d < 0) continue;
-                // weights of axis d at 8 d, window starts in the bytes of pt_lo
-                float* q = pt_w + pp[it] * PSTR + 8 * d;
+                // weights of axis d at W d, window starts in the bytes of pt_lo
+                float* q = pt_w + pp[it] * PSTR + W * d;
 #pragma unroll
                 for (int j = 0; j < W; ++j) q[j] = d == 0 ? scale * ph[it][j] : ph[it][j];
                 reinterpret_cast<unsigned char*>(pt_lo)[4 * pp[it] + d] = (unsigned char)lod[it];
@@ -326,7 +341,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             const int lm = lmap[lane];
             const int j2 = lm & 15, j3 = (lm >> 4) & 15;
             const bool act = (lm >> 8) != 0;
-            constexpr int FQ = 4;  // the register list of the asm statement below names 4
+            static_assert(FQ == 4, "the register list of the asm statement below names 4");
             static_assert(FQ * 8 + FQ <= 64, "one read for the uniform data");
             const int wvu = __builtin_amdgcn_readfirstlane(wv);
             // lane roles of the uniform read: 8 q + k -> weight k of point q (k < 8); 32 + q -> window
@@ -343,8 +358,8 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                 float w2[FQ], w3[FQ];
 #pragma unroll
                 for (int q = 0; q < FQ; ++q) {
-                    w2[q] = pt_w[pq[q] * PSTR + 8 + j2];
-                    w3[q] = pt_w[pq[q] * PSTR + 16 + j3];
+                    w2[q] = pt_w[pq[q] * PSTR + W + j2];
+                    w3[q] = pt_w[pq[q] * PSTR + 2 * W + j3];
                 }
                 float u = *src;
                 // all the reads are issued here, before any register of theirs is used

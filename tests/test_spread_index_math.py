@@ -13,7 +13,7 @@ import itertools
 import numpy as np
 import pytest
 
-SP_PB, PSTR, FQ, NTH = 96, 24, 4, 512
+SP_QCAP, FQ, NTH = 1024, 4, 512
 LDS_CU = 160 * 1024
 
 
@@ -109,17 +109,37 @@ def test_footprint_lanes_and_tile_indices(T, W, cplx):
     assert len(li) == PT ** 3 and max(li) < PT * PP
 
 
-@pytest.mark.parametrize("T,W,cplx", CASES)
-def test_staged_record_and_uniform_read(T, W, cplx):
+def staging_batch(T, W, cplx):
+    """The kernel's batch size and record stride: the most points, in whole rounds of FQ per
+    wavefront, with one staging item (point, axis) per thread and the workgroup's LDS (the rest
+    of it counted as the kernel counts it) within 80 KB up to W = 7, 160 KB at W = 8."""
     PT = T + W
     RP = row_pitch(PT, W, 4)
-    # staging: item (point p, axis d) writes weights at p PSTR + 8 d + j and byte d of pt_lo[p]
+    fixed = PT * PT * RP * 8 + NTH * 4 * (3 if cplx else 1) + (264 * 4 if cplx else 0) + SP_QCAP * 4 + 512
+    pstr = 3 * W
+    per = pstr * 4 + 4
+    budget = (160 if W >= 8 else 80) * 1024
+    rnd = FQ * NTH // 64
+    pb = NTH // 3 // rnd * rnd
+    while pb > rnd and fixed + pb * per > budget:
+        pb -= rnd
+    return pb, pstr, fixed + pb * per
+
+
+@pytest.mark.parametrize("T,W,cplx", CASES)
+def test_staged_record_and_uniform_read(T, W, cplx):
+    SP_PB, PSTR, lds = staging_batch(T, W, cplx)
+    assert SP_PB % (FQ * NTH // 64) == 0 and 3 * SP_PB <= NTH
+    # staging: item (point p, axis d) writes weights at p PSTR + W d + j and byte d of pt_lo[p]
     for p, d, j in itertools.product(range(SP_PB), range(3), range(W)):
-        assert p * PSTR + 8 * d + j < SP_PB * PSTR and 8 * d + j < PSTR
+        assert p * PSTR + W * d + j < SP_PB * PSTR and W * d + j < PSTR
         assert 4 * p + d < 4 * SP_PB
+    # the accumulation's own reads: axis-1 and axis-2 weights of its footprint cell
+    for p, j in itertools.product((0, SP_PB - 1), range(W)):
+        assert p * PSTR + W + j < SP_PB * PSTR and p * PSTR + 2 * W + j < SP_PB * PSTR
     # the uniform read: roles of the lanes and the lanes the readlanes take
     assert FQ * 8 + FQ <= 64
-    for nb in (1, 2, 7, 8, 9, 33, 95, 96):
+    for nb in sorted({1, 2, 7, 8, 9, 33, 95, 96, SP_PB - 1, SP_PB}):
         for wv in range(NTH // 64):
             for p0 in range(wv, nb, FQ * (NTH // 64)):
                 pq = [min(p0 + q * (NTH // 64), nb - 1) for q in range(FQ)]
@@ -146,12 +166,13 @@ def test_staged_record_and_uniform_read(T, W, cplx):
     for N in (8, 16, 32, 64, 128, 256):
         assert max(k1 + N // 2 for k1 in range(N // 2 + 1)) <= N < 264
     # LDS of one workgroup: the 64-bit tile, the staged points, the queue, the view slots (and the
-    # row starts for complex data); two workgroups share a CU up to width 7
-    lds = PT * PT * RP * 8 + SP_PB * PSTR * 4 + SP_PB * 4 + 1024 * 4 + NTH * 4
-    if cplx:
-        lds += 264 * 4
+    # slots' views and groups and the row starts for complex data); two workgroups share a CU up
+    # to width 7.  At the widths the library runs by default (7) the batch holds 128 points for
+    # the kernel's tile and 160 for the A*b tile.
     wgs = 1 if W >= 8 else 2
     assert wgs * lds <= LDS_CU
+    if W == 7:
+        assert SP_PB == (160 if cplx else 128)
 
 
 def test_fixed_point_sums_are_exact_and_order_free():
