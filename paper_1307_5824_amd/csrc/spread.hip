@@ -160,7 +160,9 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     // groups and the disk's row starts), the queue, and 512 bytes for the counters, the tile
     // constants, the lane map, the flush's partial sums and alignment.  The batch is as large as
     // the rest allows: two workgroups share a CU up to W = 7 (80 KB each), one at W = 8.
-    constexpr int LDS_FIXED = PT * PP * 8 + NTH * 4 * (CPLX ? 3 : 1) + (CPLX ? 264 * 4 : 0) + SP_QCAP * 4 + 512;
+    // the queue: the A*b tile leaves room for 256 more entries (fewer stops of the enumeration)
+    constexpr int QCAP = CPLX ? SP_QCAP + 256 : SP_QCAP;
+    constexpr int LDS_FIXED = PT * PP * 8 + NTH * 4 * (CPLX ? 3 : 1) + (CPLX ? 264 * 4 : 0) + QCAP * 4 + 512;
     constexpr int SP_PB = sp_batch(NTH, LDS_FIXED, PSTR * 4 + 4, W >= 8 ? 160 * 1024 : 80 * 1024, FQ * SP_WAVES);
     static_assert(SP_PB >= FQ * SP_WAVES && 3 * SP_PB <= NTH, "staging batch");
     constexpr int NIT = (3 * SP_PB + NTH - 1) / NTH;   // staging items (point, axis) per thread
@@ -171,7 +173,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     __shared__ int img_o[CPLX ? SP_THREADS : 1];  // complex data: the slot's view in the caller's order
     __shared__ int img_g[CPLX ? SP_THREADS : 1];  // complex data: the slot's CTF group
     __shared__ int rs_l[CPLX ? 264 : 1];              // row starts of the disk order (N <= 256)
-    __shared__ int queue[SP_QCAP];
+    __shared__ int queue[QCAP];
     __shared__ int nimg, qn, qfail, any;
     __shared__ float geo[12];  // the tile's constants (see below)
     __shared__ unsigned short lmap[64];  // footprint cell of each lane (see below)
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     const double halfL = 0.5 * L;
 
     for (int i = tid; i < PT * PP; i += SP_THREADS) tile64[i] = 0ull;
-    if (tid == 0) { any = 0; nimg = 0; qn = 0; qfail = SP_QCAP; }
+    if (tid == 0) { any = 0; nimg = 0; qn = 0; qfail = QCAP; }
     if constexpr (CPLX)
         for (int i = tid; i <= a.N; i += SP_THREADS) rs_l[i] = a.rowstart[i];
 
@@ -513,7 +515,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                 while (true) {
                     if (pend) {
                         const int pos = atomicAdd(&qn, cnt);
-                        if (pos + cnt <= SP_QCAP) {
+                        if (pos + cnt <= QCAP) {
                             for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
                             pend = false;
                         } else {
@@ -529,7 +531,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     const int keep = tid < rest ? queue[nfull + tid] : 0;
                     __syncthreads();
                     if (tid < rest) queue[tid] = keep;
-                    if (tid == 0) { qn = rest; qfail = SP_QCAP; }
+                    if (tid == 0) { qn = rest; qfail = QCAP; }
                     __syncthreads();
                 }
             }
@@ -538,7 +540,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             // the slots ran out: process everything queued, then reuse them
             process(qn);
             __syncthreads();
-            if (tid == 0) { qn = 0; qfail = SP_QCAP; nimg = 0; }
+            if (tid == 0) { qn = 0; qfail = QCAP; nimg = 0; }
             __syncthreads();
             base = 0;
         }

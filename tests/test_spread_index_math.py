@@ -115,7 +115,8 @@ def staging_batch(T, W, cplx):
     of it counted as the kernel counts it) within 80 KB up to W = 7, 160 KB at W = 8."""
     PT = T + W
     RP = row_pitch(PT, W, 4)
-    fixed = PT * PT * RP * 8 + NTH * 4 * (3 if cplx else 1) + (264 * 4 if cplx else 0) + SP_QCAP * 4 + 512
+    qcap = SP_QCAP + 256 if cplx else SP_QCAP  # the queue: 1280 entries for A*b, 1024 for Ker
+    fixed = PT * PT * RP * 8 + NTH * 4 * (3 if cplx else 1) + (264 * 4 if cplx else 0) + qcap * 4 + 512
     pstr = 3 * W
     per = pstr * 4 + 4
     budget = (160 if W >= 8 else 80) * 1024
