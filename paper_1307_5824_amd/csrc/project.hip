@@ -33,9 +33,13 @@ namespace {
 struct ProjArgs {
     int N, M, L, nt, P, Q, QP;
     double s;
+    // per-view arrays in the order of the views' normals (blocks of 512 views with the box of
+    // their normals in vbox), and the map from that order to the caller's
     const double* c12;
     const float* nrm;
     const int32_t* group;
+    const int* vorder;
+    const float4* vbox;
     const float* table;
     const float* poly;
     const int4* work;
@@ -183,8 +187,9 @@ __device__ __forceinline__ void gather_point(const ProjArgs& a, const float2* __
     // h exp(-i theta) (ar + i ai), and its conjugate at -k
     const float2 v = make_float2(h * (ar * cs + ai * sn), h * (ai * cs - ar * sn));
     const int idx = a.rowstart[k1 + N / 2] + k2;
-    a.b[(int64_t)m * a.P + idx] = v;
-    a.b[(int64_t)m * a.P + (a.P - 1 - idx)] = make_float2(v.x, -v.y);
+    const int64_t mo = a.vorder[m];  // the caller's view index
+    a.b[mo * a.P + idx] = v;
+    a.b[mo * a.P + (a.P - 1 - idx)] = make_float2(v.x, -v.y);
 }
 
 // Four waves per SIMD (two 512-thread workgroups per CU) up to W = 7; the W = 8 gather needs
@@ -265,12 +270,26 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
         //    round overlap
         int ni = 0;
         do {
+            // a block of NTH views whose box of normals n gives no |n . c| within the bound below
+            // for the tile's centre c holds no view that meets the tile: its normals are not loaded
             float4 nv[PJ_VPT];
+            unsigned livev = 0u;
 #pragma unroll
             for (int v = 0; v < PJ_VPT; ++v) {
-                const int m = m0 + v * NTH + tid;
-                nv[v] = m < wk.z ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m)
-                                 : make_float4(0.f, 0.f, 0.f, 1e30f);
+                const int mb = m0 + v * NTH, m = mb + tid;
+                bool live = mb < wk.z;
+                if (live) {
+                    const float4 lo = a.vbox[2 * (mb / NTH)], hi = a.vbox[2 * (mb / NTH) + 1];
+                    const float p0 = tcl[0] * lo.x, q0 = tcl[0] * hi.x, p1 = tcl[1] * lo.y, q1 = tcl[1] * hi.y;
+                    const float p2 = tcl[2] * lo.z, q2 = tcl[2] * hi.z;
+                    const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
+                    const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
+                    const float lim = 0.5f * T * lo.w + 3e-3f;
+                    live = dmin <= lim && dmax >= -lim;
+                }
+                live = live && m < wk.z;
+                nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                livev |= (unsigned)live << v;
             }
 #pragma unroll
             for (int v = 0; v < PJ_VPT; ++v) {
@@ -278,7 +297,7 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
                 // the plane meets the tile's cube: distance of the centre at most the cube's
                 // half extent along the normal
                 const float dist = fabsf(tcl[0] * nv[v].x + tcl[1] * nv[v].y + tcl[2] * nv[v].z);
-                if (m < wk.z && dist <= 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f) {
+                if (((livev >> v) & 1u) && dist <= 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f) {
                     const double* c = a.c12 + 6 * (int64_t)m;
                     const float u1 = (tcl[0] * (float)c[0] + tcl[1] * (float)c[1] + tcl[2] * (float)c[2]) / (float)a.s;
                     const int sl = atomicAdd(&nimg, 1);
@@ -379,9 +398,12 @@ hipError_t forward_project(firm_plan p, const float* V, float2* b) {
     ProjArgs a;
     a.N = N; a.M = p->M; a.L = L; a.nt = (L + PJ_TILE - 1) / PJ_TILE; a.P = p->P; a.Q = p->Q; a.QP = p->QP;
     a.s = 2.0;
-    a.c12 = p->c12; a.nrm = p->nrm; a.group = p->group; a.table = p->table; a.poly = p->kb_poly;
+    // the views in the order of their normals (blocks of SP_VBLK views, one per round and thread)
+    static_assert(PJ_THREADS == SP_VBLK, "a block of views per round and thread");
+    a.c12 = p->c12s; a.nrm = p->nrms; a.group = p->groups; a.table = p->table; a.poly = p->kb_poly;
+    a.vorder = p->vorder; a.vbox = p->vbox;
     a.work = reinterpret_cast<const int4*>(p->tiles_atb);
-    a.X = X; a.shifts = p->shifts; a.rowstart = p->rowstart; a.b = b;
+    a.X = X; a.shifts = p->shiftss; a.rowstart = p->rowstart; a.b = b;
     const dim3 grid(p->ntiles_atb), blk(PJ_THREADS);
     switch (p->kbw) {
         case 4: hipLaunchKernelGGL((k_project<PJ_TILE, 4, PJ_THREADS>), grid, blk, 0, st, a); break;

@@ -187,13 +187,15 @@ def test_fixed_point_sums_are_exact_and_order_free():
     assert (2 ** 31) * (2 ** 32) <= 2 ** 63
 
 
-def test_normal_box_culling_never_drops_a_view():
-    """The spread skips a block of 512 views when the box of their (hemisphere-folded) normals
-    gives no |n . c| within 0.5 T max|n|_1 + 3e-3 of the tile's centre c.  Emulated with the
-    kernel's expressions (FP32 normals, FP64 products): whenever some view of a block passes the
-    per-view plane test, the block test passes too; and the test does prune."""
-    rng = np.random.default_rng(11)
-    M, T, L = 4096, 13, 1024
+@pytest.mark.parametrize("T,L", [(13, 1024), (12, 512)])
+def test_normal_box_culling_never_drops_a_view(T, L):
+    """The spread (and the forward projector, tile 12 on the 2N grid) skips a block of 512 views
+    when the box of their (hemisphere-folded) normals gives no |n . c| within 0.5 T max|n|_1 +
+    3e-3 of the tile's centre c.  Emulated with the kernel's expressions (FP32 normals, FP64
+    products): whenever some view of a block passes the per-view plane test, the block test
+    passes too; and the test does prune."""
+    rng = np.random.default_rng(11 + T)
+    M = 4096
     # a concentrated cluster and uniform directions, as the workloads' view distributions
     n = rng.standard_normal((M, 3))
     n[: M // 2] = n[: M // 2] * 0.2 + np.array([0.3, 0.5, 0.8])
