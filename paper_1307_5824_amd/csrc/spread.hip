@@ -160,8 +160,9 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     // groups and the disk's row starts), the queue, and 512 bytes for the counters, the tile
     // constants, the lane map, the flush's partial sums and alignment.  The batch is as large as
     // the rest allows: two workgroups share a CU up to W = 7 (80 KB each), one at W = 8.
-    // the queue: the A*b tile leaves room for 256 more entries (fewer stops of the enumeration)
-    constexpr int QCAP = CPLX ? SP_QCAP + 256 : SP_QCAP;
+    // the queue: the A*b tile leaves room for 256 more entries (fewer stops of the enumeration);
+    // the kernel's tile 32 fewer, for the block mask of the culling
+    constexpr int QCAP = CPLX ? SP_QCAP + 256 : SP_QCAP - 32;
     constexpr int LDS_FIXED = PT * PP * 8 + NTH * 4 * (CPLX ? 3 : 1) + (CPLX ? 264 * 4 : 0) + QCAP * 4 + 512;
     constexpr int SP_PB = sp_batch(NTH, LDS_FIXED, PSTR * 4 + 4, W >= 8 ? 160 * 1024 : 80 * 1024, FQ * SP_WAVES);
     static_assert(SP_PB >= FQ * SP_WAVES && 3 * SP_PB <= NTH, "staging batch");
@@ -408,141 +409,171 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
     // been processed.  A chunk is VPT views per thread (the fixed cost of a chunk, barriers and
     // the latency of the view data, is paid once for all of them).
     constexpr int VPT = 8;
+    __shared__ unsigned bmask[SP_THREADS / 32];  // the live blocks of the current group of blocks
+    // a chunk's live blocks (in the group), their count, and the next block of the group to look at
+    __shared__ int lblk[VPT + 2];
     int base = 0;  // first slot whose rows are not yet enumerated
-    for (int mb = wk.y; mb < wk.z; mb += VPT * SP_THREADS) {
-        unsigned pendv = 0u;  // this thread's views of the chunk that meet the tile, not yet in a slot
-        {
-            // a block of SP_VBLK views whose box of normals n gives no |n . c| within the bound
-            // below for the tile's centre c holds no view that meets the tile: skipped whole
-            float4 nv[VPT];
-            unsigned livev = 0u;
-#pragma unroll
-            for (int v = 0; v < VPT; ++v) {
-                const int m0 = mb + v * SP_THREADS, m = m0 + tid;
-                bool live = m0 < wk.z;
-                const float tc0 = geo[G_TC0], tc1 = geo[G_TC1], tc2 = geo[G_TC2];
-                if (live) {
-                    const float4 lo = a.vbox[2 * (m0 / SP_THREADS)], hi = a.vbox[2 * (m0 / SP_THREADS) + 1];
-                    const float p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
-                    const float p2 = tc2 * lo.z, q2 = tc2 * hi.z;
-                    const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
-                    const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
-                    const float lim = 0.5f * T * lo.w + 3e-3f;
-                    live = dmin <= lim && dmax >= -lim;
-                }
-                live = live && m < wk.z;
-                nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
-                livev |= (unsigned)live << v;
-            }
-#pragma unroll
-            for (int v = 0; v < VPT; ++v) {
-                // the plane meets the tile's cube: distance of the centre at most the cube's half
-                // extent along the normal
-                if (((livev >> v) & 1u) && fabsf(geo[G_TC0] * nv[v].x + geo[G_TC1] * nv[v].y + geo[G_TC2] * nv[v].z) <=
-                                                0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f)
-                    pendv |= 1u << v;
-            }
+    // blocks of SP_THREADS views (the work range starts on a block)
+    const int blk0 = wk.y / SP_THREADS, blk1 = (wk.z + SP_THREADS - 1) / SP_THREADS;
+    for (int gb = blk0; gb < blk1; gb += SP_THREADS) {
+        // block tests, one block per thread, up to SP_THREADS blocks at a time: a block whose box
+        // of normals n gives no |n . c| within the bound below for the tile's centre c holds no
+        // view that meets the tile.  The chunks below visit the live blocks only.
+        if (tid < SP_THREADS / 32) bmask[tid] = 0u;
+        __syncthreads();
+        if (gb + tid < blk1) {
+            const float tc0 = geo[G_TC0], tc1 = geo[G_TC1], tc2 = geo[G_TC2];
+            const float4 lo = a.vbox[2 * (gb + tid)], hi = a.vbox[2 * (gb + tid) + 1];
+            const float p0 = tc0 * lo.x, q0 = tc0 * hi.x, p1 = tc1 * lo.y, q1 = tc1 * hi.y;
+            const float p2 = tc2 * lo.z, q2 = tc2 * hi.z;
+            const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
+            const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
+            const float lim = 0.5f * T * lo.w + 3e-3f;
+            if (dmin <= lim && dmax >= -lim) atomicOr(&bmask[tid >> 5], 1u << (tid & 31));
         }
+        if (tid == 0) lblk[VPT + 1] = 0;
         while (true) {
-            // slots for the surviving views while free ones last
-            for (int v = 0; v < VPT; ++v) {
-                if (!((pendv >> v) & 1u)) continue;
-                const int sl = atomicAdd(&nimg, 1);
-                if (sl < SP_THREADS) {
-                    img_m[sl] = mb + v * SP_THREADS + tid;
-                    pendv &= ~(1u << v);
+            __syncthreads();  // the mask is complete, and the last chunk's blocks are no longer read
+            if (tid == 0) {
+                int n = 0, cur = lblk[VPT + 1];
+                while (n < VPT && cur < SP_THREADS) {
+                    const unsigned w = bmask[cur >> 5] & (~0u << (cur & 31));
+                    if (w == 0u) {
+                        cur = (cur | 31) + 1;
+                        continue;
+                    }
+                    const int b = (cur & ~31) + __builtin_ctz(w);
+                    lblk[n++] = b;
+                    cur = b + 1;
                 }
+                lblk[VPT] = n;
+                lblk[VPT + 1] = cur;
             }
             __syncthreads();
-            const int top = min(nimg, SP_THREADS);
-            if constexpr (CPLX) {
-                // the new slots' CTF groups and views in the caller's order, read once per slot
-                // here (in parallel) rather than by the staging of every point
-                if (tid >= base && tid < top) {
-                    const int m = img_m[tid];
-                    img_o[tid] = a.vorder[m];
-                    img_g[tid] = a.group[m];
+            const int nl = lblk[VPT];
+            if (nl == 0) break;
+            // a chunk: the views of up to VPT live blocks, one per thread and block
+            unsigned pendv = 0u;  // this thread's views of the chunk that meet the tile, not yet in a slot
+            {
+                float4 nv[VPT];
+                unsigned livev = 0u;
+#pragma unroll
+                for (int v = 0; v < VPT; ++v) {
+                    const int m = v < nl ? (gb + lblk[v]) * SP_THREADS + tid : wk.z;
+                    const bool live = m < wk.z;
+                    nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    livev |= (unsigned)live << v;
+                }
+    #pragma unroll
+                for (int v = 0; v < VPT; ++v) {
+                    // the plane meets the tile's cube: distance of the centre at most the cube's half
+                    // extent along the normal
+                    if (((livev >> v) & 1u) && fabsf(geo[G_TC0] * nv[v].x + geo[G_TC1] * nv[v].y + geo[G_TC2] * nv[v].z) <=
+                                                    0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f)
+                        pendv |= 1u << v;
+                }
+            }
+            while (true) {
+                // slots for the surviving views while free ones last
+                for (int v = 0; v < VPT; ++v) {
+                    if (!((pendv >> v) & 1u)) continue;
+                    const int sl = atomicAdd(&nimg, 1);
+                    if (sl < SP_THREADS) {
+                        img_m[sl] = (gb + lblk[v]) * SP_THREADS + tid;
+                        pendv &= ~(1u << v);
+                    }
                 }
                 __syncthreads();
-            }
-            // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
-            // plus the disk and half-disk bounds), trimmed to the exact test at both ends (the cell
-            // along a row is monotone in k2, so the points that pass form an interval), then the
-            // points are queued.  A reservation that does not fit waits for the queue's whole
-            // batches to be processed; the reservations that fitted form the prefix up to the
-            // first that did not.
-            const int units = (top - base) * S;
-            for (int ub = 0; ub < units; ub += SP_THREADS) {
-                const int u = ub + tid;
-                int sl = 0, k1 = 0, klo = 0, cnt = 0;
-                if (u < units) {
-                    const int v = u / S;
-                    sl = base + v;
-                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const float u1 = (geo[G_TC0] * (float)c[0] + geo[G_TC1] * (float)c[1] + geo[G_TC2] * (float)c[2]) *
-                                     geo[G_INVS];
-                    k1 = (int)ceilf(u1 - geo[G_RK] - 1e-3f) + (u - v * S);
-                    if (k1 >= 0 && 4 * k1 * k1 <= N2) {
-                        const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
-                        float lo = (float)-kd, hi = (float)kd;
-                        bool ok = true;
-#pragma unroll
-                        for (int d = 0; d < 3; ++d) {
-                            const float bl = geo[G_BLO0 + d], bh = geo[G_BHI0 + d];
-                            const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
-                            if (fabsf(be) < 1e-6f) {
-                                ok = ok && al >= bl && al <= bh;
-                            } else {
-                                // reciprocal to about 1 ulp: far inside the bounds' margin
-                                const float rb = __builtin_amdgcn_rcpf(be);
-                                const float t1 = (bl - al) * rb, t2 = (bh - al) * rb;
-                                lo = fmaxf(lo, fminf(t1, t2));
-                                hi = fminf(hi, fmaxf(t1, t2));
+                const int top = min(nimg, SP_THREADS);
+                if constexpr (CPLX) {
+                    // the new slots' CTF groups and views in the caller's order, read once per slot
+                    // here (in parallel) rather than by the staging of every point
+                    if (tid >= base && tid < top) {
+                        const int m = img_m[tid];
+                        img_o[tid] = a.vorder[m];
+                        img_g[tid] = a.group[m];
+                    }
+                    __syncthreads();
+                }
+                // one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three slabs,
+                // plus the disk and half-disk bounds), trimmed to the exact test at both ends (the cell
+                // along a row is monotone in k2, so the points that pass form an interval), then the
+                // points are queued.  A reservation that does not fit waits for the queue's whole
+                // batches to be processed; the reservations that fitted form the prefix up to the
+                // first that did not.
+                const int units = (top - base) * S;
+                for (int ub = 0; ub < units; ub += SP_THREADS) {
+                    const int u = ub + tid;
+                    int sl = 0, k1 = 0, klo = 0, cnt = 0;
+                    if (u < units) {
+                        const int v = u / S;
+                        sl = base + v;
+                        const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                        const float u1 = (geo[G_TC0] * (float)c[0] + geo[G_TC1] * (float)c[1] + geo[G_TC2] * (float)c[2]) *
+                                         geo[G_INVS];
+                        k1 = (int)ceilf(u1 - geo[G_RK] - 1e-3f) + (u - v * S);
+                        if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+                            const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                            float lo = (float)-kd, hi = (float)kd;
+                            bool ok = true;
+    #pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                const float bl = geo[G_BLO0 + d], bh = geo[G_BHI0 + d];
+                                const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
+                                if (fabsf(be) < 1e-6f) {
+                                    ok = ok && al >= bl && al <= bh;
+                                } else {
+                                    // reciprocal to about 1 ulp: far inside the bounds' margin
+                                    const float rb = __builtin_amdgcn_rcpf(be);
+                                    const float t1 = (bl - al) * rb, t2 = (bh - al) * rb;
+                                    lo = fmaxf(lo, fminf(t1, t2));
+                                    hi = fminf(hi, fmaxf(t1, t2));
+                                }
+                            }
+                            klo = (int)ceilf(lo);
+                            if (k1 == 0) klo = max(klo, 1);
+                            int khi = (int)floorf(hi);
+                            if (ok) {
+                                while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
+                                while (khi >= klo && !in_tile(c, k1, khi)) --khi;
+                                // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                                cnt = min(khi - klo + 1, 32);
                             }
                         }
-                        klo = (int)ceilf(lo);
-                        if (k1 == 0) klo = max(klo, 1);
-                        int khi = (int)floorf(hi);
-                        if (ok) {
-                            while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
-                            while (khi >= klo && !in_tile(c, k1, khi)) --khi;
-                            // a row crosses a tile in at most T sqrt(3) / s + 1 points
-                            cnt = min(khi - klo + 1, 32);
+                    }
+                    bool pend = cnt > 0;
+                    while (true) {
+                        if (pend) {
+                            const int pos = atomicAdd(&qn, cnt);
+                            if (pos + cnt <= QCAP) {
+                                for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
+                                pend = false;
+                            } else {
+                                atomicMin(&qfail, pos);
+                            }
                         }
+                        if (!__syncthreads_or(pend)) break;
+                        // the queue is full: process its whole batches and keep the rest at its front
+                        const int nv = min(qfail, qn);
+                        const int nfull = nv / SP_PB * SP_PB;
+                        process(nfull);
+                        const int rest = nv - nfull;
+                        const int keep = tid < rest ? queue[nfull + tid] : 0;
+                        __syncthreads();
+                        if (tid < rest) queue[tid] = keep;
+                        if (tid == 0) { qn = rest; qfail = QCAP; }
+                        __syncthreads();
                     }
                 }
-                bool pend = cnt > 0;
-                while (true) {
-                    if (pend) {
-                        const int pos = atomicAdd(&qn, cnt);
-                        if (pos + cnt <= QCAP) {
-                            for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 18) | ((k1 + 256) << 9) | (klo + j + 256);
-                            pend = false;
-                        } else {
-                            atomicMin(&qfail, pos);
-                        }
-                    }
-                    if (!__syncthreads_or(pend)) break;
-                    // the queue is full: process its whole batches and keep the rest at its front
-                    const int nv = min(qfail, qn);
-                    const int nfull = nv / SP_PB * SP_PB;
-                    process(nfull);
-                    const int rest = nv - nfull;
-                    const int keep = tid < rest ? queue[nfull + tid] : 0;
-                    __syncthreads();
-                    if (tid < rest) queue[tid] = keep;
-                    if (tid == 0) { qn = rest; qfail = QCAP; }
-                    __syncthreads();
-                }
+                base = top;
+                if (!__syncthreads_or(pendv != 0u)) break;
+                // the slots ran out: process everything queued, then reuse them
+                process(qn);
+                __syncthreads();
+                if (tid == 0) { qn = 0; qfail = QCAP; nimg = 0; }
+                __syncthreads();
+                base = 0;
             }
-            base = top;
-            if (!__syncthreads_or(pendv != 0u)) break;
-            // the slots ran out: process everything queued, then reuse them
-            process(qn);
-            __syncthreads();
-            if (tid == 0) { qn = 0; qfail = QCAP; nimg = 0; }
-            __syncthreads();
-            base = 0;
         }
     }
     __syncthreads();

@@ -115,7 +115,7 @@ def staging_batch(T, W, cplx):
     of it counted as the kernel counts it) within 80 KB up to W = 7, 160 KB at W = 8."""
     PT = T + W
     RP = row_pitch(PT, W, 4)
-    qcap = SP_QCAP + 256 if cplx else SP_QCAP  # the queue: 1280 entries for A*b, 1024 for Ker
+    qcap = SP_QCAP + 256 if cplx else SP_QCAP - 32  # the queue: 1280 entries for A*b, 992 for Ker
     fixed = PT * PT * RP * 8 + NTH * 4 * (3 if cplx else 1) + (264 * 4 if cplx else 0) + qcap * 4 + 512
     pstr = 3 * W
     per = pstr * 4 + 4
@@ -275,3 +275,34 @@ def test_plane_test_and_candidate_rows_cover_every_point(T, kind):
             u1 = dot / f32(s)
             start = np.ceil(u1 - rk).astype(np.int64) - 1
         assert np.all(k1 >= start) and np.all(k1 < start + S)
+
+
+def test_live_block_chunks_visit_every_live_block_once():
+    """The culling tests up to 512 blocks of views at a time into a bit mask, then one thread
+    hands out the live blocks in chunks of VPT = 8 (scanning 32-bit words from a cursor, skipping
+    empty words).  Emulated as the kernel does it: the chunks list every set bit once, in order."""
+    rng = np.random.default_rng(23)
+    VPT = 8
+    for density in (0.0, 0.01, 0.2, 0.9, 1.0):
+        for nblk in (1, 31, 32, 33, 300, 512):
+            bits = (rng.random(nblk) < density)
+            mask = [0] * 16
+            for b in np.flatnonzero(bits).tolist():
+                mask[b >> 5] |= 1 << (b & 31)
+            seen, cur = [], 0
+            while True:
+                n, chunk = 0, []
+                while n < VPT and cur < 512:
+                    w = mask[cur >> 5] & ((0xFFFFFFFF << (cur & 31)) & 0xFFFFFFFF)
+                    if w == 0:
+                        cur = (cur | 31) + 1
+                        continue
+                    b = (cur & ~31) + ((w & -w).bit_length() - 1)
+                    chunk.append(b)
+                    n += 1
+                    cur = b + 1
+                if not chunk:
+                    break
+                assert len(chunk) <= VPT
+                seen += chunk
+            assert seen == np.flatnonzero(bits).tolist()
