@@ -262,118 +262,149 @@ __global__ void __launch_bounds__(NTH, (W <= 7 ? 4 : 2)) k_project(ProjArgs a) {
         }
     };
 
-    int m0 = wk.y;
-    while (m0 < wk.z) {  // m0 is uniform
-        __syncthreads();  // the counters are reset, the tile is in place
-        // 1. views whose plane meets the tile, at least NTH of them
-        //    (or all that remain), PJ_VPT views per thread per round so that the loads of a
-        //    round overlap
-        int ni = 0;
-        do {
-            // a block of NTH views whose box of normals n gives no |n . c| within the bound below
-            // for the tile's centre c holds no view that meets the tile: its normals are not loaded
-            float4 nv[PJ_VPT];
-            unsigned livev = 0u;
-#pragma unroll
-            for (int v = 0; v < PJ_VPT; ++v) {
-                const int mb = m0 + v * NTH, m = mb + tid;
-                bool live = mb < wk.z;
-                if (live) {
-                    const float4 lo = a.vbox[2 * (mb / NTH)], hi = a.vbox[2 * (mb / NTH) + 1];
-                    const float p0 = tcl[0] * lo.x, q0 = tcl[0] * hi.x, p1 = tcl[1] * lo.y, q1 = tcl[1] * hi.y;
-                    const float p2 = tcl[2] * lo.z, q2 = tcl[2] * hi.z;
-                    const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
-                    const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
-                    const float lim = 0.5f * T * lo.w + 3e-3f;
-                    live = dmin <= lim && dmax >= -lim;
+    // blocks of NTH views (the work range starts on a block), up to NTH of them at a time: their
+    // boxes of normals are tested first, into a bit mask, and the rounds below visit the live
+    // blocks only, PJ_VPT at a time (a block whose box of normals n gives no |n . c| within the
+    // bound below for the tile's centre c holds no view that meets the tile)
+    __shared__ unsigned bmask[NTH / 32];
+    __shared__ int lblk[PJ_VPT + 2];  // a round's live blocks (in the group), their count, the cursor
+    const int blk0 = wk.y / NTH, blk1 = (wk.z + NTH - 1) / NTH;
+    for (int gb = blk0; gb < blk1; gb += NTH) {
+        if (tid < NTH / 32) bmask[tid] = 0u;
+        __syncthreads();
+        if (gb + tid < blk1) {
+            const float4 lo = a.vbox[2 * (gb + tid)], hi = a.vbox[2 * (gb + tid) + 1];
+            const float p0 = tcl[0] * lo.x, q0 = tcl[0] * hi.x, p1 = tcl[1] * lo.y, q1 = tcl[1] * hi.y;
+            const float p2 = tcl[2] * lo.z, q2 = tcl[2] * hi.z;
+            const float dmin = fminf(p0, q0) + fminf(p1, q1) + fminf(p2, q2);
+            const float dmax = fmaxf(p0, q0) + fmaxf(p1, q1) + fmaxf(p2, q2);
+            const float lim = 0.5f * T * lo.w + 3e-3f;
+            if (dmin <= lim && dmax >= -lim) atomicOr(&bmask[tid >> 5], 1u << (tid & 31));
+        }
+        if (tid == 0) lblk[PJ_VPT + 1] = 0;
+        bool more = true;  // uniform
+        while (more) {
+            __syncthreads();  // the counters are reset, the tile and the block mask are in place
+            // 1. views whose plane meets the tile, at least NTH of them (or all that remain),
+            //    PJ_VPT live blocks per round, one view per thread and block, so that the loads
+            //    of a round overlap
+            int ni = 0;
+            while (true) {
+                if (tid == 0) {
+                    int n = 0, cur = lblk[PJ_VPT + 1];
+                    while (n < PJ_VPT && cur < NTH) {
+                        const unsigned w = bmask[cur >> 5] & (~0u << (cur & 31));
+                        if (w == 0u) {
+                            cur = (cur | 31) + 1;
+                            continue;
+                        }
+                        const int b = (cur & ~31) + __builtin_ctz(w);
+                        lblk[n++] = b;
+                        cur = b + 1;
+                    }
+                    lblk[PJ_VPT] = n;
+                    lblk[PJ_VPT + 1] = cur;
                 }
-                live = live && m < wk.z;
-                nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
-                livev |= (unsigned)live << v;
-            }
-#pragma unroll
-            for (int v = 0; v < PJ_VPT; ++v) {
-                const int m = m0 + v * NTH + tid;
-                // the plane meets the tile's cube: distance of the centre at most the cube's
-                // half extent along the normal
-                const float dist = fabsf(tcl[0] * nv[v].x + tcl[1] * nv[v].y + tcl[2] * nv[v].z);
-                if (((livev >> v) & 1u) && dist <= 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f) {
-                    const double* c = a.c12 + 6 * (int64_t)m;
-                    const float u1 = (tcl[0] * (float)c[0] + tcl[1] * (float)c[1] + tcl[2] * (float)c[2]) / (float)a.s;
-                    const int sl = atomicAdd(&nimg, 1);
-                    img_m[sl] = m;
-                    img_r[sl] = (int)ceilf(u1 - rkl) - 1;
+                __syncthreads();
+                const int nl = lblk[PJ_VPT];
+                if (nl == 0) {
+                    more = false;
+                    ni = nimg;
+                    break;
                 }
-            }
-            m0 += PJ_VPT * NTH;
-            __syncthreads();
-            ni = nimg;
-            __syncthreads();  // read by every thread before the next round adds to it
-        } while (ni < NTH && m0 < wk.z);
-        // 2. one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three
-        //    slabs, plus the disk and half-disk bounds), trimmed to the exact cell test at both
-        //    ends (the cell along a row is monotone in k2, so the points that pass form an
-        //    interval).  Queue space is reserved per thread; a reservation that does not fit
-        //    is retried after the full queue has been gathered.
-        const int units = ni * S;
-        for (int base = 0; base < units; base += NTH) {
-            const int u = base + tid;
-            int sl = 0, k1 = 0, klo = 0, cnt = 0;
-            if (u < units) {
-                sl = u / S;
-                k1 = img_r[sl] + (u - sl * S);
-                if (k1 >= 0 && 4 * k1 * k1 <= N2) {
-                    const double* c = a.c12 + 6 * (int64_t)img_m[sl];
-                    const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
-                    float lo = (float)-kd, hi = (float)kd;
-                    bool ok = true;
+                float4 nv[PJ_VPT];
+                unsigned livev = 0u;
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) {
-                        const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
-                        if (fabsf(be) < 1e-6f) {
-                            ok = ok && al >= blo[d] && al <= bhi[d];
-                        } else {
-                            // reciprocal to about 1 ulp: far inside the bounds' margin
-                            const float rb = __builtin_amdgcn_rcpf(be);
-                            const float t1 = (blo[d] - al) * rb, t2 = (bhi[d] - al) * rb;
-                            lo = fmaxf(lo, fminf(t1, t2));
-                            hi = fminf(hi, fmaxf(t1, t2));
+                for (int v = 0; v < PJ_VPT; ++v) {
+                    const int m = v < nl ? (gb + lblk[v]) * NTH + tid : wk.z;
+                    const bool live = m < wk.z;
+                    nv[v] = live ? *reinterpret_cast<const float4*>(a.nrm + 4 * (int64_t)m) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    livev |= (unsigned)live << v;
+                }
+#pragma unroll
+                for (int v = 0; v < PJ_VPT; ++v) {
+                    const int m = v < nl ? (gb + lblk[v]) * NTH + tid : wk.z;
+                    // the plane meets the tile's cube: distance of the centre at most the cube's
+                    // half extent along the normal
+                    const float dist = fabsf(tcl[0] * nv[v].x + tcl[1] * nv[v].y + tcl[2] * nv[v].z);
+                    if (((livev >> v) & 1u) && dist <= 0.5f * T * (fabsf(nv[v].x) + fabsf(nv[v].y) + fabsf(nv[v].z)) + 2e-3f) {
+                        const double* c = a.c12 + 6 * (int64_t)m;
+                        const float u1 = (tcl[0] * (float)c[0] + tcl[1] * (float)c[1] + tcl[2] * (float)c[2]) / (float)a.s;
+                        const int sl = atomicAdd(&nimg, 1);
+                        img_m[sl] = m;
+                        img_r[sl] = (int)ceilf(u1 - rkl) - 1;
+                    }
+                }
+                __syncthreads();
+                ni = nimg;
+                __syncthreads();  // read by every thread before the next round adds to it
+                if (ni >= NTH) break;
+            }
+            // 2. one (view, row k1) per thread: the k2 interval whose cells lie in the tile (three
+            //    slabs, plus the disk and half-disk bounds), trimmed to the exact cell test at both
+            //    ends (the cell along a row is monotone in k2, so the points that pass form an
+            //    interval).  Queue space is reserved per thread; a reservation that does not fit
+            //    is retried after the full queue has been gathered.
+            const int units = ni * S;
+            for (int base = 0; base < units; base += NTH) {
+                const int u = base + tid;
+                int sl = 0, k1 = 0, klo = 0, cnt = 0;
+                if (u < units) {
+                    sl = u / S;
+                    k1 = img_r[sl] + (u - sl * S);
+                    if (k1 >= 0 && 4 * k1 * k1 <= N2) {
+                        const double* c = a.c12 + 6 * (int64_t)img_m[sl];
+                        const int kd = (int)sqrtf((float)(N2 / 4 - k1 * k1)) + 1;  // >= the disk's |k2|
+                        float lo = (float)-kd, hi = (float)kd;
+                        bool ok = true;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const float al = (float)(a.s * k1 * c[d] + halfL), be = (float)(a.s * c[3 + d]);
+                            if (fabsf(be) < 1e-6f) {
+                                ok = ok && al >= blo[d] && al <= bhi[d];
+                            } else {
+                                // reciprocal to about 1 ulp: far inside the bounds' margin
+                                const float rb = __builtin_amdgcn_rcpf(be);
+                                const float t1 = (blo[d] - al) * rb, t2 = (bhi[d] - al) * rb;
+                                lo = fmaxf(lo, fminf(t1, t2));
+                                hi = fminf(hi, fmaxf(t1, t2));
+                            }
+                        }
+                        klo = (int)ceilf(lo);
+                        if (k1 == 0) klo = max(klo, 1);
+                        int khi = (int)floorf(hi);
+                        if (ok) {
+                            while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
+                            while (khi >= klo && !in_tile(c, k1, khi)) --khi;
+                            // a row crosses a tile in at most T sqrt(3) / s + 1 points
+                            cnt = min(khi - klo + 1, 32);
                         }
                     }
-                    klo = (int)ceilf(lo);
-                    if (k1 == 0) klo = max(klo, 1);
-                    int khi = (int)floorf(hi);
-                    if (ok) {
-                        while (klo <= khi && !in_tile(c, k1, klo)) ++klo;
-                        while (khi >= klo && !in_tile(c, k1, khi)) --khi;
-                        // a row crosses a tile in at most T sqrt(3) / s + 1 points
-                        cnt = min(khi - klo + 1, 32);
+                }
+                bool pend = cnt > 0;
+                while (true) {
+                    if (pend) {
+                        const int pos = atomicAdd(&qn, cnt);
+                        if (pos + cnt <= PJ_QCAP) {
+                            for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 17) | (k1 << 9) | (klo + j + 256);
+                            pend = false;
+                        } else {
+                            for (int j = pos; j < PJ_QCAP; ++j) queue[j] = -1;
+                        }
                     }
+                    if (!__syncthreads_or(pend)) break;
+                    flush(PJ_QCAP);  // the queue is full
+                    __syncthreads();
+                    if (tid == 0) qn = 0;
+                    __syncthreads();
                 }
             }
-            bool pend = cnt > 0;
-            while (true) {
-                if (pend) {
-                    const int pos = atomicAdd(&qn, cnt);
-                    if (pos + cnt <= PJ_QCAP) {
-                        for (int j = 0; j < cnt; ++j) queue[pos + j] = (sl << 17) | (k1 << 9) | (klo + j + 256);
-                        pend = false;
-                    } else {
-                        for (int j = pos; j < PJ_QCAP; ++j) queue[j] = -1;
-                    }
-                }
-                if (!__syncthreads_or(pend)) break;
-                flush(PJ_QCAP);  // the queue is full
-                __syncthreads();
-                if (tid == 0) qn = 0;
-                __syncthreads();
-            }
+            // 3. the view slots are refilled next round: gather what is queued
+            const int nq = qn;  // every reservation of the last chunk fitted (read after its barrier)
+            flush(nq);
+            __syncthreads();
+            if (tid == 0) { qn = 0; nimg = 0; }
         }
-        // 3. the view slots are refilled next round: gather what is queued
-        const int nq = qn;  // every reservation of the last chunk fitted (read after its barrier)
-        flush(nq);
-        __syncthreads();
-        if (tid == 0) { qn = 0; nimg = 0; }
     }
 }
 
