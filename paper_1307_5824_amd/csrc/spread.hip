@@ -350,6 +350,10 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
             // lane roles of the uniform read: 8 q + k -> weight k of point q (k < 8); 32 + q -> window
             // word of point q; the other lanes repeat point q's window word
             const int uq = lane < 32 ? (lane >> 3) : (lane - 32) % FQ;
+            // the adds at a raised wavefront priority: where the two workgroups of a CU are in
+            // different phases, the issue of the LDS-bound adds goes first and the staging or
+            // enumeration of the other, bound by load latency, fills the gaps
+            __builtin_amdgcn_s_setprio(2);
             for (int p0 = wvu; p0 < nb; p0 += FQ * SP_WAVES) {
                 int pq[FQ];
 #pragma unroll
@@ -385,6 +389,7 @@ __global__ void __launch_bounds__(NTH, (W >= 8 ? NTH / 256 : NTH / 128)) k_sprea
                     }
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             __syncthreads();
         }
     };
